@@ -1,0 +1,277 @@
+/*
+ * bml_oracle.c -- plain, slow, obviously correct CPU oracle for the
+ * Biham-Middleton-Levine traffic automaton (Model I).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source with the HIP path.
+ *
+ * What it follows (Marzolla, "Parallel Implementations of Cellular Automata
+ * for Traffic Models", arXiv:1804.07981):
+ *   - Sec. 2 (the BML model): an N x N periodic lattice; each cell is EMPTY,
+ *     LR (moves left-to-right) or TB (moves top-to-bottom); horizontal and
+ *     vertical phases alternate; a car leaving one side re-enters on the
+ *     opposite side.
+ *   - Sec. 2, horizontal-phase case table: center' = LR if left = LR and
+ *     center = EMPTY; EMPTY if center = LR and right = EMPTY; else center.
+ *   - Sec. 2, vertical-phase case table: same with top / bottom and TB.
+ *   - Sec. 2, Fig. 1 caption text: one step = a horizontal then a vertical
+ *     phase.
+ *   - Sec. 3 (serial implementation): synchronous update through two grids
+ *     (read cur, write next, swap); row-major IDX(i,j) = i*N + j; one byte
+ *     per cell with EMPTY=0, LR=1, TB=2; neighbours by modulo indexing.
+ *   - Sec. 4 (OpenMP): the row loop is split across threads.
+ * Readings where the paper is silent (initial placement, stats) are the
+ * project's own and are stated at each function.
+ *
+ * Lattices are rows x cols (the paper's case is rows = cols = N); the
+ * oracle accepts any rows, cols >= 1.
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#include <math.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { EMPTY = 0, LR = 1, TB = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* Initial placement.  The paper only says vehicles are placed at random     */
+/* (Sec. 2, text under Fig. 1).  Reading used here: every cell is drawn      */
+/* independently, LR with probability rho/2, TB with probability rho/2,      */
+/* else EMPTY, from SplitMix64 (Steele, Lea & Flood, OOPSLA 2014; Vigna's    */
+/* public-domain reference generator).                                       */
+/* ------------------------------------------------------------------------ */
+
+/* The k-th output (k = 0, 1, ...) of the SplitMix64 stream whose state
+ * starts at `seed`: the state advances by the golden gamma before each
+ * output, and the output is the state passed through the finaliser. */
+uint64_t bmlo_splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Integer thresholds on a 53-bit uniform u = output >> 11: a cell is LR if
+ * u < thr_lr, TB if thr_lr <= u < thr_tb, EMPTY otherwise.  Both are
+ * truncations of rho/2 * 2^53 and rho * 2^53 computed in IEEE double. */
+void bmlo_thresholds(double rho, uint64_t *thr_lr, uint64_t *thr_tb)
+{
+    *thr_lr = (uint64_t)ldexp(rho * 0.5, 53);
+    *thr_tb = (uint64_t)ldexp(rho, 53);
+}
+
+/* Cell k = i*cols + j takes the k-th SplitMix64 output of stream `seed`. */
+void bmlo_init_cells(int64_t rows, int64_t cols, uint64_t seed, double rho,
+                     uint8_t *cells)
+{
+    uint64_t thr_lr, thr_tb;
+    bmlo_thresholds(rho, &thr_lr, &thr_tb);
+    int64_t total = rows * cols;
+    for (int64_t k = 0; k < total; k++) {
+        uint64_t u = bmlo_splitmix64(seed, (uint64_t)k) >> 11;
+        cells[k] = (u < thr_lr) ? LR : (u < thr_tb) ? TB : EMPTY;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The two phases.  Each reads only `cur` and writes only `next`            */
+/* (synchronous update, Sec. 3).  Returns the number of cars that moved,    */
+/* i.e. cars whose destination cell was EMPTY in `cur`.                     */
+/* ------------------------------------------------------------------------ */
+
+static int64_t phase_h_rows(int64_t r0, int64_t r1, int64_t cols,
+                            const uint8_t *cur, uint8_t *next)
+{
+    int64_t moved = 0;
+    for (int64_t i = r0; i < r1; i++) {
+        for (int64_t j = 0; j < cols; j++) {
+            uint8_t left = cur[i * cols + (j - 1 + cols) % cols];
+            uint8_t center = cur[i * cols + j];
+            uint8_t right = cur[i * cols + (j + 1) % cols];
+            uint8_t out;
+            if (left == LR && center == EMPTY) {
+                out = LR;
+            } else if (center == LR && right == EMPTY) {
+                out = EMPTY;
+                moved++;
+            } else {
+                out = center;
+            }
+            next[i * cols + j] = out;
+        }
+    }
+    return moved;
+}
+
+static int64_t phase_v_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
+                            const uint8_t *cur, uint8_t *next)
+{
+    int64_t moved = 0;
+    for (int64_t i = r0; i < r1; i++) {
+        int64_t up = (i - 1 + rows) % rows, down = (i + 1) % rows;
+        for (int64_t j = 0; j < cols; j++) {
+            uint8_t top = cur[up * cols + j];
+            uint8_t center = cur[i * cols + j];
+            uint8_t bottom = cur[down * cols + j];
+            uint8_t out;
+            if (top == TB && center == EMPTY) {
+                out = TB;
+            } else if (center == TB && bottom == EMPTY) {
+                out = EMPTY;
+                moved++;
+            } else {
+                out = center;
+            }
+            next[i * cols + j] = out;
+        }
+    }
+    return moved;
+}
+
+static int64_t count_value(const uint8_t *cells, int64_t n, uint8_t v)
+{
+    int64_t c = 0;
+    for (int64_t k = 0; k < n; k++)
+        c += (cells[k] == v);
+    return c;
+}
+
+/* Serial horizontal phase (the paper's horizontal_step, Sec. 3). */
+int64_t bmlo_phase_h(int64_t rows, int64_t cols, const uint8_t *cur,
+                     uint8_t *next)
+{
+    return phase_h_rows(0, rows, cols, cur, next);
+}
+
+/* Serial vertical phase (Sec. 2 vertical case table; Sec. 3 says it mirrors
+ * the horizontal one). */
+int64_t bmlo_phase_v(int64_t rows, int64_t cols, const uint8_t *cur,
+                     uint8_t *next)
+{
+    return phase_v_rows(0, rows, rows, cols, cur, next);
+}
+
+int64_t bmlo_count(const uint8_t *cells, int64_t n, int32_t value)
+{
+    return count_value(cells, n, (uint8_t)value);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step loop.  One step = horizontal phase (cells -> tmp) then vertical     */
+/* phase (tmp -> cells).  Per step it records four counts (the project's    */
+/* reading of "per-phase car counts and moved counts"):                     */
+/*   stats[4s+0] n_lr     = LR cars in the lattice after the H phase        */
+/*   stats[4s+1] moved_lr = LR cars that moved in the H phase               */
+/*   stats[4s+2] n_tb     = TB cars in the lattice after the V phase        */
+/*   stats[4s+3] moved_tb = TB cars that moved in the V phase               */
+/* `stats` may be NULL.  `tmp` is caller scratch of rows*cols bytes.        */
+/* n_threads > 0 splits the row loop over that many OpenMP threads (Sec. 4);*/
+/* any thread count gives the same bytes and counts.                        */
+/* ------------------------------------------------------------------------ */
+void bmlo_run(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
+              int64_t steps, uint32_t *stats, int32_t n_threads)
+{
+    int nt = n_threads > 0 ? n_threads : 1;
+    for (int64_t s = 0; s < steps; s++) {
+        int64_t moved_lr = 0, moved_tb = 0, n_lr = 0, n_tb = 0;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : moved_lr, n_lr)
+#endif
+        for (int64_t i = 0; i < rows; i++) {
+            moved_lr += phase_h_rows(i, i + 1, cols, cells, tmp);
+            n_lr += count_value(tmp + i * cols, cols, LR);
+        }
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : moved_tb, n_tb)
+#endif
+        for (int64_t i = 0; i < rows; i++) {
+            moved_tb += phase_v_rows(i, i + 1, rows, cols, tmp, cells);
+            n_tb += count_value(cells + i * cols, cols, TB);
+        }
+        if (stats) {
+            stats[4 * s + 0] = (uint32_t)n_lr;
+            stats[4 * s + 1] = (uint32_t)moved_lr;
+            stats[4 * s + 2] = (uint32_t)n_tb;
+            stats[4 * s + 3] = (uint32_t)moved_tb;
+        }
+    }
+    (void)nt; /* unused when built without OpenMP */
+}
+
+/* Many independent square lattices, one lattice per thread at a time
+ * (dynamic schedule): lattice b has sizes[b] x sizes[b] cells starting at
+ * cells + offsets[b]; its per-step counts (4 per step, as in bmlo_run) go to
+ * stats + stats_offsets[b] when stats is not NULL.  Returns 0, or -1 if
+ * scratch could not be allocated. */
+int32_t bmlo_run_many(int64_t count, const int64_t *sizes,
+                      const int64_t *offsets, uint8_t *cells,
+                      const int64_t *stats_offsets, uint32_t *stats,
+                      int64_t steps, int32_t n_threads)
+{
+    int nt = n_threads > 0 ? n_threads : 1;
+    int32_t status = 0;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+#endif
+    for (int64_t b = 0; b < count; b++) {
+        int64_t n = sizes[b];
+        uint8_t *tmp = (uint8_t *)malloc((size_t)(n * n));
+        if (!tmp) {
+            status = -1;
+            continue;
+        }
+        bmlo_run(n, n, cells + offsets[b], tmp, steps,
+                 stats ? stats + stats_offsets[b] : NULL, 1);
+        free(tmp);
+    }
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2-bitplane packed form.  The paper notes that two bits per cell would    */
+/* suffice (Sec. 3).  Layout used by the project: two planes of             */
+/* rows x (cols/32) 32-bit words, row-major; bit b of word w in row i is    */
+/* cell (i, 32w + b), least significant bit = leftmost cell.  Plane `lr`    */
+/* has a 1 where the cell is LR, plane `tb` where it is TB.  cols must be a */
+/* multiple of 32.                                                           */
+/* ------------------------------------------------------------------------ */
+void bmlo_pack(int64_t rows, int64_t cols, const uint8_t *cells,
+               uint32_t *lr, uint32_t *tb)
+{
+    int64_t words = cols / 32;
+    for (int64_t i = 0; i < rows; i++) {
+        for (int64_t w = 0; w < words; w++) {
+            uint32_t a = 0, b = 0;
+            for (int bit = 0; bit < 32; bit++) {
+                uint8_t c = cells[i * cols + 32 * w + bit];
+                if (c == LR)
+                    a |= 1u << bit;
+                if (c == TB)
+                    b |= 1u << bit;
+            }
+            lr[i * words + w] = a;
+            tb[i * words + w] = b;
+        }
+    }
+}
+
+/* Inverse of bmlo_pack.  A position set in both planes is not a valid
+ * state; it is written as 3 so that a caller can detect it. */
+void bmlo_unpack(int64_t rows, int64_t cols, const uint32_t *lr,
+                 const uint32_t *tb, uint8_t *cells)
+{
+    int64_t words = cols / 32;
+    for (int64_t i = 0; i < rows; i++) {
+        for (int64_t j = 0; j < cols; j++) {
+            uint32_t a = (lr[i * words + j / 32] >> (j % 32)) & 1u;
+            uint32_t b = (tb[i * words + j / 32] >> (j % 32)) & 1u;
+            cells[i * cols + j] = (uint8_t)(a * LR + b * TB);
+        }
+    }
+}

@@ -1,0 +1,53 @@
+"""Plants plausible mistakes in a copy of the oracle (on the CPU) and checks
+that the pin tests catch every one of them."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "bml_oracle.c")
+
+MUTATIONS = [
+    ("right neighbour taken on the left", "(j + 1) % cols", "(j + cols - 1) % cols"),
+    ("top and bottom swapped",
+     "int64_t up = (i - 1 + rows) % rows, down = (i + 1) % rows;",
+     "int64_t down = (i - 1 + rows) % rows, up = (i + 1) % rows;"),
+    ("TB enters any non-TB cell", "if (top == TB && center == EMPTY) {",
+     "if (top == TB && center != TB) {"),
+    ("LR leaves into any non-LR cell", "} else if (center == LR && right == EMPTY) {",
+     "} else if (center == LR && right != LR) {"),
+    ("V phase reads the pre-H lattice",
+     "moved_tb += phase_v_rows(i, i + 1, rows, cols, tmp, cells);",
+     "moved_tb += phase_v_rows(i, i + 1, rows, cols, cells, tmp);"),
+    ("moved counts the arrivals twice", "                moved++;\n            } else {\n                out = center;\n            }\n            next[i * cols + j] = out;\n        }\n    }\n    return moved;\n}\n\nstatic int64_t phase_v_rows",
+     "                moved += 2;\n            } else {\n                out = center;\n            }\n            next[i * cols + j] = out;\n        }\n    }\n    return moved;\n}\n\nstatic int64_t phase_v_rows"),
+    ("LR threshold off by a factor of two", "*thr_lr = (uint64_t)ldexp(rho * 0.5, 53);",
+     "*thr_lr = (uint64_t)ldexp(rho * 0.5, 52);"),
+    ("SplitMix64 shift constant", "z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
+     "z = (z ^ (z >> 26)) * 0x94D049BB133111EBull;"),
+    ("SplitMix64 stream offset by one", "uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;",
+     "uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;"),
+    ("bit order reversed in the TB plane", "if (c == TB)\n                    b |= 1u << bit;",
+     "if (c == TB)\n                    b |= 1u << (31 - bit);"),
+    ("stats fields swapped", "stats[4 * s + 1] = (uint32_t)moved_lr;",
+     "stats[4 * s + 1] = (uint32_t)moved_tb;"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,before,after", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, name, before, after):
+    src = open(SRC).read()
+    assert before in src, "mutation site not found"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(before, after, 1))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fopenmp", "-shared", "-fPIC",
+                    "-o", str(so), str(mut), "-lm"], check=True)
+    env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-m", "not slow",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True)
+    assert r.returncode != 0, f"pins did not catch: {name}"

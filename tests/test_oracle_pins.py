@@ -1,0 +1,319 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test pins the oracle to something other than itself: a second
+formulation printed in the paper, a car-centric brute force, a textbook
+special case (elementary CA rule 184), symmetries and invariants of the
+model, closed-form trajectories, and the published SplitMix64 outputs.
+Paper: Marzolla, arXiv:1804.07981 (Sec. 2 model and case tables, Sec. 3
+synchronous update and layout, Sec. 5 select-and-mask formulation).
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import brute
+
+EMPTY, LR, TB = 0, 1, 2
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --- local rule ---------------------------------------------------------
+
+def _select_and_mask(left, center, right, mover):
+    """Sec. 5's branch-free form: masks are 0 or -1, combined bitwise."""
+    m = lambda b: -1 if b else 0
+    mask_in = m(left == mover) & m(center == EMPTY)
+    mask_out = m(center == mover) & m(right == EMPTY)
+    mask_keep = ~(mask_in | mask_out)
+    return (mask_in & mover) | (mask_out & EMPTY) | (mask_keep & center)
+
+
+@pytest.mark.parametrize("l,c,r", list(itertools.product((0, 1, 2), repeat=3)))
+def test_h_rule_matches_select_and_mask(l, c, r):
+    row = np.array([[l, c, r]], dtype=np.uint8)  # periodic 1x3: c sees l, r
+    out, _ = oracle.phase_h(row)
+    assert out[0, 1] == _select_and_mask(l, c, r, LR)
+
+
+@pytest.mark.parametrize("t,c,b", list(itertools.product((0, 1, 2), repeat=3)))
+def test_v_rule_matches_select_and_mask(t, c, b):
+    col = np.array([[t], [c], [b]], dtype=np.uint8)
+    out, _ = oracle.phase_v(col)
+    assert out[1, 0] == _select_and_mask(t, c, b, TB)
+
+
+# --- brute force on tiny lattices ----------------------------------------
+
+def _check_against_brute(grid, steps):
+    g = np.array(grid, dtype=np.uint8)
+    bg, bstats = brute.run(grid, steps)
+    og, ostats = oracle.run(g, steps)
+    assert np.array_equal(og, np.array(bg, dtype=np.uint8))
+    assert [tuple(int(x) for x in s) for s in ostats] == bstats
+
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_brute_force_random(n):
+    rng = np.random.default_rng(1000 + n)
+    for trial in range(40):
+        p = rng.random()
+        q = rng.random() * (1 - p)
+        g = workloads.random_lattice(rng, n, n, p, q)
+        _check_against_brute(g.tolist(), 6)
+
+
+@pytest.mark.parametrize("rows,cols", [(2, 3), (3, 2), (1, 5), (5, 1), (4, 7), (7, 3)])
+def test_brute_force_rectangular(rows, cols):
+    rng = np.random.default_rng(rows * 31 + cols)
+    for _ in range(30):
+        g = workloads.random_lattice(rng, rows, cols, 0.35, 0.35)
+        _check_against_brute(g.tolist(), 5)
+
+
+def test_brute_force_exhaustive_2x2_and_3x3_one_step():
+    for n in (2,):
+        for cells in itertools.product((0, 1, 2), repeat=n * n):
+            _check_against_brute(np.array(cells).reshape(n, n).tolist(), 2)
+    rng = np.random.default_rng(7)
+    all3 = list(itertools.product((0, 1, 2), repeat=9))
+    for idx in rng.choice(len(all3), 1500, replace=False):
+        _check_against_brute(np.array(all3[idx]).reshape(3, 3).tolist(), 1)
+
+
+def test_brute_force_8x8_init_lattices():
+    for seed in range(20):
+        for rho in (0.0, 0.2, 0.3, 0.5, 0.8, 1.0):
+            g = oracle.init_cells(8, seed, rho)
+            _check_against_brute(g.tolist(), 12)
+
+
+# --- elementary CA rule 184 ---------------------------------------------
+
+def _rule184(ring):
+    n = len(ring)
+    return [(184 >> (4 * ring[(j - 1) % n] + 2 * ring[j] + ring[(j + 1) % n])) & 1
+            for j in range(n)]
+
+
+def test_lr_only_rows_follow_rule_184():
+    """An LR-only row under the H phase is Wolfram's elementary rule 184."""
+    rng = np.random.default_rng(184)
+    for _ in range(200):
+        n = int(rng.integers(1, 40))
+        ring = (rng.random(n) < rng.random()).astype(int).tolist()
+        out, moved = oracle.phase_h(np.array([ring], dtype=np.uint8) * LR)
+        assert (out[0] // LR).tolist() == _rule184(ring)
+
+
+def test_rule_184_stationary_flux():
+    """Rule 184 on a ring of n cells with k cars reaches a state where
+    exactly min(k, n-k) cars move every step (traffic flow of rule 184)."""
+    rng = np.random.default_rng(1840)
+    for _ in range(100):
+        n = int(rng.integers(2, 48))
+        k = int(rng.integers(0, n + 1))
+        row = np.zeros((1, n), dtype=np.uint8)
+        row[0, rng.choice(n, k, replace=False)] = LR
+        _, stats = oracle.run(row, 2 * n + 4)
+        assert all(int(m) == min(k, n - k) for m in stats[n:, 1])
+
+
+# --- symmetries and invariants -------------------------------------------
+
+def _tau(g):
+    """Transpose and swap LR <-> TB."""
+    t = g.T.copy()
+    out = t.copy()
+    out[t == LR] = TB
+    out[t == TB] = LR
+    return out
+
+
+def test_vertical_is_transposed_horizontal():
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        r, c = (int(x) for x in rng.integers(1, 12, size=2))
+        g = workloads.random_lattice(rng, r, c, rng.random() * 0.5, rng.random() * 0.5)
+        v, mv = oracle.phase_v(g)
+        h, mh = oracle.phase_h(_tau(g))
+        assert np.array_equal(v, _tau(h)) and mv == mh
+
+
+def test_translation_equivariance():
+    rng = np.random.default_rng(12)
+    for _ in range(60):
+        n = int(rng.integers(2, 24))
+        g = workloads.random_lattice(rng, n, n + int(rng.integers(0, 5)), 0.2, 0.2)
+        a, b = (int(x) for x in rng.integers(0, 30, size=2))
+        s1, st1 = oracle.run(np.roll(g, (a, b), axis=(0, 1)), 7)
+        s2, st2 = oracle.run(g, 7)
+        assert np.array_equal(s1, np.roll(s2, (a, b), axis=(0, 1)))
+        assert np.array_equal(st1, st2)
+
+
+def test_conservation_per_row_and_column():
+    rng = np.random.default_rng(13)
+    for n in (5, 16, 33, 64):
+        g = workloads.random_lattice(rng, n, n, 0.2, 0.2)
+        out, stats = oracle.run(g, 50)
+        assert np.array_equal((out == LR).sum(axis=1), (g == LR).sum(axis=1))
+        assert np.array_equal((out == TB).sum(axis=0), (g == TB).sum(axis=0))
+        assert (stats[:, 0] == (g == LR).sum()).all()
+        assert (stats[:, 2] == (g == TB).sum()).all()
+
+
+@pytest.mark.parametrize("kind", [LR, TB])
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 17, 32])
+def test_lone_car_returns_after_n_steps(kind, n):
+    g = workloads.lone_car(n, kind, n // 2, n // 3)
+    out, stats = oracle.run(g, n)
+    assert np.array_equal(out, g)
+    moving = 1 if n > 1 else 0
+    want = (1, moving, 0, 0) if kind == LR else (0, 0, 1, moving)
+    assert all(tuple(int(x) for x in s) == want for s in stats)
+    if n > 2:
+        mid, _ = oracle.run(g, 1)
+        i, j = n // 2, n // 3
+        expect = (i, (j + 1) % n) if kind == LR else ((i + 1) % n, j)
+        assert mid[expect] == kind and mid.sum() == kind
+
+
+@pytest.mark.parametrize("lattice", ["checkerboard", "rows", "rho1"])
+def test_full_lattice_is_fixed_point(lattice):
+    n = 12
+    g = {"checkerboard": workloads.full_checkerboard(n),
+         "rows": workloads.full_rows(n),
+         "rho1": oracle.init_cells(n, 3, 1.0)}[lattice]
+    assert (g != EMPTY).all()
+    out, stats = oracle.run(g, 20)
+    assert np.array_equal(out, g)
+    assert (stats[:, 1] == 0).all() and (stats[:, 3] == 0).all()
+
+
+def test_zero_moves_means_fixed_point_forever():
+    """If a step moves nothing, the next state equals the current one, so the
+    lattice is frozen for good; checked on lattices that jam."""
+    for seed in range(6):
+        g = oracle.init_cells(32, seed, 0.7)
+        out, stats = oracle.run(g, 400)
+        zero = np.nonzero((stats[:, 1] == 0) & (stats[:, 3] == 0))[0]
+        if len(zero) == 0:
+            continue
+        t = int(zero[0])
+        assert (stats[t:, 1] == 0).all() and (stats[t:, 3] == 0).all()
+        at_t, _ = oracle.run(g, t + 1)
+        assert np.array_equal(at_t, out)
+
+
+def test_car_train_only_front_moves():
+    row = np.array([[LR, LR, LR, EMPTY, EMPTY, EMPTY]], dtype=np.uint8)
+    out, moved = oracle.phase_h(row)
+    assert out.tolist() == [[LR, LR, EMPTY, LR, EMPTY, EMPTY]] and moved == 1
+    col = row.T.copy() * 2
+    out, moved = oracle.phase_v(col)
+    assert out.T.tolist() == [[TB, TB, EMPTY, TB, EMPTY, EMPTY]] and moved == 1
+
+
+def test_h_then_v_order():
+    # LR at (0,0) wants (0,1); TB at (1,1)... a TB above (0,1) at (n-1,1)
+    # wants (0,1) too.  H goes first, so the LR car takes the cell.
+    n = 4
+    g = np.zeros((n, n), dtype=np.uint8)
+    g[0, 0] = LR
+    g[n - 1, 1] = TB
+    out, stats = oracle.run(g, 1)
+    assert out[0, 1] == LR and out[n - 1, 1] == TB
+    assert tuple(int(x) for x in stats[0]) == (1, 1, 1, 0)
+
+
+def test_thread_count_does_not_change_result():
+    g = oracle.init_cells(96, 5, 0.33)
+    a, sa = oracle.run(g, 40, n_threads=1)
+    for t in (2, 3, 8):
+        b, sb = oracle.run(g, 40, n_threads=t)
+        assert np.array_equal(a, b) and np.array_equal(sa, sb)
+
+
+def test_run_many_matches_run():
+    lats = [oracle.init_cells(n, n, 0.3) for n in (8, 32, 20)]
+    outs, stats = oracle.run_many(lats, 30, n_threads=3)
+    for g, o, s in zip(lats, outs, stats):
+        a, sa = oracle.run(g, 30)
+        assert np.array_equal(a, o) and np.array_equal(sa, s)
+
+
+def test_checkpoint_resume():
+    g = oracle.init_cells(40, 9, 0.35)
+    full, sf = oracle.run(g, 70)
+    mid, s1 = oracle.run(g, 30)
+    end, s2 = oracle.run(mid, 40)
+    assert np.array_equal(full, end)
+    assert np.array_equal(sf, np.concatenate([s1, s2]))
+
+
+# --- initial placement ---------------------------------------------------
+
+def test_splitmix64_published_outputs():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_state0.txt"))
+            if l.strip() and not l.startswith("#")]
+    for k, hexval in rows:
+        assert oracle.splitmix64(0, int(k)) == int(hexval, 16)
+
+
+def test_init_cell_k_uses_kth_output():
+    rho = 0.4
+    thr_lr, thr_tb = oracle.thresholds(rho)
+    assert thr_lr == int(rho / 2 * 2**53) and thr_tb == int(rho * 2**53)
+    g = oracle.init_cells(8, 12345, rho, cols=16)
+    for k in range(g.size):
+        u = oracle.splitmix64(12345, k) >> 11
+        want = LR if u < thr_lr else (TB if u < thr_tb else EMPTY)
+        assert g.ravel()[k] == want
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.1, 0.3, 0.55, 1.0])
+def test_init_fractions(rho):
+    g = oracle.init_cells(256, 99, rho)
+    n = g.size
+    for kind in (LR, TB):
+        p = rho / 2
+        frac = (g == kind).sum() / n
+        sigma = np.sqrt(max(p * (1 - p), 1e-12) / n)
+        assert abs(frac - p) <= 5 * sigma + 1e-12
+
+
+# --- bitplane definition ---------------------------------------------------
+
+def test_pack_layout_and_roundtrip():
+    g = np.zeros((2, 64), dtype=np.uint8)
+    g[0, 0] = LR      # word 0 bit 0 (leftmost cell = least significant bit)
+    g[0, 33] = TB     # word 1 bit 1
+    g[1, 31] = LR     # row 1 word 0 bit 31
+    lr, tb = oracle.pack(g)
+    assert lr.tolist() == [[1, 0], [1 << 31, 0]]
+    assert tb.tolist() == [[0, 2], [0, 0]]
+    rng = np.random.default_rng(3)
+    r = workloads.random_lattice(rng, 17, 96, 0.3, 0.3)
+    assert np.array_equal(oracle.unpack(*oracle.pack(r)), r)
+
+
+# --- physics sanity (qualitative) -----------------------------------------
+
+@pytest.mark.slow
+def test_fig1_free_flow_and_jam():
+    """Fig. 1: at 256 x 256 after 4096 steps, rho = 0.25 flows freely and
+    rho = 0.38 is jammed (most seeds; both phases can coexist near the
+    critical density, so a majority of three seeds is asked for)."""
+    def mean_v(rho, seed):
+        g = oracle.init_cells(256, seed, rho)
+        _, st = oracle.run(g, 4096, n_threads=os.cpu_count() or 1)
+        cars = st[-100:, 0].astype(float) + st[-100:, 2]
+        return float(((st[-100:, 1] + st[-100:, 3]) / cars).mean())
+    free = [mean_v(0.25, s) for s in range(3)]
+    jam = [mean_v(0.38, s) for s in range(3)]
+    assert sum(v > 0.9 for v in free) >= 2
+    assert sum(v < 0.05 for v in jam) >= 2
