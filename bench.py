@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X BML step library (one GPU).
+
+Default workload: four 4096 x 4096 lattices (rho 0.25 / 0.35 / 0.38 / 0.45,
+seeds 1-4), 10000 steps each, uint8 cells.  One benchmark step is that whole
+job: every lattice advanced 10000 steps with every per-step count recorded.
+The initial lattices are resident in HBM before the timed region starts.
+
+Prints one JSON line: GCUPS (cell updates per second, one update = one cell
+advanced one full step, horizontal + vertical phase), the roofline of the
+step kernel, the CPU oracle timed on the host cores, and per-layout /
+per-density figures.  `--workload large` times the 32768 x 32768 lattice
+(rho 0.30, seed 7, 1000 steps) instead.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_1804_07981_amd/csrc/bml_pass.hpp",
+                  "paper_1804_07981_amd/csrc/bml_tile.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_cell_step(layout: int, k: int) -> float:
+    """Algorithmic HBM bytes per cell-step of one pass of k steps: the state
+    is read once and written once per pass (1 byte per cell for uint8, 2 bits
+    for bitplanes), shared by the k steps of the pass."""
+    per_cell_pass = 2.0 if layout == 0 else 0.5
+    return per_cell_pass / k
+
+
+def load_tuning(workload: str, layout: int, n: int):
+    path = os.path.join(ROOT, "paper_1804_07981_amd", "tune_cache.json")
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+            key = f"gfx950/{'u8' if layout == 0 else 'bp'}/{n}"
+            if key in cache:
+                t = cache[key]
+                return int(t["tile_rows"]), int(t["t_phases"]), int(t["waves_per_block"])
+        except (OSError, ValueError, KeyError):
+            pass
+    return None
+
+
+def traffic_from_profile(name: str, launches_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"{name}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n: int, rho: float, seed: int, target_s: float = 15.0):
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    g = oracle.init_cells(n, seed, rho)
+    t0 = time.perf_counter()
+    g, _ = oracle.run(g, 2, n_threads=threads)
+    cal = (time.perf_counter() - t0) / 2
+    steps = max(2, min(int(target_s / max(cal, 1e-6)), 2000))
+    t0 = time.perf_counter()
+    oracle.run(g, steps, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt / 1e9, "unit": "GCUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n}x{n} rho={rho} seed={seed}, {steps} steps, {threads} threads, "
+                      f"{dt:.1f} s (plain C oracle, -O3, OpenMP row split)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["medium", "large"], default="medium")
+    ap.add_argument("--layout", choices=["u8", "bitplane"], default="u8")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the per-layout secondary measurements")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "row-slab decomposition is a design, not built.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1804_07981_amd as B
+    import workloads
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    wl = workloads.MEDIUM if args.workload == "medium" else workloads.LARGE
+    layout = 0 if args.layout == "u8" else 1
+
+    def make_lattices(lay):
+        lats = []
+        for lt in wl.lattices:
+            lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps, device=dev)
+            tun = load_tuning(wl.name, lay, lt.n)
+            if tun:
+                lat.set_tuning(*tun)
+            lats.append(lat)
+        return lats
+
+    def run_job(lats):
+        for lat in lats:
+            lat.step(wl.steps)
+
+    def time_layout(lay, steps, warmup):
+        lats = make_lattices(lay)
+        for _ in range(warmup):
+            run_job(lats)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(dev)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(steps):
+            run_job(lats)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_s = ev0.elapsed_time(ev1) / 1e3
+        # Every recorded count must still show the initial car numbers.
+        for lat in lats:
+            lat.stats(lat.steps_done - wl.steps, wl.steps)
+        tr, tp, wpb = lats[0].tuning()
+        k = tp // 2
+        launches = sum(-(-wl.steps // k) for _ in lats) * steps
+        cells = sum(lt.n * lt.n for lt in wl.lattices)
+        for lat in lats:
+            lat.close()
+        return {"gpu_s": gpu_s, "wall_s": wall, "k": k, "tile_rows": tr, "wpb": wpb,
+                "launches": launches, "cells": cells,
+                "gcups": cells * wl.steps * steps / gpu_s / 1e9}
+
+    res = time_layout(layout, args.steps, args.warmup)
+    total_cell_steps = res["cells"] * wl.steps * args.steps
+    value = total_cell_steps / res["gpu_s"] / 1e9
+    ms_per_step = res["gpu_s"] * 1e3 / args.steps
+
+    k = res["k"]
+    per_launch_s = res["gpu_s"] / res["launches"]
+    per_lattice_cells = res["cells"] / len(wl.lattices)
+    alg_bytes = bytes_per_cell_step(layout, k) * per_lattice_cells * k
+    achieved = alg_bytes / per_launch_s / 1e9
+    kname = f"pass_{args.layout}_{wl.lattices[0].n}"
+    traffic = traffic_from_profile(kname, alg_bytes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernel": f"pass_kernel<{args.layout}, K={k}, VR={res['tile_rows']}>",
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "avg_launch_us": round(per_launch_s * 1e6, 2)}
+
+    out = {
+        "metric": "GCUPS (cell updates/s) + % HBM roofline",
+        "value": round(value, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.layout,
+        "data": "synthetic (SplitMix64 iid lattices, seeded)",
+        "config": {"workload": wl.name, "layout": args.layout,
+                   "lattices": [[lt.n, lt.rho, lt.seed] for lt in wl.lattices],
+                   "steps_per_lattice": wl.steps,
+                   "tuning": {"tile_rows": res["tile_rows"], "t_phases": 2 * k,
+                              "waves_per_block": res["wpb"]},
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+    }
+
+    if not args.no_variants:
+        other = 1 - layout
+        r2 = time_layout(other, 1, 1)
+        out["variants"] = {("bitplane" if other else "u8"): {
+            "gcups": round(r2["gcups"], 2), "t_phases": 2 * r2["k"],
+            "tile_rows": r2["tile_rows"]}}
+
+    if not args.no_cpu_baseline:
+        lt = wl.lattices[0]
+        out["cpu_baseline"] = cpu_baseline(min(lt.n, 4096), lt.rho, lt.seed)
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

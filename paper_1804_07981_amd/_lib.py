@@ -1,0 +1,195 @@
+"""ctypes declarations of the C ABI in include/bml.h (same names).
+
+torch is imported before libbml.so is opened so that the library binds to
+the HIP runtime torch already loaded (one runtime per process).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the process's HIP runtime first)
+
+BML_OK = 0
+BML_EINVAL = -1
+BML_EDEVICE = -2
+BML_ERANGE = -3
+BML_ESTATE = -4
+BML_ECORRUPT = -5
+BML_EBADARG = BML_EINVAL
+BML_LAYOUT_U8 = 0
+BML_LAYOUT_BITPLANE = 1
+
+# bml_step_stats as a numpy record: n_lr, moved_lr, n_tb, moved_tb.
+STEP_STATS_DTYPE = np.dtype([("n_lr", "<u4"), ("moved_lr", "<u4"),
+                             ("n_tb", "<u4"), ("moved_tb", "<u4")])
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libbml.so")
+
+
+class BmlError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"libbml error {code}: {message}")
+        self.code = code
+        self.message = message
+
+
+_lib = None
+
+_i32, _i64, _u64, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+_vp, _sz = ctypes.c_void_p, ctypes.c_size_t
+
+_SIGNATURES = {
+    "bml_state_bytes": ([_i32, _i32, ctypes.POINTER(_sz)], ctypes.c_int),
+    "bml_init": ([ctypes.POINTER(_vp), _i32, _i32, _u64, _dbl, _vp, _vp, _vp, _vp,
+                  _i64, _vp], ctypes.c_int),
+    "bml_step": ([_vp, _i64], ctypes.c_int),
+    "bml_stats": ([_vp, _i64, _i64, _vp], ctypes.c_int),
+    "bml_get_cells": ([_vp, _vp], ctypes.c_int),
+    "bml_initial_counts": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
+    "bml_set_tuning": ([_vp, _i32, _i32, _i32], ctypes.c_int),
+    "bml_get_tuning": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                        ctypes.POINTER(_i32)], ctypes.c_int),
+    "bml_step_count": ([_vp], _i64),
+    "bml_current_state": ([_vp], _vp),
+    "bml_free": ([_vp], None),
+    "bml_last_error": ([], ctypes.c_char_p),
+    "bml_pack": ([_i32, _vp, _vp, _vp], ctypes.c_int),
+    "bml_unpack": ([_i32, _vp, _vp, _vp], ctypes.c_int),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libbml.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise BmlError(BML_EDEVICE, f"{path} is missing: run "
+                           "`python -m paper_1804_07981_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(path)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return sorted(_SIGNATURES)
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise BmlError(rc, bml_last_error())
+    return rc
+
+
+def _ptr(x) -> int | None:
+    """Device or host address of a torch tensor / numpy array / int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def bml_last_error() -> str:
+    msg = lib().bml_last_error()
+    return msg.decode() if msg else ""
+
+
+def bml_state_bytes(n: int, layout: int) -> int:
+    out = _sz()
+    _check(lib().bml_state_bytes(n, layout, ctypes.byref(out)))
+    return int(out.value)
+
+
+def bml_init(n: int, layout: int, seed: int, rho: float, cells_host, d_state_a,
+             d_state_b, d_stats, stats_cap: int, stream) -> int:
+    """Returns the opaque handle (an int)."""
+    h = _vp()
+    cells = None
+    if cells_host is not None:
+        cells = np.ascontiguousarray(cells_host, dtype=np.uint8)
+        if cells.size != n * n:
+            raise BmlError(BML_EINVAL, f"cells_host must hold {n}*{n} bytes")
+    _check(lib().bml_init(ctypes.byref(h), n, layout, seed & (2**64 - 1), float(rho),
+                          _ptr(cells), _ptr(d_state_a), _ptr(d_state_b), _ptr(d_stats),
+                          stats_cap, _stream_ptr(stream)))
+    return int(h.value)
+
+
+def bml_step(handle: int, n_steps: int) -> None:
+    _check(lib().bml_step(handle, n_steps))
+
+
+def bml_stats(handle: int, first_step: int, count: int, check: bool = True) -> np.ndarray:
+    """Counts of steps first_step .. first_step+count-1 as a STEP_STATS_DTYPE
+    array.  With check=False a BML_ECORRUPT result is returned, not raised."""
+    out = np.zeros(count, dtype=STEP_STATS_DTYPE)
+    rc = lib().bml_stats(handle, first_step, count, out.ctypes.data)
+    if rc < 0 and (check or rc != BML_ECORRUPT):
+        raise BmlError(rc, bml_last_error())
+    return out
+
+
+def bml_get_cells(handle: int, n: int) -> np.ndarray:
+    out = np.empty((n, n), dtype=np.uint8)
+    _check(lib().bml_get_cells(handle, out.ctypes.data))
+    return out
+
+
+def bml_initial_counts(handle: int) -> tuple[int, int]:
+    a, b = _u64(), _u64()
+    _check(lib().bml_initial_counts(handle, ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def bml_set_tuning(handle: int, tile_rows: int = 0, t_phases: int = 0,
+                   waves_per_block: int = 0) -> None:
+    _check(lib().bml_set_tuning(handle, tile_rows, t_phases, waves_per_block))
+
+
+def bml_get_tuning(handle: int) -> tuple[int, int, int]:
+    a, b, c = _i32(), _i32(), _i32()
+    _check(lib().bml_get_tuning(handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return int(a.value), int(b.value), int(c.value)
+
+
+def bml_step_count(handle: int) -> int:
+    return int(lib().bml_step_count(handle))
+
+
+def bml_current_state(handle: int) -> int:
+    return int(lib().bml_current_state(handle) or 0)
+
+
+def bml_free(handle: int) -> None:
+    lib().bml_free(handle)
+
+
+def bml_pack(n: int, d_cells, d_planes, stream=None) -> None:
+    _check(lib().bml_pack(n, _ptr(d_cells), _ptr(d_planes), _stream_ptr(stream)))
+
+
+def bml_unpack(n: int, d_planes, d_cells, stream=None) -> None:
+    _check(lib().bml_unpack(n, _ptr(d_planes), _ptr(d_cells), _stream_ptr(stream)))

@@ -1,0 +1,693 @@
+// bml_lattice.hip -- single-lattice BML step on gfx950: initial placement,
+// byte/bitplane conversion, car counting and the temporally blocked step
+// kernels, plus the host side of the single-lattice C ABI (include/bml.h).
+//
+// Model: Marzolla, arXiv:1804.07981, Sec. 2 (periodic N x N lattice, H phase
+// then V phase, case tables) and Sec. 3 (synchronous update through two
+// grids, row-major layout, one byte per cell; two bits would suffice).
+//
+// The step kernel itself (temporal blocking over register tiles) is in
+// bml_pass.hpp, instantiated in bml_pass_*.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "bml.h"
+#include "bml_common.hpp"
+#include "bml_pass.hpp"
+#include "bml_tile.hpp"
+
+namespace bml {
+
+// ============================================================================
+// Errors and device properties
+// ============================================================================
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int device_info(DeviceInfo *out)
+{
+    static std::mutex mu;
+    static std::vector<DeviceInfo> cache;
+    int dev = 0;
+    BML_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev)
+        cache.resize(dev + 1);
+    if (cache[dev].device < 0) {
+        hipDeviceProp_t p;
+        BML_HIP(hipGetDeviceProperties(&p, dev));
+        cache[dev].device = dev;
+        cache[dev].cu_count = p.multiProcessorCount;
+    }
+    *out = cache[dev];
+    return BML_OK;
+}
+
+// ============================================================================
+// Kernels
+// ============================================================================
+
+// SplitMix64 (Steele, Lea & Flood 2014): k-th output of the stream whose
+// state starts at `seed`.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// One thread per 32-cell word: cells k0 .. k0+31 of row-major index.
+template <int IO>
+__global__ __launch_bounds__(256) void init_kernel(void *out, int32_t n, int32_t words,
+                                                   uint64_t seed, uint64_t thr_lr,
+                                                   uint64_t thr_tb)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)n * words;
+    if (idx >= total)
+        return;
+    const uint64_t k0 = (uint64_t)idx * 32u;   // row*n + 32*w == 32*(row*words + w)
+    uint32_t lr = 0, tb = 0;
+#pragma unroll 4
+    for (int j = 0; j < 32; ++j) {
+        const uint64_t u = splitmix64_at(seed, k0 + j) >> 11;
+        lr |= (uint32_t)(u < thr_lr) << j;
+        tb |= (uint32_t)(u >= thr_lr && u < thr_tb) << j;
+    }
+    if (IO == IO_U8) {
+        uint32_t d[8];
+        planes_to_bytes(lr, tb, d);
+        uint4 *p = (uint4 *)((uint8_t *)out + k0);
+        p[0] = make_uint4(d[0], d[1], d[2], d[3]);
+        p[1] = make_uint4(d[4], d[5], d[6], d[7]);
+    } else {
+        uint32_t *pl = (uint32_t *)out;
+        pl[idx] = lr;
+        pl[total + idx] = tb;
+    }
+}
+
+// Byte cells -> bitplanes, one thread per word.
+__global__ __launch_bounds__(256) void pack_kernel(const uint8_t *cells, uint32_t *planes,
+                                                   int64_t total_words)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total_words)
+        return;
+    const uint4 *p = (const uint4 *)(cells + idx * 32);
+    const uint4 u0 = p[0], u1 = p[1];
+    const uint32_t d[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+    uint32_t lr, tb;
+    bytes_to_planes(d, lr, tb);
+    planes[idx] = lr;
+    planes[total_words + idx] = tb;
+}
+
+// Bitplanes -> byte cells, one thread per word.
+__global__ __launch_bounds__(256) void unpack_kernel(const uint32_t *planes, uint8_t *cells,
+                                                     int64_t total_words)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total_words)
+        return;
+    uint32_t d[8];
+    planes_to_bytes(planes[idx], planes[total_words + idx], d);
+    uint4 *p = (uint4 *)(cells + idx * 32);
+    p[0] = make_uint4(d[0], d[1], d[2], d[3]);
+    p[1] = make_uint4(d[4], d[5], d[6], d[7]);
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += (uint32_t)__shfl_xor((int)v, off, 64);
+    return v;
+}
+
+// Counts LR and TB cells; out[0] += LR, out[1] += TB.  One thread per word.
+template <int IO>
+__global__ __launch_bounds__(256) void count_kernel(const void *state, int64_t total_words,
+                                                    unsigned long long *out)
+{
+    __shared__ uint32_t s[2];
+    if (threadIdx.x < 2)
+        s[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t lr = 0, tb = 0;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total_words;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        if (IO == IO_U8) {
+            const uint4 *p = (const uint4 *)((const uint8_t *)state + idx * 32);
+            const uint4 u0 = p[0], u1 = p[1];
+            const uint32_t d[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                lr += __builtin_popcount(d[q] & 0x01010101u);
+                tb += __builtin_popcount(d[q] & 0x02020202u);
+            }
+        } else {
+            const uint32_t *pl = (const uint32_t *)state;
+            lr += __builtin_popcount(pl[idx]);
+            tb += __builtin_popcount(pl[total_words + idx]);
+        }
+    }
+    lr = wave_sum(lr);
+    tb = wave_sum(tb);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&s[0], lr);
+        atomicAdd(&s[1], tb);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        atomicAdd(&out[threadIdx.x], (unsigned long long)s[threadIdx.x]);
+}
+
+__global__ void zero_words_kernel(uint32_t *p, int count)
+{
+    for (int i = threadIdx.x; i < count; i += blockDim.x)
+        p[i] = 0;
+}
+
+// ============================================================================
+// Kernel table
+// ============================================================================
+
+constexpr int N_ROWS_OPT = 2;
+constexpr int ROWS_OPT[N_ROWS_OPT] = {32, 64};   // output rows per wavefront tile
+
+struct KernelTable {
+    PassFn fn[2][N_ROWS_OPT][MAX_K + 1] = {};
+    KernelTable()
+    {
+        pass_table_u8_r32(fn[IO_U8][0]);
+        pass_table_u8_r64(fn[IO_U8][1]);
+        pass_table_bp_r32(fn[IO_BP][0]);
+        pass_table_bp_r64(fn[IO_BP][1]);
+    }
+};
+
+static const KernelTable &kernels()
+{
+    static KernelTable t;
+    return t;
+}
+
+static int rows_index(int VR)
+{
+    for (int i = 0; i < N_ROWS_OPT; ++i)
+        if (ROWS_OPT[i] == VR)
+            return i;
+    return -1;
+}
+
+// Resident blocks per CU of a pass kernel at `threads` threads per block.
+static int resident_blocks(int io, int ri, int k, int threads, int *out)
+{
+    static std::mutex mu;
+    static int cache[8][2][N_ROWS_OPT][MAX_K + 1][3];   // [dev][io][ri][k][log2 wpb]
+    int dev = 0;
+    BML_HIP(hipGetDevice(&dev));
+    int wl = threads == 64 ? 0 : threads == 128 ? 1 : 2;
+    std::lock_guard<std::mutex> lock(mu);
+    int *c = dev < 8 ? &cache[dev][io][ri][k][wl] : nullptr;
+    if (c && *c > 0) {
+        *out = *c;
+        return BML_OK;
+    }
+    int nb = 0;
+    BML_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, reinterpret_cast<const void *>(kernels().fn[io][ri][k]), threads, 0));
+    if (nb < 1)
+        nb = 1;
+    if (c)
+        *c = nb;
+    *out = nb;
+    return BML_OK;
+}
+
+static int launch_1d_grid(int64_t work, int threads, unsigned *grid)
+{
+    const int64_t g = (work + threads - 1) / threads;
+    if (g > 0x7fffffff)
+        return fail(BML_EINVAL, "launch too large");
+    *grid = (unsigned)std::max<int64_t>(g, 1);
+    return BML_OK;
+}
+
+} // namespace bml
+
+// ============================================================================
+// Handle and C ABI
+// ============================================================================
+
+using namespace bml;
+
+struct bml_lattice {
+    int32_t n = 0, layout = 0;
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint32_t *stats = nullptr;
+    int64_t cap = 0;
+    hipStream_t stream = nullptr;
+    int64_t steps_done = 0;
+    uint64_t n_lr0 = 0, n_tb0 = 0;
+    int32_t tile_rows = 64, t_phases = 8, wpb = 4;   // tile_rows: output rows per tile
+    DeviceInfo dev;
+    unsigned long long *d_counts = nullptr;   // library scratch: 2 counters
+    PassScratch *d_scratch = nullptr;         // library scratch: stats reduction
+};
+
+static std::mutex g_handles_mu;
+static std::unordered_set<const bml_lattice *> g_handles;
+
+static bool live(const bml_lattice *L)
+{
+    if (!L)
+        return false;
+    std::lock_guard<std::mutex> lock(g_handles_mu);
+    return g_handles.count(L) != 0;
+}
+
+static int count_cars(bml_lattice *L, const void *state, uint64_t *n_lr, uint64_t *n_tb)
+{
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, L->stream,
+                       (uint32_t *)L->d_counts, 4);
+    const int64_t total_words = (int64_t)L->n * (L->n / 32);
+    const unsigned grid = (unsigned)std::min<int64_t>((total_words + 255) / 256,
+                                                      (int64_t)L->dev.cu_count * 8);
+    if (L->layout == BML_LAYOUT_U8)
+        hipLaunchKernelGGL(count_kernel<IO_U8>, dim3(grid), dim3(256), 0, L->stream, state,
+                           total_words, L->d_counts);
+    else
+        hipLaunchKernelGGL(count_kernel<IO_BP>, dim3(grid), dim3(256), 0, L->stream, state,
+                           total_words, L->d_counts);
+    BML_HIP(hipGetLastError());
+    unsigned long long h[2] = {0, 0};
+    BML_HIP(hipMemcpyAsync(h, L->d_counts, sizeof h, hipMemcpyDeviceToHost, L->stream));
+    BML_HIP(hipStreamSynchronize(L->stream));
+    *n_lr = h[0];
+    *n_tb = h[1];
+    return BML_OK;
+}
+
+extern "C" {
+
+const char *bml_last_error(void) { return g_err; }
+
+int bml_state_bytes(int32_t n, int32_t layout, size_t *bytes)
+{
+    clear_error();
+    if (!bytes)
+        return fail(BML_EINVAL, "bytes is NULL");
+    if (!valid_n(n))
+        return fail(BML_EINVAL, "n=%d must be a multiple of 32 in [32, 65504]", n);
+    if (layout == BML_LAYOUT_U8)
+        *bytes = (size_t)n * n;
+    else if (layout == BML_LAYOUT_BITPLANE)
+        *bytes = (size_t)n * n / 4;
+    else
+        return fail(BML_EINVAL, "unknown layout %d", layout);
+    return BML_OK;
+}
+
+int bml_pack(int32_t n, const uint8_t *d_cells, uint32_t *d_planes, void *hip_stream)
+{
+    clear_error();
+    if (!valid_n(n) || !d_cells || !d_planes)
+        return fail(BML_EINVAL, "bml_pack: bad n or NULL buffer");
+    if (!aligned256(d_cells) || !aligned256(d_planes))
+        return fail(BML_EINVAL, "bml_pack: buffers must be 256-byte aligned");
+    const int64_t total_words = (int64_t)n * (n / 32);
+    unsigned grid;
+    int rc = launch_1d_grid(total_words, 256, &grid);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_cells, d_planes, total_words);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_unpack(int32_t n, const uint32_t *d_planes, uint8_t *d_cells, void *hip_stream)
+{
+    clear_error();
+    if (!valid_n(n) || !d_cells || !d_planes)
+        return fail(BML_EINVAL, "bml_unpack: bad n or NULL buffer");
+    if (!aligned256(d_cells) || !aligned256(d_planes))
+        return fail(BML_EINVAL, "bml_unpack: buffers must be 256-byte aligned");
+    const int64_t total_words = (int64_t)n * (n / 32);
+    unsigned grid;
+    int rc = launch_1d_grid(total_words, 256, &grid);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_planes, d_cells, total_words);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double rho,
+             const uint8_t *cells_host, void *d_state_a, void *d_state_b,
+             bml_step_stats *d_stats, int64_t stats_cap, void *hip_stream)
+{
+    clear_error();
+    if (!out)
+        return fail(BML_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t bytes = 0;
+    int rc = bml_state_bytes(n, layout, &bytes);
+    if (rc)
+        return rc;
+    if (!d_state_a || !d_state_b || !d_stats)
+        return fail(BML_EINVAL, "state or stats buffer is NULL");
+    if (d_state_a == d_state_b)
+        return fail(BML_EINVAL, "the two state buffers must differ");
+    if (!aligned256(d_state_a) || !aligned256(d_state_b) || !aligned256(d_stats))
+        return fail(BML_EINVAL, "device buffers must be 256-byte aligned");
+    {
+        const uintptr_t a = (uintptr_t)d_state_a, b = (uintptr_t)d_state_b;
+        if (a < b + bytes && b < a + bytes)
+            return fail(BML_EINVAL, "state buffers overlap");
+    }
+    if (stats_cap < 1 || stats_cap > 0x7fffffff)
+        return fail(BML_EINVAL, "stats_cap=%lld must be in [1, 2^31-1]", (long long)stats_cap);
+    if (!cells_host && !(rho >= 0.0 && rho <= 1.0))
+        return fail(BML_EINVAL, "rho must be in [0, 1]");
+    if (cells_host) {
+        for (size_t k = 0; k < (size_t)n * n; ++k)
+            if (cells_host[k] > 2)
+                return fail(BML_EINVAL, "cell %zu has value %d (must be 0, 1 or 2)", k,
+                            (int)cells_host[k]);
+    }
+
+    bml_lattice *L = new (std::nothrow) bml_lattice();
+    if (!L)
+        return fail(BML_EDEVICE, "out of host memory");
+    L->n = n;
+    L->layout = layout;
+    L->buf[0] = d_state_a;
+    L->buf[1] = d_state_b;
+    L->stats = (uint32_t *)d_stats;
+    L->cap = stats_cap;
+    L->stream = (hipStream_t)hip_stream;
+    L->t_phases = layout == BML_LAYOUT_U8 ? 8 : 16;
+    L->tile_rows = 64;
+    L->wpb = 4;
+    auto cleanup = [&](int code) {
+        if (L->d_counts)
+            (void)hipFree(L->d_counts);
+        if (L->d_scratch)
+            (void)hipFree(L->d_scratch);
+        delete L;
+        return code;
+    };
+    if ((rc = device_info(&L->dev)))
+        return cleanup(rc);
+    if (hipMalloc(&L->d_counts, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        L->d_counts = nullptr;
+        return cleanup(fail(BML_EDEVICE, "hipMalloc of count scratch failed"));
+    }
+    if (hipMalloc(&L->d_scratch, sizeof(PassScratch)) != hipSuccess) {
+        L->d_scratch = nullptr;
+        return cleanup(fail(BML_EDEVICE, "hipMalloc of stats scratch failed"));
+    }
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, L->stream,
+                       (uint32_t *)L->d_scratch, (int)(sizeof(PassScratch) / 4));
+
+    const int32_t words = n / 32;
+    const int64_t total_words = (int64_t)n * words;
+    unsigned grid;
+    if ((rc = launch_1d_grid(total_words, 256, &grid)))
+        return cleanup(rc);
+    if (!cells_host) {
+        const uint64_t thr_lr = (uint64_t)ldexp(rho * 0.5, 53);
+        const uint64_t thr_tb = (uint64_t)ldexp(rho, 53);
+        if (layout == BML_LAYOUT_U8)
+            hipLaunchKernelGGL(init_kernel<IO_U8>, dim3(grid), dim3(256), 0, L->stream,
+                               d_state_a, n, words, seed, thr_lr, thr_tb);
+        else
+            hipLaunchKernelGGL(init_kernel<IO_BP>, dim3(grid), dim3(256), 0, L->stream,
+                               d_state_a, n, words, seed, thr_lr, thr_tb);
+        if (hipGetLastError() != hipSuccess)
+            return cleanup(fail(BML_EDEVICE, "init kernel launch failed"));
+    } else if (layout == BML_LAYOUT_U8) {
+        if (hipMemcpyAsync(d_state_a, cells_host, bytes, hipMemcpyHostToDevice, L->stream) !=
+            hipSuccess)
+            return cleanup(fail(BML_EDEVICE, "hipMemcpyAsync of the initial cells failed"));
+    } else {
+        // The byte lattice is 4x larger than a bitplane state buffer, so it
+        // is staged in a temporary device buffer and packed from there.
+        void *tmp = nullptr;
+        if (hipMalloc(&tmp, (size_t)n * n) != hipSuccess)
+            return cleanup(fail(BML_EDEVICE, "hipMalloc of the staging buffer failed"));
+        bool ok = hipMemcpyAsync(tmp, cells_host, (size_t)n * n, hipMemcpyHostToDevice,
+                                 L->stream) == hipSuccess;
+        if (ok) {
+            hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, L->stream,
+                               (const uint8_t *)tmp, (uint32_t *)d_state_a, total_words);
+            ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(L->stream) == hipSuccess;
+        }
+        (void)hipFree(tmp);
+        if (!ok)
+            return cleanup(fail(BML_EDEVICE, "upload/pack of the initial cells failed"));
+    }
+    if ((rc = count_cars(L, d_state_a, &L->n_lr0, &L->n_tb0)))
+        return cleanup(rc);
+    {
+        std::lock_guard<std::mutex> lock(g_handles_mu);
+        g_handles.insert(L);
+    }
+    *out = L;
+    return BML_OK;
+}
+
+int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases, int32_t waves_per_block)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    const int R = tile_rows ? tile_rows : L->tile_rows;
+    const int T = t_phases ? t_phases : L->t_phases;
+    const int W = waves_per_block ? waves_per_block : L->wpb;
+    if (rows_index(R) < 0)
+        return fail(BML_EINVAL, "tile_rows=%d must be 32 or 64", R);
+    if (T < 2 || T > 2 * MAX_K || T % 2)
+        return fail(BML_EINVAL, "t_phases=%d must be even in [2, %d]", T, 2 * MAX_K);
+    if (W != 1 && W != 2 && W != 4)
+        return fail(BML_EINVAL, "waves_per_block=%d must be 1, 2 or 4", W);
+    L->tile_rows = R;
+    L->t_phases = T;
+    L->wpb = W;
+    return BML_OK;
+}
+
+int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
+                   int32_t *waves_per_block)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    if (tile_rows)
+        *tile_rows = L->tile_rows;
+    if (t_phases)
+        *t_phases = L->t_phases;
+    if (waves_per_block)
+        *waves_per_block = L->wpb;
+    return BML_OK;
+}
+
+// Output rows per tile actually used: the tuned value if it divides N,
+// else 32 (every valid N is a multiple of 32).
+static int effective_rows(const bml_lattice *L)
+{
+    return L->n % L->tile_rows == 0 ? L->tile_rows : 32;
+}
+
+// One kernel pass of k steps starting at global step `step0`.
+static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
+{
+    const int io = L->layout == BML_LAYOUT_U8 ? IO_U8 : IO_BP;
+    const int VR = effective_rows(L);
+    const int ri = rows_index(VR);
+    PassArgs a;
+    a.src = L->buf[L->cur];
+    a.dst = L->buf[L->cur ^ 1];
+    a.stats = L->stats;
+    a.scratch = L->d_scratch;
+    a.n = L->n;
+    a.words = L->n / 32;
+    a.tiles_x = (a.words + TILE_WORDS - 1) / TILE_WORDS;
+    a.n_tiles = a.tiles_x * (L->n / VR);
+    a.rec_mask = 0;
+    for (int j = 0; j < MAX_K; ++j) {
+        a.slot[j] = 0;
+        if (j < k && step0 + j >= rec_from) {
+            a.rec_mask |= 1u << j;
+            a.slot[j] = (int32_t)((step0 + j) % L->cap);
+        }
+    }
+    const int threads = 64 * L->wpb;
+    int per_cu = 1;
+    int rc = resident_blocks(io, ri, k, threads, &per_cu);
+    if (rc)
+        return rc;
+    const int64_t max_blocks = (int64_t)per_cu * L->dev.cu_count;
+    const int64_t tile_blocks = (a.n_tiles + L->wpb - 1) / L->wpb;
+    // Even out the rounds: every wavefront gets ceil(tiles / waves) tiles.
+    const int64_t rounds = (tile_blocks + max_blocks - 1) / max_blocks;
+    int64_t grid = (tile_blocks + rounds - 1) / rounds;
+    if (grid >= 8) {
+        grid = (grid + 7) / 8 * 8;
+        if (grid > max_blocks)
+            grid = max_blocks / 8 * 8;
+    }
+    a.xcd_split = (grid >= 8 && grid % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(kernels().fn[io][ri][k], dim3((unsigned)grid), dim3(threads), 0,
+                       L->stream, a);
+    BML_HIP(hipGetLastError());
+    L->cur ^= 1;
+    return BML_OK;
+}
+
+int bml_step(bml_lattice *L, int64_t n_steps)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    if (n_steps < 0)
+        return fail(BML_EINVAL, "n_steps must be >= 0");
+    if (n_steps == 0)
+        return BML_OK;
+    const int64_t end = L->steps_done + n_steps;
+    const int64_t kept = std::min<int64_t>(n_steps, L->cap);
+    const int64_t rec_from = end - kept;   // earlier steps of this call would be overwritten
+    const int K = L->t_phases / 2;
+    int64_t s = L->steps_done;
+    while (s < end) {
+        const int k = (int)std::min<int64_t>(K, end - s);
+        int rc = run_pass(L, k, s, rec_from);
+        if (rc)
+            return rc;
+        s += k;
+        L->steps_done = s;
+    }
+    return BML_OK;
+}
+
+int bml_stats(bml_lattice *L, int64_t first_step, int64_t count, bml_step_stats *out_host)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    if (count < 0 || (count > 0 && !out_host))
+        return fail(BML_EINVAL, "bad count or NULL output");
+    if (first_step < 0 || first_step + count > L->steps_done ||
+        first_step < L->steps_done - L->cap)
+        return fail(BML_ERANGE, "steps [%lld, %lld) not retained (done %lld, ring %lld)",
+                    (long long)first_step, (long long)(first_step + count),
+                    (long long)L->steps_done, (long long)L->cap);
+    int64_t i = 0;
+    while (i < count) {
+        const int64_t slot = (first_step + i) % L->cap;
+        const int64_t run = std::min<int64_t>(count - i, L->cap - slot);
+        BML_HIP(hipMemcpyAsync(out_host + i, L->stats + slot * 4, run * sizeof(bml_step_stats),
+                               hipMemcpyDeviceToHost, L->stream));
+        i += run;
+    }
+    BML_HIP(hipStreamSynchronize(L->stream));
+    for (int64_t j = 0; j < count; ++j)
+        if (out_host[j].n_lr != L->n_lr0 || out_host[j].n_tb != L->n_tb0)
+            return fail(BML_ECORRUPT,
+                        "step %lld: car counts (%u, %u) differ from the initial (%llu, %llu)",
+                        (long long)(first_step + j), out_host[j].n_lr, out_host[j].n_tb,
+                        (unsigned long long)L->n_lr0, (unsigned long long)L->n_tb0);
+    return BML_OK;
+}
+
+int bml_get_cells(bml_lattice *L, uint8_t *out_host)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    if (!out_host)
+        return fail(BML_EINVAL, "out_host is NULL");
+    const size_t cells = (size_t)L->n * L->n;
+    if (L->layout == BML_LAYOUT_U8) {
+        BML_HIP(hipMemcpyAsync(out_host, L->buf[L->cur], cells, hipMemcpyDeviceToHost,
+                               L->stream));
+        BML_HIP(hipStreamSynchronize(L->stream));
+        return BML_OK;
+    }
+    void *tmp = nullptr;
+    BML_HIP(hipMalloc(&tmp, cells));
+    const int64_t total_words = (int64_t)L->n * (L->n / 32);
+    unsigned grid;
+    int rc = launch_1d_grid(total_words, 256, &grid);
+    if (rc) {
+        (void)hipFree(tmp);
+        return rc;
+    }
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid), dim3(256), 0, L->stream,
+                       (const uint32_t *)L->buf[L->cur], (uint8_t *)tmp, total_words);
+    bool ok = hipGetLastError() == hipSuccess &&
+              hipMemcpyAsync(out_host, tmp, cells, hipMemcpyDeviceToHost, L->stream) ==
+                  hipSuccess &&
+              hipStreamSynchronize(L->stream) == hipSuccess;
+    (void)hipFree(tmp);
+    if (!ok)
+        return fail(BML_EDEVICE, "unpack/copy of the cells failed");
+    return BML_OK;
+}
+
+int bml_initial_counts(const bml_lattice *L, uint64_t *n_lr, uint64_t *n_tb)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    if (n_lr)
+        *n_lr = L->n_lr0;
+    if (n_tb)
+        *n_tb = L->n_tb0;
+    return BML_OK;
+}
+
+int64_t bml_step_count(const bml_lattice *L) { return live(L) ? L->steps_done : -1; }
+
+const void *bml_current_state(const bml_lattice *L) { return live(L) ? L->buf[L->cur] : nullptr; }
+
+void bml_free(bml_lattice *L)
+{
+    if (!live(L))
+        return;
+    {
+        std::lock_guard<std::mutex> lock(g_handles_mu);
+        g_handles.erase(L);
+    }
+    (void)hipStreamSynchronize(L->stream);
+    if (L->d_counts)
+        (void)hipFree(L->d_counts);
+    if (L->d_scratch)
+        (void)hipFree(L->d_scratch);
+    delete L;
+}
+
+} // extern "C"

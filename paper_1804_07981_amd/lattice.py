@@ -1,0 +1,86 @@
+"""``Lattice``: one BML lattice on the GPU -- torch-allocated state buffers,
+stats ring and stream around a libbml handle."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as B
+
+
+class Lattice:
+    """An N x N periodic BML lattice resident in device memory.
+
+    Cells start from SplitMix64 stream `seed` at density `rho` (LR and TB
+    each with probability rho/2), or from `cells` (N x N bytes 0/1/2).
+    """
+
+    def __init__(self, n: int, rho: float = 0.3, seed: int = 0, *,
+                 layout: int = B.BML_LAYOUT_U8, cells: np.ndarray | None = None,
+                 stats_cap: int = 4096, device: str | torch.device = "cuda",
+                 stream: torch.cuda.Stream | None = None):
+        self.n = int(n)
+        self.layout = int(layout)
+        self.device = torch.device(device)
+        nbytes = B.bml_state_bytes(self.n, self.layout)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self._bufs = [torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                      for _ in range(2)]
+        self.stats_cap = int(stats_cap)
+        self._stats = torch.zeros(self.stats_cap * 4, dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            self.handle = B.bml_init(self.n, self.layout, seed, rho, cells,
+                                     self._bufs[0], self._bufs[1], self._stats,
+                                     self.stats_cap, self.stream)
+
+    # -- ABI passthroughs -------------------------------------------------
+    def step(self, n_steps: int = 1) -> None:
+        B.bml_step(self.handle, n_steps)
+
+    def stats(self, first_step: int | None = None, count: int | None = None,
+              check: bool = True) -> np.ndarray:
+        done = self.steps_done
+        if count is None:
+            count = min(done, self.stats_cap) if first_step is None else done - first_step
+        if first_step is None:
+            first_step = done - count
+        return B.bml_stats(self.handle, first_step, count, check=check)
+
+    def cells(self) -> np.ndarray:
+        return B.bml_get_cells(self.handle, self.n)
+
+    def set_tuning(self, tile_rows: int = 0, t_phases: int = 0,
+                   waves_per_block: int = 0) -> None:
+        B.bml_set_tuning(self.handle, tile_rows, t_phases, waves_per_block)
+
+    def tuning(self) -> tuple[int, int, int]:
+        return B.bml_get_tuning(self.handle)
+
+    def initial_counts(self) -> tuple[int, int]:
+        return B.bml_initial_counts(self.handle)
+
+    @property
+    def steps_done(self) -> int:
+        return B.bml_step_count(self.handle)
+
+    def state_tensor(self) -> torch.Tensor:
+        """The device buffer currently holding the state (uint8 view)."""
+        ptr = B.bml_current_state(self.handle)
+        return self._bufs[0] if ptr == self._bufs[0].data_ptr() else self._bufs[1]
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            B.bml_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,99 @@
+"""CPU-only checks of the C ABI library: it loads, exports every function
+include/bml.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bml.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bml_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    pkg = pytest.importorskip("paper_1804_07981_amd")
+    if not os.path.exists(pkg.library_path()):
+        pytest.skip("libbml.so not built")
+    return pkg
+
+
+def test_header_declares_core_entry_points():
+    names = declared_functions()
+    for n in ("bml_init", "bml_step", "bml_stats", "bml_get_cells", "bml_free",
+              "bml_last_error", "bml_state_bytes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    lib = ctypes.CDLL(B.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol(B):
+    assert set(declared_functions()) <= set(B.exported_symbols())
+
+
+@pytest.mark.parametrize("n,layout,want", [
+    (32, 0, 32 * 32), (64, 1, 64 * 64 // 4), (65504, 0, 65504 * 65504),
+    (4096, 1, 4096 * 4096 // 4)])
+def test_state_bytes(B, n, layout, want):
+    assert B.bml_state_bytes(n, layout) == want
+
+
+@pytest.mark.parametrize("n,layout", [(0, 0), (31, 0), (48, 0), (65536, 0), (64, 2), (-32, 1)])
+def test_state_bytes_rejects(B, n, layout):
+    with pytest.raises(B.BmlError) as e:
+        B.bml_state_bytes(n, layout)
+    assert e.value.code == B.BML_EINVAL
+    assert B.bml_last_error()
+
+
+def test_null_handle_is_estate(B):
+    lib = B.lib()
+    assert lib.bml_step(None, 1) == B.BML_ESTATE
+    assert lib.bml_step_count(None) == -1
+    assert lib.bml_current_state(None) is None
+    lib.bml_free(None)   # ignored
+
+
+def test_init_rejects_bad_arguments_without_gpu(B):
+    lib = B.lib()
+    h = ctypes.c_void_p()
+    # NULL buffers are rejected before any device call.
+    assert lib.bml_init(ctypes.byref(h), 64, 0, 0, 0.3, None, None, None, None, 16, None) \
+        == B.BML_EINVAL
+    assert lib.bml_init(None, 64, 0, 0, 0.3, None, None, None, None, 16, None) == B.BML_EINVAL
+    assert lib.bml_init(ctypes.byref(h), 33, 0, 0, 0.3, None, 256, 512, 1024, 16, None) \
+        == B.BML_EINVAL
+    # Misaligned buffers.
+    assert lib.bml_init(ctypes.byref(h), 64, 0, 0, 0.3, None, 257, 1 << 20, 1 << 21, 16, None) \
+        == B.BML_EINVAL
+    # Overlapping state buffers.
+    assert lib.bml_init(ctypes.byref(h), 64, 0, 0, 0.3, None, 1 << 20, (1 << 20) + 256,
+                        1 << 22, 16, None) == B.BML_EINVAL
+    # rho out of range, stats_cap out of range.
+    assert lib.bml_init(ctypes.byref(h), 64, 0, 0, 1.5, None, 1 << 20, 1 << 21, 1 << 22, 16,
+                        None) == B.BML_EINVAL
+    assert lib.bml_init(ctypes.byref(h), 64, 0, 0, float("nan"), None, 1 << 20, 1 << 21,
+                        1 << 22, 16, None) == B.BML_EINVAL
+    assert lib.bml_init(ctypes.byref(h), 64, 0, 0, 0.3, None, 1 << 20, 1 << 21, 1 << 22, 0,
+                        None) == B.BML_EINVAL
+
+
+def test_init_rejects_bad_cell_values_without_gpu(B):
+    import numpy as np
+    lib = B.lib()
+    h = ctypes.c_void_p()
+    cells = np.zeros(64 * 64, dtype=np.uint8)
+    cells[100] = 3
+    rc = lib.bml_init(ctypes.byref(h), 64, 0, 0, 0.3, cells.ctypes.data, 1 << 20, 1 << 21,
+                      1 << 22, 16, None)
+    assert rc == B.BML_EINVAL and "value 3" in B.bml_last_error()

@@ -1,0 +1,317 @@
+"""GPU parity of the single-lattice path (libbml through its C ABI) against
+the CPU oracle: every cell and every per-step count, bit for bit.
+
+Sizes span several tiles and the periodic wrap; tunings cover every kernel
+variant and pass length, including passes that end mid-pass (n_steps not a
+multiple of the steps per pass).  Large lattices are checked on sampled
+windows using the dependence cone: after s steps a cell depends only on
+cells within s rows and s columns of it, so a (W+2s)^2 periodic window of the
+initial lattice, run s steps by the oracle, fixes its middle W x W block.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+U8, BP = 0, 1
+LAYOUTS = [U8, BP]
+HOST_THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_07981_amd as pkg
+    pkg.lib()   # fail loudly if the library is missing
+    return pkg
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stats_array(rec):
+    return np.stack([rec["n_lr"], rec["moved_lr"], rec["n_tb"], rec["moved_tb"]], axis=1)
+
+
+def make(B, n, rho=0.3, seed=0, layout=U8, cells=None, cap=4096, tuning=None):
+    lat = B.Lattice(n, rho, seed, layout=layout, cells=cells, stats_cap=cap)
+    if tuning:
+        lat.set_tuning(*tuning)
+    return lat
+
+
+# --- initial placement --------------------------------------------------
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("n,seed,rho", [(32, 0, 0.3), (64, 5, 0.0), (96, 7, 1.0),
+                                        (256, 0, 0.3), (512, 12345, 0.45),
+                                        (1024, 2**63 + 11, 0.25)])
+def test_init_matches_oracle(B, layout, n, seed, rho):
+    say(f"init n={n} seed={seed} rho={rho} layout={layout}")
+    with make(B, n, rho, seed, layout) as lat:
+        want = oracle.init_cells(n, seed, rho)
+        assert np.array_equal(lat.cells(), want)
+        assert lat.initial_counts() == (oracle.count(want, 1), oracle.count(want, 2))
+
+
+# --- small lattice, every step --------------------------------------------
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_small_every_step(B, layout):
+    """256 x 256, rho 0.30, seed 0: all cells and counts after each of 1024
+    steps."""
+    say(f"small every step layout={layout}")
+    w = workloads.SMALL
+    lt = w.lattices[0]
+    ref = oracle.init_cells(lt.n, lt.seed, lt.rho)
+    with make(B, lt.n, lt.rho, lt.seed, layout, cap=w.steps) as lat:
+        assert np.array_equal(lat.cells(), ref)
+        for s in range(w.steps):
+            lat.step(1)
+            ref, st = oracle.run(ref, 1)
+            got = lat.cells()
+            if not np.array_equal(got, ref):
+                bad = np.argwhere(got != ref)
+                pytest.fail(f"step {s}: {len(bad)} cells differ, first at {bad[0]}")
+        want = oracle.run(oracle.init_cells(lt.n, lt.seed, lt.rho), w.steps)[1]
+        assert np.array_equal(stats_array(lat.stats(0, w.steps)), want)
+
+
+# --- random sizes, tunings, layouts ---------------------------------------
+
+TUNINGS = [(32, 2, 4), (64, 2, 4), (32, 4, 1), (64, 8, 2), (32, 16, 4), (64, 16, 1),
+           (32, 6, 2), (64, 10, 4)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("tuning", TUNINGS, ids=[f"vr{a}_t{b}_w{c}" for a, b, c in TUNINGS])
+def test_random_sizes_all_counts(B, layout, tuning):
+    rng = np.random.default_rng(hash((layout,) + tuning) % 2**32)
+    for n in (32, 64, 96, 160, 224, 384, 2048 + 96):
+        steps = int(rng.integers(1, 40))
+        rho = float(rng.choice([0.1, 0.3, 0.38, 0.5, 0.9]))
+        seed = int(rng.integers(0, 2**32))
+        say(f"random n={n} steps={steps} rho={rho} seed={seed} layout={layout} tuning={tuning}")
+        g0 = oracle.init_cells(n, seed, rho)
+        want, wst = oracle.run(g0, steps, n_threads=HOST_THREADS)
+        with make(B, n, rho, seed, layout, cap=64, tuning=tuning) as lat:
+            lat.step(steps)
+            assert np.array_equal(lat.cells(), want), (n, steps)
+            assert np.array_equal(stats_array(lat.stats(0, steps)), wst), (n, steps)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_hand_made_lattices(B, layout):
+    n = 64
+    cases = {
+        "lone_lr": workloads.lone_car(n, 1, 5, 63),
+        "lone_tb": workloads.lone_car(n, 2, 63, 7),
+        "checkerboard_full": workloads.full_checkerboard(n),
+        "rows_full": workloads.full_rows(n),
+        "empty": np.zeros((n, n), np.uint8),
+    }
+    for name, g in cases.items():
+        say(f"hand-made {name} layout={layout}")
+        want, wst = oracle.run(g, n + 3)
+        with make(B, n, layout=layout, cells=g, cap=256, tuning=(32, 4, 2)) as lat:
+            lat.step(n + 3)
+            assert np.array_equal(lat.cells(), want), name
+            assert np.array_equal(stats_array(lat.stats(0, n + 3)), wst), name
+
+
+def test_lone_car_returns(B):
+    n = 96
+    g = workloads.lone_car(n, 1, 40, 95)
+    with make(B, n, cells=g, tuning=(32, 16, 4)) as lat:
+        lat.step(n)
+        assert np.array_equal(lat.cells(), g)
+        st = stats_array(lat.stats(0, n))
+        assert (st == np.array([1, 1, 0, 0])).all()
+
+
+# --- invariance -------------------------------------------------------------
+
+def test_tuning_and_layout_invariance(B):
+    n, steps = 320, 57
+    ref = None
+    for layout in LAYOUTS:
+        for vr in (32, 64):
+            for t in (2, 4, 8, 12, 16):
+                for w in (1, 4):
+                    say(f"invariance layout={layout} vr={vr} t={t} w={w}")
+                    with make(B, n, 0.33, 99, layout, cap=steps, tuning=(vr, t, w)) as lat:
+                        lat.step(steps)
+                        got = (lat.cells(), stats_array(lat.stats(0, steps)))
+                    if ref is None:
+                        ref = got
+                        want, wst = oracle.run(oracle.init_cells(n, 99, 0.33), steps)
+                        assert np.array_equal(ref[0], want) and np.array_equal(ref[1], wst)
+                    else:
+                        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_step_calls_compose(B):
+    """Many small bml_step calls equal one large one (pass boundaries inside
+    and across calls)."""
+    n = 128
+    with make(B, n, 0.35, 3, U8, cap=200, tuning=(32, 8, 4)) as a, \
+            make(B, n, 0.35, 3, U8, cap=200, tuning=(32, 8, 4)) as b:
+        a.step(101)
+        for k in (1, 2, 3, 5, 7, 11, 13, 17, 19, 23):
+            b.step(k)
+        b.step(0)
+        assert b.steps_done == 101
+        assert np.array_equal(a.cells(), b.cells())
+        assert np.array_equal(stats_array(a.stats(0, 101)), stats_array(b.stats(0, 101)))
+
+
+def test_checkpoint_resume(B):
+    n = 256
+    for layout in LAYOUTS:
+        with make(B, n, 0.31, 8, layout) as full:
+            full.step(150)
+            want = full.cells()
+            wst = stats_array(full.stats(100, 50))
+        with make(B, n, 0.31, 8, layout) as a:
+            a.step(100)
+            mid = a.cells()
+        with make(B, n, layout=layout, cells=mid) as b:
+            b.step(50)
+            assert np.array_equal(b.cells(), want)
+            assert np.array_equal(stats_array(b.stats(0, 50)), wst)
+
+
+# --- stats ring and errors ----------------------------------------------------
+
+def test_stats_ring_window(B):
+    n, cap = 64, 10
+    g0 = oracle.init_cells(n, 4, 0.3)
+    _, wst = oracle.run(g0, 37)
+    with make(B, n, 0.3, 4, U8, cap=cap, tuning=(32, 6, 4)) as lat:
+        lat.step(25)
+        lat.step(12)
+        assert np.array_equal(stats_array(lat.stats(27, 10)), wst[27:37])
+        assert np.array_equal(stats_array(lat.stats(30, 5)), wst[30:35])
+        for first, count in ((26, 2), (30, 8), (-1, 1)):
+            with pytest.raises(B.BmlError) as e:
+                lat.stats(first, count)
+            assert e.value.code == B.BML_ERANGE
+
+
+def test_corruption_is_detected(B):
+    import torch
+    n = 64
+    with make(B, n, 0.2, 1, U8) as lat:
+        lat.step(3)
+        buf = lat.state_tensor()
+        cells = buf.view(n, n)
+        empty = (cells == 0).nonzero()[0]
+        cells[empty[0], empty[1]] = 1    # one extra LR car appears
+        torch.cuda.synchronize()
+        lat.step(2)
+        with pytest.raises(B.BmlError) as e:
+            lat.stats(3, 2)
+        assert e.value.code == B.BML_ECORRUPT
+        rec = lat.stats(3, 2, check=False)
+        assert rec["n_lr"][0] == lat.initial_counts()[0] + 1
+
+
+def test_errors_and_free(B):
+    with pytest.raises(B.BmlError) as e:
+        make(B, 48)
+    assert e.value.code == B.BML_EINVAL
+    lat = make(B, 64)
+    with pytest.raises(B.BmlError) as e:
+        lat.set_tuning(48, 0, 0)
+    assert e.value.code == B.BML_EINVAL
+    with pytest.raises(B.BmlError):
+        lat.set_tuning(0, 3, 0)
+    with pytest.raises(B.BmlError):
+        lat.set_tuning(0, 0, 8)
+    with pytest.raises(B.BmlError):
+        lat.step(-1)
+    h = lat.handle
+    lat.close()
+    with pytest.raises(B.BmlError) as e:
+        B.bml_step(h, 1)
+    assert e.value.code == B.BML_ESTATE
+
+
+def test_pack_unpack_roundtrip(B):
+    import torch
+    n = 192
+    g = workloads.random_lattice(np.random.default_rng(5), n, n, 0.3, 0.3)
+    d_cells = torch.from_numpy(g).cuda()
+    d_planes = torch.empty(n * n // 4, dtype=torch.uint8, device="cuda")
+    d_back = torch.empty_like(d_cells)
+    B.bml_pack(n, d_cells, d_planes)
+    B.bml_unpack(n, d_planes, d_back)
+    torch.cuda.synchronize()
+    lr, tb = oracle.pack(g)
+    planes = d_planes.cpu().numpy().view(np.uint32)
+    assert np.array_equal(planes[: n * n // 32].reshape(n, n // 32), lr)
+    assert np.array_equal(planes[n * n // 32:].reshape(n, n // 32), tb)
+    assert np.array_equal(d_back.cpu().numpy(), g)
+
+
+# --- the 4096 x 4096 workload, whole lattice --------------------------------
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_medium_full_lattice(B, layout):
+    """4096 x 4096 at rho 0.38 (seed 3 as in the four-density workload),
+    default tuning: every cell and count after 120 steps."""
+    n, rho, seed, steps = 4096, 0.38, 3, 120
+    say(f"medium full n={n} layout={layout}")
+    g0 = oracle.init_cells(n, seed, rho)
+    want, wst = oracle.run(g0, steps, n_threads=HOST_THREADS)
+    with make(B, n, rho, seed, layout, cap=steps) as lat:
+        lat.step(steps)
+        assert np.array_equal(lat.cells(), want)
+        assert np.array_equal(stats_array(lat.stats(0, steps)), wst)
+
+
+# --- the 32768 x 32768 workload, sampled windows --------------------------
+
+def window(g, i0, j0, size):
+    n = g.shape[0]
+    rows = np.arange(i0, i0 + size) % n
+    cols = np.arange(j0, j0 + size) % n
+    return g[np.ix_(rows, cols)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_large_sampled_windows(B, layout):
+    """32768 x 32768, rho 0.30, seed 7, in the launch shape the benchmark
+    times: 48 steps, then 12 windows of 64 x 64 (corners, edges, interior)
+    checked against the oracle on padded windows; car counts conserved every
+    step; the first two steps' counts checked against the whole-lattice
+    oracle."""
+    n, rho, seed, steps, W = 32768, 0.30, 7, 48, 64
+    say(f"large sampled n={n} layout={layout}")
+    g0 = oracle.init_cells(n, seed, rho)
+    with make(B, n, rho, seed, layout, cap=steps) as lat:
+        lat.step(2)
+        got2 = stats_array(lat.stats(0, 2))
+        lat.step(steps - 2)
+        got = lat.cells()
+        st = stats_array(lat.stats(0, steps))
+    _, want2 = oracle.run(g0, 2, n_threads=HOST_THREADS)
+    assert np.array_equal(got2, want2)
+    assert (st[:, 0] == oracle.count(g0, 1)).all() and (st[:, 2] == oracle.count(g0, 2)).all()
+    rng = np.random.default_rng(7)
+    picks = [(0, 0), (0, n - W), (n - W, 0), (n - W, n - W), (n // 2, n // 2 - 32)]
+    picks += [tuple(int(x) for x in rng.integers(0, n, size=2)) for _ in range(7)]
+    for i0, j0 in picks:
+        pad = window(g0, i0 - steps, j0 - steps, W + 2 * steps)
+        ref, _ = oracle.run(pad, steps)
+        assert np.array_equal(window(got, i0, j0, W), ref[steps:steps + W, steps:steps + W]), \
+            (i0, j0)
