@@ -180,7 +180,8 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"pass_kernel<{args.layout}, K={k}, VR={res['tile_rows']}>",
+                "kernel": f"pass_kernel<{args.layout}, K={k}> (strip rows "
+                          f"{res['tile_rows'] or 'auto'}, {res['wpb']} waves/block)",
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_us": round(per_launch_s * 1e6, 2)}
 

@@ -113,12 +113,14 @@ int bml_get_cells(bml_lattice *L, uint8_t *out_host);
 /* Initial car counts computed at bml_init. */
 int bml_initial_counts(const bml_lattice *L, uint64_t *n_lr, uint64_t *n_tb);
 
-/* Launch shape of the step kernels: tile_rows = lattice rows one wavefront
- * writes per tile (32 or 64; 64 is used only when it divides N, else 32),
- * t_phases = phases per HBM pass (even, 2..16; each pass advances every
- * tile t_phases/2 steps), waves_per_block = 1, 2 or 4.  0 keeps the current
- * value.  Results do not depend on the tuning; only speed does.  EINVAL on
- * any other value. */
+/* Launch shape of the step kernels.  Each wavefront streams down a strip of
+ * the lattice 62 words (1984 cells) wide and `tile_rows` output rows tall
+ * (plus t_phases/2 halo rows above and below), advancing every row
+ * t_phases/2 steps per pass (t_phases even, 2..16).  tile_rows = 0 picks the
+ * strip height from the occupancy of the device; otherwise 8 <= tile_rows
+ * <= 65504.  waves_per_block = 1, 2 or 4.  A negative tile_rows, or a
+ * t_phases / waves_per_block <= 0, keeps the current value.  Results do not
+ * depend on the tuning; only speed does.  EINVAL on any other value. */
 int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases,
                    int32_t waves_per_block);
 int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
@@ -146,6 +148,131 @@ int bml_pack(int32_t n, const uint8_t *d_cells, uint32_t *d_planes,
              void *hip_stream);
 int bml_unpack(int32_t n, const uint32_t *d_planes, uint8_t *d_cells,
                void *hip_stream);
+
+/* ---------------- batched sweeps -------------------------------------------
+ * Many independent lattices of (possibly) different N advanced together: one
+ * kernel launch per pass covers every active lattice, and a run of passes
+ * can be captured once in a hipGraph and replayed.  Each lattice starts from
+ * SplitMix64 stream seed[b] at density rho[b] as in bml_init.  Per step and
+ * lattice the number of LR and TB cars that moved is written to a trace:
+ * trace[(b * trace_steps + s) * 2 + 0] = LR moved, ... + 1] = TB moved, for
+ * global step s < trace_steps (s counts every step the batch ran; a lattice
+ * that was inactive during a step has 0 there).  Car counts are conserved;
+ * bml_batch_check verifies that. */
+typedef struct bml_batch bml_batch;
+
+/* Bytes of the caller-owned device arena that holds two state buffers per
+ * lattice (each rounded up to 256 bytes). */
+int bml_batch_arena_bytes(int32_t count, const int32_t *n, int32_t layout, size_t *bytes);
+
+/* n, rho, seed: host arrays of `count` entries.  d_arena: caller device
+ * memory of bml_batch_arena_bytes(), 256-byte aligned.  d_trace: caller
+ * device memory of count * trace_steps * 2 uint32, 256-byte aligned.
+ * Synchronises the stream (initial car counts).  Every lattice is active. */
+int bml_batch_init(bml_batch **out, int32_t count, const int32_t *n, const double *rho,
+                   const uint64_t *seed, int32_t layout, void *d_arena, size_t arena_bytes,
+                   uint32_t *d_trace, int64_t trace_steps, void *hip_stream);
+
+/* strip_rows: target strip height (the largest divisor of each N not above
+ * it is used), t_phases: even, 2..16, waves_per_block: 1, 2 or 4; values
+ * <= 0 keep the current setting.  Drops a captured graph.  Synchronises. */
+int bml_batch_set_tuning(bml_batch *B, int32_t strip_rows, int32_t t_phases,
+                         int32_t waves_per_block);
+
+/* active_host: `count` bytes, non-zero = the lattice advances in later runs
+ * (NULL = all).  Inactive lattices keep their state.  Synchronises. */
+int bml_batch_set_active(bml_batch *B, const uint8_t *active_host);
+
+/* Enqueue n_steps steps of every active lattice (asynchronous). */
+int bml_batch_run(bml_batch *B, int64_t n_steps);
+
+/* Capture bml_batch_run(B, n_steps) into a hipGraph (nothing runs), and
+ * replay it with bml_batch_replay (asynchronous).  The graph reads the step
+ * counter, the parities and the active list from device memory, so replays
+ * continue where the batch stands.  Needs a non-null stream. */
+int bml_batch_capture(bml_batch *B, int64_t n_steps);
+int bml_batch_replay(bml_batch *B);
+
+/* Global steps run (-1 for a bad handle); steps run by lattice idx. */
+int64_t bml_batch_step_count(const bml_batch *B);
+int bml_batch_lattice_steps(const bml_batch *B, int32_t idx, int64_t *steps);
+
+/* Initial car counts of lattice idx. */
+int bml_batch_initial_counts(const bml_batch *B, int32_t idx, uint64_t *n_lr, uint64_t *n_tb);
+
+/* Copy lattice idx to out_host (N*N bytes, values 0..2).  Synchronises. */
+int bml_batch_get_cells(bml_batch *B, int32_t idx, uint8_t *out_host);
+
+/* Recount every lattice: ECORRUPT if any car count changed.  Synchronises. */
+int bml_batch_check(bml_batch *B);
+
+/* Release the handle and the library's scratch (synchronises first). */
+void bml_batch_free(bml_batch *B);
+
+/* ---------------- learned early exit ------------------------------------------
+ * Below a critical density a BML lattice settles into free flow, above it
+ * into a global jam, with both possible near the critical point (Sec. 2).
+ * A small MLP reads a lattice's early mobile-fraction trajectory and its
+ * density and predicts which: 65 inputs -> 64 (ReLU) -> 64 (ReLU) -> 1 logit
+ * (p = sigmoid(logit) = probability of a jam).  Its BML_MLP_PARAMS fp32
+ * parameters are one array, row-major (out x in):
+ *   W1[64][65] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3.
+ * All pointers below are device pointers; all calls are asynchronous. */
+#define BML_MLP_INPUTS 65
+#define BML_MLP_HIDDEN 64
+#define BML_MLP_PARAMS 8449
+#define BML_MLP_MAX_BATCH 256
+
+/* out[b][m] (m < 64) = (sum over steps window*m .. window*m+window-1 of
+ * trace LR moved + TB moved) / (window * cars[b]), computed in double and
+ * rounded to float (1 for a lattice without cars); out[b][64] = rho[b].
+ * trace as in bml_batch_init ([count][trace_steps][2] uint32); 64 windows
+ * must fit in trace_steps. */
+int bml_features(const uint32_t *d_trace, int64_t trace_steps, int32_t count,
+                 const uint64_t *d_cars, const double *d_rho, int32_t window,
+                 float *d_out, void *hip_stream);
+
+/* frozen[b] = 1 if some global step in [first_step, end_step) of lattice b
+ * moved no car (such a lattice is a fixed point from then on: the exact
+ * stop rule), else 0. */
+int bml_trace_frozen(const uint32_t *d_trace, int64_t trace_steps, int32_t count,
+                     int64_t first_step, int64_t end_step, uint8_t *d_frozen, void *hip_stream);
+
+/* mean[b] = mean over steps [first_step, end_step) of the mobile fraction
+ * (LR moved + TB moved) / cars[b], in double (1 without cars). */
+int bml_trace_mobility(const uint32_t *d_trace, int64_t trace_steps, int32_t count,
+                       const uint64_t *d_cars, int64_t first_step, int64_t end_step,
+                       double *d_mean, void *hip_stream);
+
+/* Column means and standard deviations (population) of x[n][65], and the
+ * in-place standardisation x = (x - mean) / std in float. */
+int bml_feature_stats(const float *d_x, int32_t n, float *d_mean, float *d_std,
+                      void *hip_stream);
+int bml_standardize(float *d_x, int32_t n, const float *d_mean, const float *d_std,
+                    void *hip_stream);
+
+/* Device scratch bml_mlp_grad / bml_mlp_train_step need. */
+size_t bml_mlp_scratch_bytes(void);
+
+/* Gradient (fp32) of the mean binary cross-entropy with logits of samples
+ * x[0..n), labels y (1 = jammed), 1 <= n <= 256, into grad[8449]; the loss
+ * into *loss. */
+int bml_mlp_grad(const float *d_params, const float *d_x, const float *d_y, int32_t n,
+                 void *d_scratch, float *d_grad, float *d_loss, void *hip_stream);
+
+/* One Adam step (t = 1, 2, ...) on the minibatch x[idx[0..n)] (n <= 256):
+ * the gradient as above, then m, v and params updated in place. */
+int bml_mlp_train_step(float *d_params, float *d_m, float *d_v, float *d_grad, int64_t t,
+                       const float *d_x, const float *d_y, const int32_t *d_idx, int32_t n,
+                       float lr, float beta1, float beta2, float eps, void *d_scratch,
+                       float *d_loss, void *hip_stream);
+
+/* Logits of n samples: fp32, and BF16 (weights and every layer's input
+ * rounded to bfloat16, nearest-even; biases and accumulation in fp32). */
+int bml_mlp_forward(const float *d_params, const float *d_x, int32_t n, float *d_logits,
+                    void *hip_stream);
+int bml_mlp_infer_bf16(const float *d_params, const float *d_x, int32_t n, float *d_logits,
+                       void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,16 @@ from ._lib import (BML_EBADARG, BML_ECORRUPT, BML_EDEVICE, BML_EINVAL,
                    bml_free, bml_get_cells, bml_get_tuning, bml_init,
                    bml_initial_counts, bml_last_error, bml_pack, bml_set_tuning,
                    bml_state_bytes, bml_stats, bml_step, bml_step_count,
-                   bml_unpack, exported_symbols, lib, library_path)
+                   bml_unpack, exported_symbols, lib, library_path,
+                   bml_batch_arena_bytes, bml_batch_init, bml_batch_set_tuning,
+                   bml_batch_set_active, bml_batch_run, bml_batch_capture,
+                   bml_batch_replay, bml_batch_step_count, bml_batch_lattice_steps,
+                   bml_batch_initial_counts, bml_batch_get_cells, bml_batch_check,
+                   bml_batch_free, bml_features, bml_trace_frozen, bml_trace_mobility,
+                   bml_feature_stats, bml_standardize, bml_mlp_scratch_bytes,
+                   bml_mlp_grad, bml_mlp_train_step, bml_mlp_forward, bml_mlp_infer_bf16,
+                   BML_MLP_INPUTS, BML_MLP_HIDDEN, BML_MLP_PARAMS, BML_MLP_MAX_BATCH)
+from .batch import Batch
 from .lattice import Lattice
 
 __all__ = [
@@ -26,5 +35,12 @@ __all__ = [
     "exported_symbols", "bml_state_bytes", "bml_init", "bml_step", "bml_stats",
     "bml_get_cells", "bml_initial_counts", "bml_set_tuning", "bml_get_tuning",
     "bml_step_count", "bml_current_state", "bml_free", "bml_last_error",
-    "bml_pack", "bml_unpack",
+    "bml_pack", "bml_unpack", "Batch", "bml_batch_arena_bytes", "bml_batch_init",
+    "bml_batch_set_tuning", "bml_batch_set_active", "bml_batch_run", "bml_batch_capture",
+    "bml_batch_replay", "bml_batch_step_count", "bml_batch_lattice_steps",
+    "bml_batch_initial_counts", "bml_batch_get_cells", "bml_batch_check", "bml_batch_free",
+    "bml_features", "bml_trace_frozen", "bml_trace_mobility", "bml_feature_stats",
+    "bml_standardize", "bml_mlp_scratch_bytes", "bml_mlp_grad", "bml_mlp_train_step",
+    "bml_mlp_forward", "bml_mlp_infer_bf16", "BML_MLP_INPUTS", "BML_MLP_HIDDEN",
+    "BML_MLP_PARAMS", "BML_MLP_MAX_BATCH",
 ]

@@ -61,6 +61,33 @@ _SIGNATURES = {
     "bml_last_error": ([], ctypes.c_char_p),
     "bml_pack": ([_i32, _vp, _vp, _vp], ctypes.c_int),
     "bml_unpack": ([_i32, _vp, _vp, _vp], ctypes.c_int),
+    "bml_batch_arena_bytes": ([_i32, _vp, _i32, ctypes.POINTER(_sz)], ctypes.c_int),
+    "bml_batch_init": ([ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _i32, _vp, _sz, _vp, _i64,
+                        _vp], ctypes.c_int),
+    "bml_batch_set_tuning": ([_vp, _i32, _i32, _i32], ctypes.c_int),
+    "bml_batch_set_active": ([_vp, _vp], ctypes.c_int),
+    "bml_batch_run": ([_vp, _i64], ctypes.c_int),
+    "bml_batch_capture": ([_vp, _i64], ctypes.c_int),
+    "bml_batch_replay": ([_vp], ctypes.c_int),
+    "bml_batch_step_count": ([_vp], _i64),
+    "bml_batch_lattice_steps": ([_vp, _i32, ctypes.POINTER(_i64)], ctypes.c_int),
+    "bml_batch_initial_counts": ([_vp, _i32, ctypes.POINTER(_u64), ctypes.POINTER(_u64)],
+                                 ctypes.c_int),
+    "bml_batch_get_cells": ([_vp, _i32, _vp], ctypes.c_int),
+    "bml_batch_check": ([_vp], ctypes.c_int),
+    "bml_batch_free": ([_vp], None),
+    "bml_features": ([_vp, _i64, _i32, _vp, _vp, _i32, _vp, _vp], ctypes.c_int),
+    "bml_trace_frozen": ([_vp, _i64, _i32, _i64, _i64, _vp, _vp], ctypes.c_int),
+    "bml_trace_mobility": ([_vp, _i64, _i32, _vp, _i64, _i64, _vp, _vp], ctypes.c_int),
+    "bml_feature_stats": ([_vp, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "bml_standardize": ([_vp, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "bml_mlp_scratch_bytes": ([], _sz),
+    "bml_mlp_grad": ([_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "bml_mlp_train_step": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i32, ctypes.c_float,
+                            ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp, _vp, _vp],
+                           ctypes.c_int),
+    "bml_mlp_forward": ([_vp, _vp, _i32, _vp, _vp], ctypes.c_int),
+    "bml_mlp_infer_bf16": ([_vp, _vp, _i32, _vp, _vp], ctypes.c_int),
 }
 
 
@@ -164,7 +191,7 @@ def bml_initial_counts(handle: int) -> tuple[int, int]:
     return int(a.value), int(b.value)
 
 
-def bml_set_tuning(handle: int, tile_rows: int = 0, t_phases: int = 0,
+def bml_set_tuning(handle: int, tile_rows: int = -1, t_phases: int = 0,
                    waves_per_block: int = 0) -> None:
     _check(lib().bml_set_tuning(handle, tile_rows, t_phases, waves_per_block))
 
@@ -193,3 +220,139 @@ def bml_pack(n: int, d_cells, d_planes, stream=None) -> None:
 
 def bml_unpack(n: int, d_planes, d_cells, stream=None) -> None:
     _check(lib().bml_unpack(n, _ptr(d_planes), _ptr(d_cells), _stream_ptr(stream)))
+
+
+# --- batched sweeps -------------------------------------------------------
+
+def bml_batch_arena_bytes(n_list, layout: int) -> int:
+    n = np.ascontiguousarray(n_list, dtype=np.int32)
+    out = _sz()
+    _check(lib().bml_batch_arena_bytes(len(n), n.ctypes.data, layout, ctypes.byref(out)))
+    return int(out.value)
+
+
+def bml_batch_init(n_list, rho_list, seed_list, layout: int, d_arena, arena_bytes: int,
+                   d_trace, trace_steps: int, stream) -> int:
+    n = np.ascontiguousarray(n_list, dtype=np.int32)
+    rho = np.ascontiguousarray(rho_list, dtype=np.float64)
+    seed = np.ascontiguousarray([int(s) & (2**64 - 1) for s in seed_list], dtype=np.uint64)
+    if not (len(n) == len(rho) == len(seed)):
+        raise BmlError(BML_EINVAL, "n, rho and seed must have the same length")
+    h = _vp()
+    _check(lib().bml_batch_init(ctypes.byref(h), len(n), n.ctypes.data, rho.ctypes.data,
+                                seed.ctypes.data, layout, _ptr(d_arena), arena_bytes,
+                                _ptr(d_trace), trace_steps, _stream_ptr(stream)))
+    return int(h.value)
+
+
+def bml_batch_set_tuning(handle: int, strip_rows: int = 0, t_phases: int = 0,
+                         waves_per_block: int = 0) -> None:
+    _check(lib().bml_batch_set_tuning(handle, strip_rows, t_phases, waves_per_block))
+
+
+def bml_batch_set_active(handle: int, active=None) -> None:
+    a = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    _check(lib().bml_batch_set_active(handle, None if a is None else a.ctypes.data))
+
+
+def bml_batch_run(handle: int, n_steps: int) -> None:
+    _check(lib().bml_batch_run(handle, n_steps))
+
+
+def bml_batch_capture(handle: int, n_steps: int) -> None:
+    _check(lib().bml_batch_capture(handle, n_steps))
+
+
+def bml_batch_replay(handle: int) -> None:
+    _check(lib().bml_batch_replay(handle))
+
+
+def bml_batch_step_count(handle: int) -> int:
+    return int(lib().bml_batch_step_count(handle))
+
+
+def bml_batch_lattice_steps(handle: int, idx: int) -> int:
+    out = _i64()
+    _check(lib().bml_batch_lattice_steps(handle, idx, ctypes.byref(out)))
+    return int(out.value)
+
+
+def bml_batch_initial_counts(handle: int, idx: int) -> tuple[int, int]:
+    a, b = _u64(), _u64()
+    _check(lib().bml_batch_initial_counts(handle, idx, ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def bml_batch_get_cells(handle: int, idx: int, n: int) -> np.ndarray:
+    out = np.empty((n, n), dtype=np.uint8)
+    _check(lib().bml_batch_get_cells(handle, idx, out.ctypes.data))
+    return out
+
+
+def bml_batch_check(handle: int) -> None:
+    _check(lib().bml_batch_check(handle))
+
+
+def bml_batch_free(handle: int) -> None:
+    lib().bml_batch_free(handle)
+
+
+# --- learned early exit -------------------------------------------------------
+
+BML_MLP_INPUTS = 65
+BML_MLP_HIDDEN = 64
+BML_MLP_PARAMS = 8449
+BML_MLP_MAX_BATCH = 256
+
+
+def bml_features(d_trace, trace_steps: int, count: int, d_cars, d_rho, window: int, d_out,
+                 stream=None) -> None:
+    _check(lib().bml_features(_ptr(d_trace), trace_steps, count, _ptr(d_cars), _ptr(d_rho),
+                              window, _ptr(d_out), _stream_ptr(stream)))
+
+
+def bml_trace_frozen(d_trace, trace_steps: int, count: int, first_step: int, end_step: int,
+                     d_frozen, stream=None) -> None:
+    _check(lib().bml_trace_frozen(_ptr(d_trace), trace_steps, count, first_step, end_step,
+                                  _ptr(d_frozen), _stream_ptr(stream)))
+
+
+def bml_trace_mobility(d_trace, trace_steps: int, count: int, d_cars, first_step: int,
+                       end_step: int, d_mean, stream=None) -> None:
+    _check(lib().bml_trace_mobility(_ptr(d_trace), trace_steps, count, _ptr(d_cars),
+                                    first_step, end_step, _ptr(d_mean), _stream_ptr(stream)))
+
+
+def bml_feature_stats(d_x, n: int, d_mean, d_std, stream=None) -> None:
+    _check(lib().bml_feature_stats(_ptr(d_x), n, _ptr(d_mean), _ptr(d_std), _stream_ptr(stream)))
+
+
+def bml_standardize(d_x, n: int, d_mean, d_std, stream=None) -> None:
+    _check(lib().bml_standardize(_ptr(d_x), n, _ptr(d_mean), _ptr(d_std), _stream_ptr(stream)))
+
+
+def bml_mlp_scratch_bytes() -> int:
+    return int(lib().bml_mlp_scratch_bytes())
+
+
+def bml_mlp_grad(d_params, d_x, d_y, n: int, d_scratch, d_grad, d_loss, stream=None) -> None:
+    _check(lib().bml_mlp_grad(_ptr(d_params), _ptr(d_x), _ptr(d_y), n, _ptr(d_scratch),
+                              _ptr(d_grad), _ptr(d_loss), _stream_ptr(stream)))
+
+
+def bml_mlp_train_step(d_params, d_m, d_v, d_grad, t: int, d_x, d_y, d_idx, n: int, lr: float,
+                       beta1: float, beta2: float, eps: float, d_scratch, d_loss,
+                       stream=None) -> None:
+    _check(lib().bml_mlp_train_step(_ptr(d_params), _ptr(d_m), _ptr(d_v), _ptr(d_grad), t,
+                                    _ptr(d_x), _ptr(d_y), _ptr(d_idx), n, lr, beta1, beta2, eps,
+                                    _ptr(d_scratch), _ptr(d_loss), _stream_ptr(stream)))
+
+
+def bml_mlp_forward(d_params, d_x, n: int, d_logits, stream=None) -> None:
+    _check(lib().bml_mlp_forward(_ptr(d_params), _ptr(d_x), n, _ptr(d_logits),
+                                 _stream_ptr(stream)))
+
+
+def bml_mlp_infer_bf16(d_params, d_x, n: int, d_logits, stream=None) -> None:
+    _check(lib().bml_mlp_infer_bf16(_ptr(d_params), _ptr(d_x), n, _ptr(d_logits),
+                                    _stream_ptr(stream)))

@@ -11,8 +11,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbml.so")
-SOURCES = ["bml_lattice.hip", "bml_pass_u8_r32.hip", "bml_pass_u8_r64.hip",
-           "bml_pass_bp_r32.hip", "bml_pass_bp_r64.hip"]
+SOURCES = ["bml_lattice.hip", "bml_pass_u8_lo.hip", "bml_pass_u8_hi.hip",
+           "bml_pass_bp_lo.hip", "bml_pass_bp_hi.hip", "bml_batch.hip",
+           "bml_batch_u8.hip", "bml_batch_bp.hip", "bml_mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",

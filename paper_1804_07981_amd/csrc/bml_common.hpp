@@ -34,6 +34,18 @@ int device_info(DeviceInfo *out);
 
 inline bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
+// Helper launches shared by the single-lattice and batch code (defined in
+// bml_lattice.hip).  All are asynchronous on `stream`.
+// Random initial state of an n x n lattice (layout 0 = bytes, 1 = planes).
+int launch_init(void *state, int32_t n, int32_t layout, uint64_t seed, double rho,
+                hipStream_t stream);
+// counts[0] = LR cars, counts[1] = TB cars of the state (clears them first).
+int launch_count(const void *state, int32_t n, int32_t layout, unsigned long long *counts,
+                 hipStream_t stream);
+int launch_pack(const uint8_t *cells, uint32_t *planes, int32_t n, hipStream_t stream);
+int launch_unpack(const uint32_t *planes, uint8_t *cells, int32_t n, hipStream_t stream);
+int launch_zero(uint32_t *p, int64_t words, hipStream_t stream);
+
 inline bool valid_n(int32_t n) { return n >= 32 && n <= 65504 && n % 32 == 0; }
 
 } // namespace bml

@@ -181,9 +181,10 @@ __global__ __launch_bounds__(256) void count_kernel(const void *state, int64_t t
         atomicAdd(&out[threadIdx.x], (unsigned long long)s[threadIdx.x]);
 }
 
-__global__ void zero_words_kernel(uint32_t *p, int count)
+__global__ void zero_words_kernel(uint32_t *p, int64_t count)
 {
-    for (int i = threadIdx.x; i < count; i += blockDim.x)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
 }
 
@@ -191,17 +192,14 @@ __global__ void zero_words_kernel(uint32_t *p, int count)
 // Kernel table
 // ============================================================================
 
-constexpr int N_ROWS_OPT = 2;
-constexpr int ROWS_OPT[N_ROWS_OPT] = {32, 64};   // output rows per wavefront tile
-
 struct KernelTable {
-    PassFn fn[2][N_ROWS_OPT][MAX_K + 1] = {};
+    PassFn fn[2][MAX_K + 1] = {};
     KernelTable()
     {
-        pass_table_u8_r32(fn[IO_U8][0]);
-        pass_table_u8_r64(fn[IO_U8][1]);
-        pass_table_bp_r32(fn[IO_BP][0]);
-        pass_table_bp_r64(fn[IO_BP][1]);
+        pass_table_u8_lo(fn[IO_U8]);
+        pass_table_u8_hi(fn[IO_U8]);
+        pass_table_bp_lo(fn[IO_BP]);
+        pass_table_bp_hi(fn[IO_BP]);
     }
 };
 
@@ -211,31 +209,23 @@ static const KernelTable &kernels()
     return t;
 }
 
-static int rows_index(int VR)
-{
-    for (int i = 0; i < N_ROWS_OPT; ++i)
-        if (ROWS_OPT[i] == VR)
-            return i;
-    return -1;
-}
-
 // Resident blocks per CU of a pass kernel at `threads` threads per block.
-static int resident_blocks(int io, int ri, int k, int threads, int *out)
+static int resident_blocks(int io, int k, int threads, int *out)
 {
     static std::mutex mu;
-    static int cache[8][2][N_ROWS_OPT][MAX_K + 1][3];   // [dev][io][ri][k][log2 wpb]
+    static int cache[8][2][MAX_K + 1][3];   // [dev][io][k][log2 wpb]
     int dev = 0;
     BML_HIP(hipGetDevice(&dev));
     int wl = threads == 64 ? 0 : threads == 128 ? 1 : 2;
     std::lock_guard<std::mutex> lock(mu);
-    int *c = dev < 8 ? &cache[dev][io][ri][k][wl] : nullptr;
+    int *c = dev < 8 ? &cache[dev][io][k][wl] : nullptr;
     if (c && *c > 0) {
         *out = *c;
         return BML_OK;
     }
     int nb = 0;
     BML_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(kernels().fn[io][ri][k]), threads, 0));
+        &nb, reinterpret_cast<const void *>(kernels().fn[io][k]), threads, 0));
     if (nb < 1)
         nb = 1;
     if (c)
@@ -250,6 +240,86 @@ static int launch_1d_grid(int64_t work, int threads, unsigned *grid)
     if (g > 0x7fffffff)
         return fail(BML_EINVAL, "launch too large");
     *grid = (unsigned)std::max<int64_t>(g, 1);
+    return BML_OK;
+}
+
+int launch_zero(uint32_t *p, int64_t words, hipStream_t stream)
+{
+    if (words <= 0)
+        return BML_OK;
+    const unsigned grid = (unsigned)std::min<int64_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid), dim3(256), 0, stream, p, words);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int launch_init(void *state, int32_t n, int32_t layout, uint64_t seed, double rho,
+                hipStream_t stream)
+{
+    const int32_t words = n / 32;
+    unsigned grid;
+    int rc = launch_1d_grid((int64_t)n * words, 256, &grid);
+    if (rc)
+        return rc;
+    // Thresholds on the 53-bit uniform, truncated from IEEE double.
+    const uint64_t thr_lr = (uint64_t)ldexp(rho * 0.5, 53);
+    const uint64_t thr_tb = (uint64_t)ldexp(rho, 53);
+    if (layout == BML_LAYOUT_U8)
+        hipLaunchKernelGGL(init_kernel<IO_U8>, dim3(grid), dim3(256), 0, stream, state, n, words,
+                           seed, thr_lr, thr_tb);
+    else
+        hipLaunchKernelGGL(init_kernel<IO_BP>, dim3(grid), dim3(256), 0, stream, state, n, words,
+                           seed, thr_lr, thr_tb);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int launch_count(const void *state, int32_t n, int32_t layout, unsigned long long *counts,
+                 hipStream_t stream)
+{
+    int rc = launch_zero((uint32_t *)counts, 4, stream);
+    if (rc)
+        return rc;
+    DeviceInfo dev;
+    if ((rc = device_info(&dev)))
+        return rc;
+    const int64_t total_words = (int64_t)n * (n / 32);
+    const unsigned grid =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>((total_words + 255) / 256,
+                                                         (int64_t)dev.cu_count * 8));
+    if (layout == BML_LAYOUT_U8)
+        hipLaunchKernelGGL(count_kernel<IO_U8>, dim3(grid), dim3(256), 0, stream, state,
+                           total_words, counts);
+    else
+        hipLaunchKernelGGL(count_kernel<IO_BP>, dim3(grid), dim3(256), 0, stream, state,
+                           total_words, counts);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int launch_pack(const uint8_t *cells, uint32_t *planes, int32_t n, hipStream_t stream)
+{
+    const int64_t total_words = (int64_t)n * (n / 32);
+    unsigned grid;
+    int rc = launch_1d_grid(total_words, 256, &grid);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, stream, cells, planes,
+                       total_words);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int launch_unpack(const uint32_t *planes, uint8_t *cells, int32_t n, hipStream_t stream)
+{
+    const int64_t total_words = (int64_t)n * (n / 32);
+    unsigned grid;
+    int rc = launch_1d_grid(total_words, 256, &grid);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid), dim3(256), 0, stream, planes, cells,
+                       total_words);
+    BML_HIP(hipGetLastError());
     return BML_OK;
 }
 
@@ -270,7 +340,8 @@ struct bml_lattice {
     hipStream_t stream = nullptr;
     int64_t steps_done = 0;
     uint64_t n_lr0 = 0, n_tb0 = 0;
-    int32_t tile_rows = 64, t_phases = 8, wpb = 4;   // tile_rows: output rows per tile
+    int32_t tile_rows = 0, t_phases = 8, wpb = 4;   // tile_rows: strip rows (0 = auto)
+    int32_t last_strip_rows = 0;                    // strip height of the last pass
     DeviceInfo dev;
     unsigned long long *d_counts = nullptr;   // library scratch: 2 counters
     PassScratch *d_scratch = nullptr;         // library scratch: stats reduction
@@ -289,18 +360,9 @@ static bool live(const bml_lattice *L)
 
 static int count_cars(bml_lattice *L, const void *state, uint64_t *n_lr, uint64_t *n_tb)
 {
-    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, L->stream,
-                       (uint32_t *)L->d_counts, 4);
-    const int64_t total_words = (int64_t)L->n * (L->n / 32);
-    const unsigned grid = (unsigned)std::min<int64_t>((total_words + 255) / 256,
-                                                      (int64_t)L->dev.cu_count * 8);
-    if (L->layout == BML_LAYOUT_U8)
-        hipLaunchKernelGGL(count_kernel<IO_U8>, dim3(grid), dim3(256), 0, L->stream, state,
-                           total_words, L->d_counts);
-    else
-        hipLaunchKernelGGL(count_kernel<IO_BP>, dim3(grid), dim3(256), 0, L->stream, state,
-                           total_words, L->d_counts);
-    BML_HIP(hipGetLastError());
+    int rc = launch_count(state, L->n, L->layout, L->d_counts, L->stream);
+    if (rc)
+        return rc;
     unsigned long long h[2] = {0, 0};
     BML_HIP(hipMemcpyAsync(h, L->d_counts, sizeof h, hipMemcpyDeviceToHost, L->stream));
     BML_HIP(hipStreamSynchronize(L->stream));
@@ -410,7 +472,7 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
     L->cap = stats_cap;
     L->stream = (hipStream_t)hip_stream;
     L->t_phases = layout == BML_LAYOUT_U8 ? 8 : 16;
-    L->tile_rows = 64;
+    L->tile_rows = 0;
     L->wpb = 4;
     auto cleanup = [&](int code) {
         if (L->d_counts)
@@ -430,25 +492,12 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
         L->d_scratch = nullptr;
         return cleanup(fail(BML_EDEVICE, "hipMalloc of stats scratch failed"));
     }
-    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, L->stream,
-                       (uint32_t *)L->d_scratch, (int)(sizeof(PassScratch) / 4));
-
-    const int32_t words = n / 32;
-    const int64_t total_words = (int64_t)n * words;
-    unsigned grid;
-    if ((rc = launch_1d_grid(total_words, 256, &grid)))
+    if ((rc = launch_zero((uint32_t *)L->d_scratch, sizeof(PassScratch) / 4, L->stream)))
         return cleanup(rc);
+
     if (!cells_host) {
-        const uint64_t thr_lr = (uint64_t)ldexp(rho * 0.5, 53);
-        const uint64_t thr_tb = (uint64_t)ldexp(rho, 53);
-        if (layout == BML_LAYOUT_U8)
-            hipLaunchKernelGGL(init_kernel<IO_U8>, dim3(grid), dim3(256), 0, L->stream,
-                               d_state_a, n, words, seed, thr_lr, thr_tb);
-        else
-            hipLaunchKernelGGL(init_kernel<IO_BP>, dim3(grid), dim3(256), 0, L->stream,
-                               d_state_a, n, words, seed, thr_lr, thr_tb);
-        if (hipGetLastError() != hipSuccess)
-            return cleanup(fail(BML_EDEVICE, "init kernel launch failed"));
+        if ((rc = launch_init(d_state_a, n, layout, seed, rho, L->stream)))
+            return cleanup(rc);
     } else if (layout == BML_LAYOUT_U8) {
         if (hipMemcpyAsync(d_state_a, cells_host, bytes, hipMemcpyHostToDevice, L->stream) !=
             hipSuccess)
@@ -460,12 +509,10 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
         if (hipMalloc(&tmp, (size_t)n * n) != hipSuccess)
             return cleanup(fail(BML_EDEVICE, "hipMalloc of the staging buffer failed"));
         bool ok = hipMemcpyAsync(tmp, cells_host, (size_t)n * n, hipMemcpyHostToDevice,
-                                 L->stream) == hipSuccess;
-        if (ok) {
-            hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, L->stream,
-                               (const uint8_t *)tmp, (uint32_t *)d_state_a, total_words);
-            ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(L->stream) == hipSuccess;
-        }
+                                 L->stream) == hipSuccess &&
+                  launch_pack((const uint8_t *)tmp, (uint32_t *)d_state_a, n, L->stream) ==
+                      BML_OK &&
+                  hipStreamSynchronize(L->stream) == hipSuccess;
         (void)hipFree(tmp);
         if (!ok)
             return cleanup(fail(BML_EDEVICE, "upload/pack of the initial cells failed"));
@@ -485,11 +532,11 @@ int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases, int32_t 
     clear_error();
     if (!live(L))
         return fail(BML_ESTATE, "invalid handle");
-    const int R = tile_rows ? tile_rows : L->tile_rows;
-    const int T = t_phases ? t_phases : L->t_phases;
-    const int W = waves_per_block ? waves_per_block : L->wpb;
-    if (rows_index(R) < 0)
-        return fail(BML_EINVAL, "tile_rows=%d must be 32 or 64", R);
+    const int R = tile_rows >= 0 ? tile_rows : L->tile_rows;
+    const int T = t_phases > 0 ? t_phases : L->t_phases;
+    const int W = waves_per_block > 0 ? waves_per_block : L->wpb;
+    if (R != 0 && (R < 8 || R > 65504))
+        return fail(BML_EINVAL, "tile_rows=%d must be 0 (auto) or in [8, 65504]", R);
     if (T < 2 || T > 2 * MAX_K || T % 2)
         return fail(BML_EINVAL, "t_phases=%d must be even in [2, %d]", T, 2 * MAX_K);
     if (W != 1 && W != 2 && W != 4)
@@ -515,19 +562,10 @@ int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
     return BML_OK;
 }
 
-// Output rows per tile actually used: the tuned value if it divides N,
-// else 32 (every valid N is a multiple of 32).
-static int effective_rows(const bml_lattice *L)
-{
-    return L->n % L->tile_rows == 0 ? L->tile_rows : 32;
-}
-
 // One kernel pass of k steps starting at global step `step0`.
 static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
 {
     const int io = L->layout == BML_LAYOUT_U8 ? IO_U8 : IO_BP;
-    const int VR = effective_rows(L);
-    const int ri = rows_index(VR);
     PassArgs a;
     a.src = L->buf[L->cur];
     a.dst = L->buf[L->cur ^ 1];
@@ -536,7 +574,6 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
     a.n = L->n;
     a.words = L->n / 32;
     a.tiles_x = (a.words + TILE_WORDS - 1) / TILE_WORDS;
-    a.n_tiles = a.tiles_x * (L->n / VR);
     a.rec_mask = 0;
     for (int j = 0; j < MAX_K; ++j) {
         a.slot[j] = 0;
@@ -547,12 +584,26 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
     }
     const int threads = 64 * L->wpb;
     int per_cu = 1;
-    int rc = resident_blocks(io, ri, k, threads, &per_cu);
+    int rc = resident_blocks(io, k, threads, &per_cu);
     if (rc)
         return rc;
     const int64_t max_blocks = (int64_t)per_cu * L->dev.cu_count;
+    // Strip height: the tuned value, or by default enough strips for about
+    // two rounds of resident waves, but at least 4K rows so that the 2K halo
+    // rows of a strip stay a minor overhead.
+    int H = L->tile_rows;
+    if (H <= 0) {
+        const int64_t target_items = 2 * max_blocks * L->wpb;
+        H = (int)std::min<int64_t>(L->n, ((int64_t)L->n * a.tiles_x + target_items - 1) /
+                                             target_items);
+        H = std::max(H, std::min(4 * k, L->n));
+        H = (H + 7) / 8 * 8;
+    }
+    H = std::min(H, L->n);
+    a.strip_rows = H;
+    a.n_tiles = a.tiles_x * ((L->n + H - 1) / H);
     const int64_t tile_blocks = (a.n_tiles + L->wpb - 1) / L->wpb;
-    // Even out the rounds: every wavefront gets ceil(tiles / waves) tiles.
+    // Even out the rounds: every wavefront gets ceil(items / waves) items.
     const int64_t rounds = (tile_blocks + max_blocks - 1) / max_blocks;
     int64_t grid = (tile_blocks + rounds - 1) / rounds;
     if (grid >= 8) {
@@ -561,10 +612,11 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
             grid = max_blocks / 8 * 8;
     }
     a.xcd_split = (grid >= 8 && grid % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(kernels().fn[io][ri][k], dim3((unsigned)grid), dim3(threads), 0,
-                       L->stream, a);
+    hipLaunchKernelGGL(kernels().fn[io][k], dim3((unsigned)grid), dim3(threads), 0, L->stream,
+                       a);
     BML_HIP(hipGetLastError());
     L->cur ^= 1;
+    L->last_strip_rows = H;
     return BML_OK;
 }
 

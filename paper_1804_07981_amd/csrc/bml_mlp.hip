@@ -1,0 +1,542 @@
+// bml_mlp.hip -- the learned early exit: trajectory features and a small
+// MLP (65 -> 64 -> 64 -> 1, ReLU, logit) trained in fp32 and run in BF16,
+// all in hand-written HIP kernels.
+//
+// The physics it predicts (Marzolla, arXiv:1804.07981, Sec. 2): below a
+// critical density the lattice self-organises into free flow (every car
+// moves), above it a global jam forms and motion stops; near the critical
+// point both outcomes can occur.  The network reads the early trajectory of
+// the mobile fraction and the density and predicts the final phase.
+//
+// Parameter vector (fp32, BML_MLP_PARAMS = 8449 entries, row-major out x in):
+//   W1[64][65] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "bml.h"
+#include "bml_common.hpp"
+
+namespace bml {
+
+constexpr int NI = BML_MLP_INPUTS;   // 65
+constexpr int NH = BML_MLP_HIDDEN;   // 64
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + NH * NI;
+constexpr int OFF_W2 = OFF_B1 + NH;
+constexpr int OFF_B2 = OFF_W2 + NH * NH;
+constexpr int OFF_W3 = OFF_B2 + NH;
+constexpr int OFF_B3 = OFF_W3 + NH;
+constexpr int NP = OFF_B3 + 1;
+static_assert(NP == BML_MLP_PARAMS, "parameter layout");
+constexpr int MAX_BATCH = 256;
+
+// ---------------------------------------------------------------------------
+// Features: f_m = sum over steps 8m+1 .. 8m+8 of (LR moved + TB moved),
+// divided by 8 * (number of cars), m = 0..63 (the mobile fraction averaged
+// over windows of 8 steps), computed in double and rounded to float; f_64 =
+// rho.  A lattice without cars has mobile fraction 1 by definition.  One
+// thread per (lattice, feature).
+// ---------------------------------------------------------------------------
+__global__ void features_kernel(const uint32_t *trace, int64_t trace_steps, int32_t count,
+                                const uint64_t *cars, const double *rho, int32_t window,
+                                float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)count * NI)
+        return;
+    const int64_t b = i / NI;
+    const int m = (int)(i - b * NI);
+    if (m == NI - 1) {
+        out[i] = (float)rho[b];
+        return;
+    }
+    const uint64_t c = cars[b];
+    if (c == 0) {
+        out[i] = 1.0f;
+        return;
+    }
+    uint64_t moved = 0;
+    for (int s = m * window; s < (m + 1) * window; ++s) {
+        const uint32_t *p = trace + (b * trace_steps + s) * 2;
+        moved += (uint64_t)p[0] + p[1];
+    }
+    out[i] = (float)((double)moved / ((double)window * (double)c));
+}
+
+// frozen[b] = 1 if some step s in [s0, s1) of lattice b moved no car.  A
+// step without moves leaves the lattice unchanged, so it stays frozen for
+// good (the exact stop rule).  One wave per lattice.
+__global__ __launch_bounds__(256) void trace_frozen_kernel(const uint32_t *trace,
+                                                           int64_t trace_steps, int32_t count,
+                                                           int64_t s0, int64_t s1,
+                                                           uint8_t *frozen)
+{
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x / 64);
+    if (b >= count)
+        return;
+    const int lane = threadIdx.x & 63;
+    int any = 0;
+    for (int64_t s = s0 + lane; s < s1; s += 64) {
+        const uint32_t *p = trace + (b * trace_steps + s) * 2;
+        any |= (p[0] + p[1]) == 0u;
+    }
+    const unsigned long long m = __ballot(any);
+    if (lane == 0)
+        frozen[b] = m ? 1 : 0;
+}
+
+// mean[b] = mean over steps [s0, s1) of (LR moved + TB moved) / cars[b]
+// (1 for a lattice without cars), in double.  One wave per lattice.
+__global__ __launch_bounds__(256) void trace_mobility_kernel(const uint32_t *trace,
+                                                             int64_t trace_steps, int32_t count,
+                                                             const uint64_t *cars, int64_t s0,
+                                                             int64_t s1, double *mean)
+{
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x / 64);
+    if (b >= count)
+        return;
+    const int lane = threadIdx.x & 63;
+    unsigned long long moved = 0;
+    for (int64_t s = s0 + lane; s < s1; s += 64) {
+        const uint32_t *p = trace + (b * trace_steps + s) * 2;
+        moved += (unsigned long long)p[0] + p[1];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        moved += __shfl_xor(moved, off, 64);
+    if (lane == 0)
+        mean[b] = cars[b] ? (double)moved / ((double)(s1 - s0) * (double)cars[b]) : 1.0;
+}
+
+// Column means and standard deviations (population, double accumulation) of
+// x[n][NI]; one block per column.
+__global__ __launch_bounds__(256) void feature_stats_kernel(const float *x, int32_t n,
+                                                           float *mean, float *stdev)
+{
+    __shared__ double s1[256], s2[256];
+    const int col = blockIdx.x;
+    double a = 0, q = 0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const double v = x[(int64_t)r * NI + col];
+        a += v;
+        q += v * v;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = q;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s1[threadIdx.x] += s1[threadIdx.x + o];
+            s2[threadIdx.x] += s2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = s1[0] / n;
+        const double var = fmax(s2[0] / n - m * m, 0.0);
+        mean[col] = (float)m;
+        // A constant column is left unscaled.
+        stdev[col] = var > 1e-24 ? (float)sqrt(var) : 1.0f;
+    }
+}
+
+// x[i][c] = (x[i][c] - mean[c]) / stdev[c] in float.
+__global__ void standardize_kernel(float *x, int32_t n, const float *mean, const float *stdev)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * NI)
+        return;
+    const int c = (int)(i % NI);
+    x[i] = (x[i] - mean[c]) / stdev[c];
+}
+
+// ---------------------------------------------------------------------------
+// Training: one block of MAX_BATCH threads per minibatch.  The parameters sit
+// in LDS (33.8 KB); thread i runs sample i forward and back to its hidden
+// gradients, parks its activations in global scratch, and after a barrier
+// every thread reduces the per-sample products of its share of parameters.
+// ---------------------------------------------------------------------------
+struct SampleScratch {       // per sample, in global memory
+    float x[NI];
+    float h1[NH];
+    float d1[NH];            // dL/d(pre-activation of layer 1)
+    float h2[NH];
+    float d2[NH];            // dL/d(pre-activation of layer 2)
+    float dz;                // dL/dz
+};
+
+__device__ __forceinline__ float bce_with_logits(float z, float y)
+{
+    // max(z, 0) - z*y + log(1 + exp(-|z|)), stable for any z.
+    return fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
+}
+
+__device__ __forceinline__ float sigmoidf(float z)
+{
+    return z >= 0.0f ? 1.0f / (1.0f + expf(-z)) : expf(z) / (1.0f + expf(z));
+}
+
+constexpr int CHUNK = 32;    // samples staged in LDS at a time
+
+// Gradient of the mean BCE-with-logits loss over samples idx[0..n) (idx NULL
+// = 0..n-1) into grad[NP]; loss into *loss.  n <= MAX_BATCH.
+__device__ void mlp_grad_block(const float *params, const float *x, const float *y,
+                               const int32_t *idx, int n, SampleScratch *scr, float *grad,
+                               float *loss)
+{
+    __shared__ float P[NP];
+    __shared__ float red[MAX_BATCH];
+    __shared__ float cx[CHUNK][NI], ch1[CHUNK][NH], cd1[CHUNK][NH], ch2[CHUNK][NH],
+        cd2[CHUNK][NH], cdz[CHUNK];
+    for (int p = threadIdx.x; p < NP; p += blockDim.x)
+        P[p] = params[p];
+    __syncthreads();
+    const int i = threadIdx.x;
+    float li = 0.0f;
+    if (i < n) {
+        const int64_t row = idx ? idx[i] : i;
+        const float *xi = x + row * NI;
+        SampleScratch &s = scr[i];
+        float h[NH];
+        for (int j = 0; j < NH; ++j) {
+            float a = P[OFF_B1 + j];
+            for (int c = 0; c < NI; ++c)
+                a = fmaf(P[OFF_W1 + j * NI + c], xi[c], a);
+            h[j] = fmaxf(a, 0.0f);
+            s.h1[j] = h[j];
+        }
+        for (int c = 0; c < NI; ++c)
+            s.x[c] = xi[c];
+        float g[NH];
+        for (int j = 0; j < NH; ++j) {
+            float a = P[OFF_B2 + j];
+            for (int c = 0; c < NH; ++c)
+                a = fmaf(P[OFF_W2 + j * NH + c], h[c], a);
+            g[j] = fmaxf(a, 0.0f);
+        }
+        float z = P[OFF_B3];
+        for (int c = 0; c < NH; ++c)
+            z = fmaf(P[OFF_W3 + c], g[c], z);
+        const float yi = y[row];
+        li = bce_with_logits(z, yi);
+        const float dz = (sigmoidf(z) - yi) / (float)n;
+        s.dz = dz;
+        for (int j = 0; j < NH; ++j) {
+            s.h2[j] = g[j];
+            g[j] = g[j] > 0.0f ? dz * P[OFF_W3 + j] : 0.0f;   // now dL/d(pre-act 2)
+            s.d2[j] = g[j];
+        }
+        for (int c = 0; c < NH; ++c) {
+            float a = 0.0f;
+            for (int j = 0; j < NH; ++j)
+                a = fmaf(P[OFF_W2 + j * NH + c], g[j], a);
+            s.d1[c] = h[c] > 0.0f ? a : 0.0f;
+        }
+    }
+    red[threadIdx.x] = li;
+    __syncthreads();
+    for (int o = MAX_BATCH / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss)
+        *loss = red[0] / (float)n;
+
+    // Parameter gradients: sums over the samples, CHUNK samples at a time
+    // staged in LDS; thread t owns parameters t, t + 256, ...
+    constexpr int PER = (NP + MAX_BATCH - 1) / MAX_BATCH;
+    float acc[PER];
+    for (int q = 0; q < PER; ++q)
+        acc[q] = 0.0f;
+    for (int k0 = 0; k0 < n; k0 += CHUNK) {
+        const int kn = min(CHUNK, n - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < kn * NI; e += blockDim.x)
+            cx[e / NI][e % NI] = scr[k0 + e / NI].x[e % NI];
+        for (int e = threadIdx.x; e < kn * NH; e += blockDim.x) {
+            const int k = e / NH, j = e % NH;
+            ch1[k][j] = scr[k0 + k].h1[j];
+            cd1[k][j] = scr[k0 + k].d1[j];
+            ch2[k][j] = scr[k0 + k].h2[j];
+            cd2[k][j] = scr[k0 + k].d2[j];
+        }
+        for (int e = threadIdx.x; e < kn; e += blockDim.x)
+            cdz[e] = scr[k0 + e].dz;
+        __syncthreads();
+        for (int q = 0; q < PER; ++q) {
+            const int p = threadIdx.x + q * MAX_BATCH;
+            if (p >= NP)
+                break;
+            float g = acc[q];
+            if (p < OFF_B1) {
+                const int j = p / NI, c = p - j * NI;
+                for (int k = 0; k < kn; ++k)
+                    g = fmaf(cd1[k][j], cx[k][c], g);
+            } else if (p < OFF_W2) {
+                const int j = p - OFF_B1;
+                for (int k = 0; k < kn; ++k)
+                    g += cd1[k][j];
+            } else if (p < OFF_B2) {
+                const int j = (p - OFF_W2) / NH, c = (p - OFF_W2) - j * NH;
+                for (int k = 0; k < kn; ++k)
+                    g = fmaf(cd2[k][j], ch1[k][c], g);
+            } else if (p < OFF_W3) {
+                const int j = p - OFF_B2;
+                for (int k = 0; k < kn; ++k)
+                    g += cd2[k][j];
+            } else if (p < OFF_B3) {
+                const int c = p - OFF_W3;
+                for (int k = 0; k < kn; ++k)
+                    g = fmaf(cdz[k], ch2[k][c], g);
+            } else {
+                for (int k = 0; k < kn; ++k)
+                    g += cdz[k];
+            }
+            acc[q] = g;
+        }
+    }
+    for (int q = 0; q < PER; ++q) {
+        const int p = threadIdx.x + q * MAX_BATCH;
+        if (p < NP)
+            grad[p] = acc[q];
+    }
+}
+
+__global__ __launch_bounds__(MAX_BATCH) void mlp_grad_kernel(const float *params, const float *x,
+                                                             const float *y, int32_t n,
+                                                             SampleScratch *scr, float *grad,
+                                                             float *loss)
+{
+    mlp_grad_block(params, x, y, nullptr, n, scr, grad, loss);
+}
+
+// One Adam step (Kingma & Ba): gradient of the minibatch idx[0..n), then
+// m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, and
+// theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+__global__ __launch_bounds__(MAX_BATCH) void mlp_train_kernel(
+    float *params, float *m, float *v, float *grad, int64_t t, const float *x, const float *y,
+    const int32_t *idx, int32_t n, float lr, float beta1, float beta2, float eps,
+    SampleScratch *scr, float *loss)
+{
+    mlp_grad_block(params, x, y, idx, n, scr, grad, loss);
+    __syncthreads();
+    const float c1 = 1.0f - powf(beta1, (float)t);
+    const float c2 = 1.0f - powf(beta2, (float)t);
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+        const float g = grad[p];
+        const float mp = beta1 * m[p] + (1.0f - beta1) * g;
+        const float vp = beta2 * v[p] + (1.0f - beta2) * g * g;
+        m[p] = mp;
+        v[p] = vp;
+        params[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inference: one thread per sample, parameters in LDS.  fp32 version and a
+// BF16 version in which the weights and each layer's input are rounded to
+// bfloat16 (round to nearest even) and products are accumulated in fp32.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u)       // inf / nan pass through
+        return __uint_as_float(u & 0xffff0000u);
+    u += 0x7fffu + ((u >> 16) & 1u);             // round to nearest, ties to even
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const float *params, const float *x,
+                                                        int32_t n, float *logits)
+{
+    __shared__ float P[NP];
+    for (int p = threadIdx.x; p < NP; p += blockDim.x)
+        P[p] = BF16 && (p < OFF_B1 || (p >= OFF_W2 && p < OFF_B2) || (p >= OFF_W3 && p < OFF_B3))
+                   ? to_bf16(params[p])
+                   : params[p];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    float xi[NI];
+    for (int c = 0; c < NI; ++c)
+        xi[c] = BF16 ? to_bf16(x[i * NI + c]) : x[i * NI + c];
+    float h1[NH];
+    for (int j = 0; j < NH; ++j) {
+        float a = P[OFF_B1 + j];
+        for (int c = 0; c < NI; ++c)
+            a = fmaf(P[OFF_W1 + j * NI + c], xi[c], a);
+        a = fmaxf(a, 0.0f);
+        h1[j] = BF16 ? to_bf16(a) : a;
+    }
+    float h2[NH];
+    for (int j = 0; j < NH; ++j) {
+        float a = P[OFF_B2 + j];
+        for (int c = 0; c < NH; ++c)
+            a = fmaf(P[OFF_W2 + j * NH + c], h1[c], a);
+        a = fmaxf(a, 0.0f);
+        h2[j] = BF16 ? to_bf16(a) : a;
+    }
+    float z = P[OFF_B3];
+    for (int c = 0; c < NH; ++c)
+        z = fmaf(P[OFF_W3 + c], h2[c], z);
+    logits[i] = z;
+}
+
+} // namespace bml
+
+using namespace bml;
+
+static int grid_for(int64_t work, unsigned *g)
+{
+    const int64_t b = (work + 255) / 256;
+    if (b > 0x7fffffff)
+        return fail(BML_EINVAL, "launch too large");
+    *g = (unsigned)(b > 0 ? b : 1);
+    return BML_OK;
+}
+
+extern "C" {
+
+int bml_features(const uint32_t *d_trace, int64_t trace_steps, int32_t count,
+                 const uint64_t *d_cars, const double *d_rho, int32_t window,
+                 float *d_out, void *hip_stream)
+{
+    clear_error();
+    if (!d_trace || !d_cars || !d_rho || !d_out || count < 1 || window < 1 ||
+        (int64_t)window * (NI - 1) > trace_steps)
+        return fail(BML_EINVAL, "bml_features: bad arguments (64 windows must fit the trace)");
+    unsigned g;
+    int rc = grid_for((int64_t)count * NI, &g);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(features_kernel, dim3(g), dim3(256), 0, (hipStream_t)hip_stream, d_trace,
+                       trace_steps, count, d_cars, d_rho, window, d_out);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_trace_frozen(const uint32_t *d_trace, int64_t trace_steps, int32_t count,
+                     int64_t first_step, int64_t end_step, uint8_t *d_frozen, void *hip_stream)
+{
+    clear_error();
+    if (!d_trace || !d_frozen || count < 1 || first_step < 0 || end_step < first_step ||
+        end_step > trace_steps)
+        return fail(BML_EINVAL, "bml_trace_frozen: bad arguments");
+    const unsigned g = (unsigned)((count + 3) / 4);
+    hipLaunchKernelGGL(trace_frozen_kernel, dim3(g), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_trace, trace_steps, count, first_step, end_step, d_frozen);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_trace_mobility(const uint32_t *d_trace, int64_t trace_steps, int32_t count,
+                       const uint64_t *d_cars, int64_t first_step, int64_t end_step,
+                       double *d_mean, void *hip_stream)
+{
+    clear_error();
+    if (!d_trace || !d_cars || !d_mean || count < 1 || first_step < 0 ||
+        end_step <= first_step || end_step > trace_steps)
+        return fail(BML_EINVAL, "bml_trace_mobility: bad arguments");
+    const unsigned g = (unsigned)((count + 3) / 4);
+    hipLaunchKernelGGL(trace_mobility_kernel, dim3(g), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_trace, trace_steps, count, d_cars, first_step, end_step, d_mean);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_feature_stats(const float *d_x, int32_t n, float *d_mean, float *d_std,
+                      void *hip_stream)
+{
+    clear_error();
+    if (!d_x || !d_mean || !d_std || n < 1)
+        return fail(BML_EINVAL, "bml_feature_stats: bad arguments");
+    hipLaunchKernelGGL(feature_stats_kernel, dim3(NI), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_x, n, d_mean, d_std);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_standardize(float *d_x, int32_t n, const float *d_mean, const float *d_std,
+                    void *hip_stream)
+{
+    clear_error();
+    if (!d_x || !d_mean || !d_std || n < 1)
+        return fail(BML_EINVAL, "bml_standardize: bad arguments");
+    unsigned g;
+    int rc = grid_for((int64_t)n * NI, &g);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(standardize_kernel, dim3(g), dim3(256), 0, (hipStream_t)hip_stream, d_x,
+                       n, d_mean, d_std);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+size_t bml_mlp_scratch_bytes(void) { return sizeof(SampleScratch) * MAX_BATCH; }
+
+int bml_mlp_grad(const float *d_params, const float *d_x, const float *d_y, int32_t n,
+                 void *d_scratch, float *d_grad, float *d_loss, void *hip_stream)
+{
+    clear_error();
+    if (!d_params || !d_x || !d_y || !d_scratch || !d_grad || n < 1 || n > MAX_BATCH)
+        return fail(BML_EINVAL, "bml_mlp_grad: bad arguments (1 <= n <= %d)", MAX_BATCH);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(1), dim3(MAX_BATCH), 0, (hipStream_t)hip_stream,
+                       d_params, d_x, d_y, n, (SampleScratch *)d_scratch, d_grad, d_loss);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_mlp_train_step(float *d_params, float *d_m, float *d_v, float *d_grad, int64_t t,
+                       const float *d_x, const float *d_y, const int32_t *d_idx, int32_t n,
+                       float lr, float beta1, float beta2, float eps, void *d_scratch,
+                       float *d_loss, void *hip_stream)
+{
+    clear_error();
+    if (!d_params || !d_m || !d_v || !d_grad || !d_x || !d_y || !d_idx || !d_scratch ||
+        n < 1 || n > MAX_BATCH || t < 1)
+        return fail(BML_EINVAL, "bml_mlp_train_step: bad arguments (1 <= n <= %d, t >= 1)",
+                    MAX_BATCH);
+    hipLaunchKernelGGL(mlp_train_kernel, dim3(1), dim3(MAX_BATCH), 0, (hipStream_t)hip_stream,
+                       d_params, d_m, d_v, d_grad, t, d_x, d_y, d_idx, n, lr, beta1, beta2, eps,
+                       (SampleScratch *)d_scratch, d_loss);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_mlp_forward(const float *d_params, const float *d_x, int32_t n, float *d_logits,
+                    void *hip_stream)
+{
+    clear_error();
+    if (!d_params || !d_x || !d_logits || n < 1)
+        return fail(BML_EINVAL, "bml_mlp_forward: bad arguments");
+    unsigned g;
+    int rc = grid_for(n, &g);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(mlp_infer_kernel<false>, dim3(g), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_params, d_x, n, d_logits);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int bml_mlp_infer_bf16(const float *d_params, const float *d_x, int32_t n, float *d_logits,
+                       void *hip_stream)
+{
+    clear_error();
+    if (!d_params || !d_x || !d_logits || n < 1)
+        return fail(BML_EINVAL, "bml_mlp_infer_bf16: bad arguments");
+    unsigned g;
+    int rc = grid_for(n, &g);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(mlp_infer_kernel<true>, dim3(g), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_params, d_x, n, d_logits);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+} // extern "C"

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "bml_tile.hpp"
@@ -52,8 +53,9 @@ struct PassArgs {
     PassScratch *scratch;
     int32_t n;               // lattice side
     int32_t words;           // n / 32
-    int32_t tiles_x;         // tiles across a row
-    int32_t n_tiles;         // tiles_x * (n / VR)
+    int32_t tiles_x;         // column blocks across a row (62 words each)
+    int32_t n_tiles;         // tiles_x * ceil(n / strip_rows) work items
+    int32_t strip_rows;      // output rows per strip
     int32_t xcd_split;       // 1: gridDim.x % 8 == 0, give each XCD a band of tiles
     uint32_t rec_mask;       // bit k set: record the counts of step k of this pass
     int32_t slot[MAX_K];     // ring slot of step k
@@ -72,24 +74,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint3
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void wave_reduce_to_lds(uint32_t v, uint32_t *dst)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v += (uint32_t)__shfl_xor((int)v, off, 64);
-    if ((threadIdx.x & 63) == 0 && v)
-        atomicAdd(dst, v);
-}
-
-template <int IO, int K, int VR>
+template <int IO, int K>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
     static_assert(K >= 1 && K <= MAX_K, "bad steps per pass");
-    constexpr int R = VR + 2 * K;   // tile rows held in registers, halo included
-    constexpr int CH = 4;           // rows per load chunk (byte lattices)
-    constexpr int NCH = (R + CH - 1) / CH;
+    constexpr int D = 8;                      // rows prefetched ahead of the pipeline
+    constexpr int NW = IO == IO_U8 ? 8 : 2;   // dwords one lane loads per row
     const int lane = threadIdx.x & 63;
-    // Wave-uniform values must be visibly uniform so that tile and row
+    // Wave-uniform values must be visibly uniform so that strip and row
     // offsets live in SGPRs (buffer soffset) rather than per-lane VGPRs.
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
@@ -101,123 +93,164 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     } else {
         first = blockIdx.x * wpb + wave;
     }
-    const uint32_t row_bytes = IO == IO_U8 ? (uint32_t)a.n : (uint32_t)a.words * 4u;
-    const uint32_t plane_bytes = row_bytes * (uint32_t)a.n;   // lattice bytes (one plane)
+    const uint32_t n = (uint32_t)a.n;
+    const uint32_t row_bytes = IO == IO_U8 ? n : (uint32_t)a.words * 4u;
+    const uint32_t plane_bytes = row_bytes * n;   // lattice bytes (one plane)
     const uint32_t state_bytes = IO == IO_U8 ? plane_bytes : 2u * plane_bytes;
     const __amdgpu_buffer_rsrc_t src = make_rsrc(a.src, state_bytes);
     const __amdgpu_buffer_rsrc_t dst = make_rsrc(a.dst, state_bytes);
+    const int H = a.strip_rows;
 
-    uint32_t acc[K][4];
+    uint32_t wtot[K][4];   // wave totals (uniform)
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0;
+        wtot[k][0] = wtot[k][1] = wtot[k][2] = wtot[k][3] = 0;
 
-    for (int t = first; t < a.n_tiles; t += total_waves) {
-        const int ty = t / a.tiles_x;
-        const int tx = t - ty * a.tiles_x;
+    for (int item = first; item < a.n_tiles; item += total_waves) {
+        const int sy = item / a.tiles_x;
+        const int tx = item - sy * a.tiles_x;
+        const int row_a = sy * H;                       // first output row
+        const int h = min(H, a.n - row_a);              // output rows of this strip
+        const int total_in = h + 2 * K;                 // input rows streamed
+        const int total_it = h + 3 * K - 1;             // pipeline iterations
         const int w0 = tx * TILE_WORDS;
         const int vwords = min(TILE_WORDS, a.words - w0);
         const uint32_t word = (uint32_t)((w0 + lane - 1 + a.words) % a.words);
-        const uint32_t lane_ok = (lane >= 1 && lane <= vwords) ? 1u : 0u;
+        const bool lane_ok = lane >= 1 && lane <= vwords;
         const uint32_t voff = IO == IO_U8 ? word * 32u : word * 4u;
-        // Byte offset of tile row 0 (lattice row ty*VR - K, periodic); later
-        // rows follow with a wrap at the end of the lattice.
-        const uint32_t roff0 = (uint32_t)((ty * VR - K + a.n) % a.n) * row_bytes;
-        auto roff = [&](int r) {
-            // 64-bit: for N near 65504 a byte lattice is close to 2^32 bytes.
-            // A tile has at most VR + 2*MAX_K = 80 rows and N >= 32, so the
-            // row index wraps at most three times.
-            uint64_t o = (uint64_t)roff0 + (uint64_t)r * row_bytes;
-            static_assert(VR + 2 * MAX_K <= 3 * 32, "row wrap needs more steps");
-#pragma unroll
-            for (int w = 0; w < 3; ++w)
-                o = o >= plane_bytes ? o - plane_bytes : o;
-            return (uint32_t)o;
-        };
 
-        uint32_t L[R], T[R];
-        if (IO == IO_U8) {
-            u32x4 buf[2][CH][2];
-#pragma unroll
-            for (int i = 0; i < CH; ++i) {
-                buf[0][i][0] = __builtin_amdgcn_raw_buffer_load_b128(src, voff, roff(i), 0);
-                buf[0][i][1] = __builtin_amdgcn_raw_buffer_load_b128(src, voff + 16, roff(i), 0);
+        // Byte offset of input row t (lattice row row_a - K + t, periodic).
+        // `ld_off` runs D rows ahead of the pipeline; `st_off` is the next
+        // output row.  Each advance moves one row: one conditional wrap.
+        uint32_t ld_off = (uint32_t)((row_a - K + a.n) % a.n) * row_bytes;
+        uint32_t st_off = (uint32_t)row_a * row_bytes;
+        auto advance = [&](uint32_t o) {
+            const uint32_t x = o + row_bytes;
+            return x >= plane_bytes ? x - plane_bytes : x;
+        };
+        uint32_t ring[D][NW];
+        auto issue = [&](uint32_t (&dstw)[NW], uint32_t off) {
+            if constexpr (IO == IO_U8) {
+                const u32x4 u0 = __builtin_amdgcn_raw_buffer_load_b128(src, voff, off, 0);
+                const u32x4 u1 = __builtin_amdgcn_raw_buffer_load_b128(src, voff + 16, off, 0);
+                dstw[0] = u0.x; dstw[1] = u0.y; dstw[2] = u0.z; dstw[3] = u0.w;
+                dstw[4] = u1.x; dstw[5] = u1.y; dstw[6] = u1.z; dstw[7] = u1.w;
+            } else {
+                dstw[0] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off, 0);
+                dstw[1] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off + plane_bytes, 0);
             }
+        };
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                if (c + 1 < NCH) {
+        for (int d = 0; d < D; ++d) {
+            if (d < total_in) {
+                issue(ring[d], ld_off);
+                ld_off = advance(ld_off);
+            }
+        }
+
+        // Skewed pipeline: in iteration t, level k works on the row level
+        // k-1 produced in iteration t-1 (lattice row row_a - K + t - 2k after
+        // k steps) and emits it one row higher after k+1 steps.  Levels are
+        // visited from K-1 down to 0 so each reads its input before level
+        // k-1 overwrites it; within one iteration the levels are independent.
+        Level lv[K];
+        uint32_t bl[K], bt[K];   // bl/bt[k]: last output of level k
+        uint32_t acc[K][4];
 #pragma unroll
-                    for (int i = 0; i < CH; ++i) {
-                        const int r = (c + 1) * CH + i;
-                        if (r < R) {
-                            buf[(c + 1) & 1][i][0] =
-                                __builtin_amdgcn_raw_buffer_load_b128(src, voff, roff(r), 0);
-                            buf[(c + 1) & 1][i][1] =
-                                __builtin_amdgcn_raw_buffer_load_b128(src, voff + 16, roff(r), 0);
+        for (int k = 0; k < K; ++k) {
+            lv[k].L = lv[k].T = lv[k].mvp = 0;
+            bl[k] = bt[k] = 0;
+            acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0;
+        }
+
+        auto body = [&](int t0, auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int t = t0 + d;
+                if (!FULL && t >= total_it)
+                    break;
+                uint32_t L0 = 0, T0 = 0;
+                if (FULL || t < total_in) {
+                    if constexpr (IO == IO_U8) {
+                        bytes_to_planes(ring[d], L0, T0);
+                        asm("" : "+v"(L0), "+v"(T0));
+                    } else {
+                        L0 = ring[d][0];
+                        T0 = ring[d][1];
+                    }
+                    if (FULL || t + D < total_in) {
+                        issue(ring[d], ld_off);
+                        ld_off = advance(ld_off);
+                    }
+                }
+#pragma unroll
+                for (int k = K - 1; k >= 0; --k) {
+                    const LevelOut o = level_push(lv[k], k ? bl[k - 1] : L0, k ? bt[k - 1] : T0);
+                    const int rh = t - 2 * k - K;   // H row relative to row_a
+                    if (FULL || (rh >= 0 && rh < h)) {
+                        acc[k][0] += __builtin_popcount(o.l_h);
+                        acc[k][1] += __builtin_popcount(o.mv_h);
+                    }
+                    if (FULL || (rh >= 1 && rh <= h)) {
+                        acc[k][2] += __builtin_popcount(o.T);
+                        acc[k][3] += __builtin_popcount(o.mv_v);
+                    }
+                    // Opaque after each row: stops the adds from being
+                    // reassociated into one tree per macro-iteration, which
+                    // would keep every popcount of it live.
+                    asm("" : "+v"(acc[k][0]), "+v"(acc[k][1]), "+v"(acc[k][2]),
+                        "+v"(acc[k][3]));
+                    bl[k] = o.L;
+                    bt[k] = o.T;
+                }
+                if (FULL || (t >= 3 * K - 1 && t < 3 * K - 1 + h)) {
+                    if (lane_ok) {
+                        if constexpr (IO == IO_U8) {
+                            uint32_t b[8];
+                            planes_to_bytes(bl[K - 1], bt[K - 1], b);
+                            __builtin_amdgcn_raw_buffer_store_b128(
+                                (u32x4){b[0], b[1], b[2], b[3]}, dst, voff, st_off, 0);
+                            __builtin_amdgcn_raw_buffer_store_b128(
+                                (u32x4){b[4], b[5], b[6], b[7]}, dst, voff + 16, st_off, 0);
+                        } else {
+                            __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1], dst, voff, st_off,
+                                                                  0);
+                            __builtin_amdgcn_raw_buffer_store_b32(bt[K - 1], dst, voff,
+                                                                  st_off + plane_bytes, 0);
                         }
                     }
+                    st_off += row_bytes;
                 }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int i = 0; i < CH; ++i) {
-                    if (c * CH + i < R) {
-                        const u32x4 u0 = buf[c & 1][i][0], u1 = buf[c & 1][i][1];
-                        const uint32_t d[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-                        bytes_to_planes(d, L[c * CH + i], T[c * CH + i]);
-                        // Materialise the planes: otherwise the last swap of
-                        // the bit transpose is folded into every consumer and
-                        // each plane occupies two registers.
-                        asm("" : "+v"(L[c * CH + i]), "+v"(T[c * CH + i]));
-                    }
-                }
+                // Keep each iteration's work together: bounds register use
+                // (iterations would otherwise be interleaved) without losing
+                // the parallelism between the levels of one iteration.
                 __builtin_amdgcn_sched_barrier(0);
             }
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                L[r] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, roff(r), 0);
-                T[r] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, roff(r) + plane_bytes, 0);
-            }
+        };
+        for (int t0 = 0; t0 < total_it; t0 += D) {
+            // Full: every level counts, every iteration stores and the
+            // prefetch stays inside the strip for all D iterations.
+#ifndef BML_NO_FULL_BODY
+            if (t0 >= 3 * K - 1 && t0 + D <= h + K && t0 + 2 * D <= total_in)
+                body(t0, std::true_type{});
+            else
+#endif
+                body(t0, std::false_type{});
         }
 
-        // Step k updates rows [k, R-k) in the H phase (all still exact) and
-        // rows [k+1, R-k-1) in the V phase; rows [K, K+VR) are counted.
-        [&]<int... ks>(std::integer_sequence<int, ks...>) {
-            (([&] {
-                 uint32_t mlr = 0, nlr = 0, mtb = 0, ntb = 0;
-                 __builtin_amdgcn_sched_barrier(0);
-                 h_phase<R, ks, R - ks, K, K + VR>(L, T, mlr, nlr);
-                 __builtin_amdgcn_sched_barrier(0);
-                 v_phase<R, ks, R - ks, K, K + VR>(L, T, mtb, ntb);
-                 __builtin_amdgcn_sched_barrier(0);
-                 acc[ks][0] += lane_ok * nlr;
-                 acc[ks][1] += lane_ok * mlr;
-                 acc[ks][2] += lane_ok * ntb;
-                 acc[ks][3] += lane_ok * mtb;
-             }()),
-             ...);
-        }(std::make_integer_sequence<int, K>{});
-
-        if (lane_ok) {
-            const uint32_t out0 = (uint32_t)(ty * VR) * row_bytes;
+        // Fold this item's counts into the wave totals (halo and duplicate
+        // lanes contribute nothing).
 #pragma unroll
-            for (int r = K; r < K + VR; ++r) {
-                const uint32_t ro = out0 + (uint32_t)(r - K) * row_bytes;
-                if (IO == IO_U8) {
-                    uint32_t d[8];
-                    planes_to_bytes(L[r], T[r], d);
-                    __builtin_amdgcn_raw_buffer_store_b128((u32x4){d[0], d[1], d[2], d[3]}, dst,
-                                                           voff, ro, 0);
-                    __builtin_amdgcn_raw_buffer_store_b128((u32x4){d[4], d[5], d[6], d[7]}, dst,
-                                                           voff + 16, ro, 0);
-                    if ((r - K) % 2 == 1)
-                        __builtin_amdgcn_sched_barrier(0);
-                } else {
-                    __builtin_amdgcn_raw_buffer_store_b32(L[r], dst, voff, ro, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(T[r], dst, voff, ro + plane_bytes, 0);
-                }
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t v = lane_ok ? acc[k][q] : 0u;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1)
+                    v += (uint32_t)__shfl_xor((int)v, off, 64);
+                wtot[k][q] += (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
             }
-        }
     }
 
     // Counts: wave -> block (LDS) -> one of 8 device-wide stripes (block b
@@ -230,11 +263,14 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     if (threadIdx.x < MAX_K * 4)
         red[threadIdx.x] = 0;
     __syncthreads();
+    if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            wave_reduce_to_lds(acc[k][q], &red[k * 4 + q]);
+            for (int q = 0; q < 4; ++q)
+                if (wtot[k][q])
+                    atomicAdd(&red[k * 4 + q], wtot[k][q]);
+    }
     __syncthreads();
     uint32_t *stripe = &a.scratch->acc[blockIdx.x % ACC_STRIPES][0][0];
     if (threadIdx.x < K * 4 && red[threadIdx.x])
@@ -264,17 +300,17 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         __hip_atomic_store(&a.scratch->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Fills tab[k] (k = 1..MAX_K) with pass_kernel<IO, k, VR>.
-template <int IO, int VR, int... Ks>
+// Fills tab[k] (k = KLO..KHI) with pass_kernel<IO, k>.
+template <int IO, int KLO, int... Ks>
 inline void fill_pass_table(PassFn *tab, std::integer_sequence<int, Ks...>)
 {
-    ((tab[Ks + 1] = pass_kernel<IO, Ks + 1, VR>), ...);
+    ((tab[KLO + Ks] = pass_kernel<IO, KLO + Ks>), ...);
 }
 
-// Defined in one translation unit per (layout, output rows per tile).
-void pass_table_u8_r32(PassFn *tab);
-void pass_table_u8_r64(PassFn *tab);
-void pass_table_bp_r32(PassFn *tab);
-void pass_table_bp_r64(PassFn *tab);
+// Defined in one translation unit per (layout, range of K).
+void pass_table_u8_lo(PassFn *tab);   // K = 1..4
+void pass_table_u8_hi(PassFn *tab);   // K = 5..8
+void pass_table_bp_lo(PassFn *tab);
+void pass_table_bp_hi(PassFn *tab);
 
 } // namespace bml

@@ -1,0 +1,13 @@
+// bml_pass_bp_lo.hip -- instantiates the streaming step kernel for the
+// bitplane layout, steps per pass K = 1..4 (one translation unit
+// per variant group keeps the build parallel).
+#include "bml_pass.hpp"
+
+namespace bml {
+
+void pass_table_bp_lo(PassFn *tab)
+{
+    fill_pass_table<IO_BP, 1>(tab, std::make_integer_sequence<int, 4>{});
+}
+
+} // namespace bml

@@ -95,6 +95,43 @@ __device__ __forceinline__ void v_phase(const uint32_t (&L)[R], uint32_t (&T)[R]
     }
 }
 
+// ---- streaming pipeline level ----------------------------------------------
+//
+// A wavefront sweeping down a strip keeps one Level per step of the pass.
+// Level s receives rows of the lattice after s steps, one row at a time, top
+// to bottom.  On receiving row r it applies the horizontal phase to r (row
+// local), then completes the vertical phase of the row above, r-1, which
+// needs the post-H rows r-2 (through its movers, kept as mvp), r-1 (kept)
+// and r; it hands row r-1 after s+1 steps to the next level.
+struct Level {
+    uint32_t L, T;   // pending row r-1 after the horizontal phase
+    uint32_t mvp;    // TB movers of row r-2 (they arrive in row r-1)
+};
+
+struct LevelOut {
+    uint32_t L, T;       // row r-1 after the step
+    uint32_t mv_h, l_h;  // LR movers and new LR plane of row r (H phase)
+    uint32_t mv_v;       // TB movers of row r-1 (V phase)
+};
+
+__device__ __forceinline__ LevelOut level_push(Level &lv, uint32_t L_in, uint32_t T_in)
+{
+    LevelOut o;
+    uint32_t L = L_in;
+    o.mv_h = h_row(L, T_in);
+    o.l_h = L;
+    const uint32_t mv = lv.T & ~(L | T_in);
+    uint32_t t_new = (lv.T & ~mv) | lv.mvp;
+    asm("" : "+v"(t_new));
+    o.L = lv.L;
+    o.T = t_new;
+    o.mv_v = mv;
+    lv.L = L;
+    lv.T = T_in;
+    lv.mvp = mv;
+    return o;
+}
+
 // ---- byte cells <-> bitplane words -----------------------------------------
 //
 // Byte j of a 32-byte chunk (cells 32w .. 32w+31) holds 0, 1 or 2; bit 0 of

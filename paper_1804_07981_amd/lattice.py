@@ -49,7 +49,7 @@ class Lattice:
     def cells(self) -> np.ndarray:
         return B.bml_get_cells(self.handle, self.n)
 
-    def set_tuning(self, tile_rows: int = 0, t_phases: int = 0,
+    def set_tuning(self, tile_rows: int = -1, t_phases: int = 0,
                    waves_per_block: int = 0) -> None:
         B.bml_set_tuning(self.handle, tile_rows, t_phases, waves_per_block)
 

@@ -88,8 +88,9 @@ def test_small_every_step(B, layout):
 
 # --- random sizes, tunings, layouts ---------------------------------------
 
-TUNINGS = [(32, 2, 4), (64, 2, 4), (32, 4, 1), (64, 8, 2), (32, 16, 4), (64, 16, 1),
-           (32, 6, 2), (64, 10, 4)]
+# (strip rows, phases per pass, waves per block); 0 strip rows = automatic.
+TUNINGS = [(0, 2, 4), (8, 2, 4), (32, 4, 1), (64, 8, 2), (0, 16, 4), (40, 16, 1),
+           (24, 6, 2), (200, 10, 4)]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -144,7 +145,7 @@ def test_tuning_and_layout_invariance(B):
     n, steps = 320, 57
     ref = None
     for layout in LAYOUTS:
-        for vr in (32, 64):
+        for vr in (0, 8, 64, 320):
             for t in (2, 4, 8, 12, 16):
                 for w in (1, 4):
                     say(f"invariance layout={layout} vr={vr} t={t} w={w}")
@@ -231,7 +232,7 @@ def test_errors_and_free(B):
     assert e.value.code == B.BML_EINVAL
     lat = make(B, 64)
     with pytest.raises(B.BmlError) as e:
-        lat.set_tuning(48, 0, 0)
+        lat.set_tuning(4, 0, 0)
     assert e.value.code == B.BML_EINVAL
     with pytest.raises(B.BmlError):
         lat.set_tuning(0, 3, 0)
