@@ -104,6 +104,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the per-layout secondary measurements")
+    ap.add_argument("--probe", action="store_true",
+                    help="for counter runs: a 1 GiB device copy (the calibration kernel "
+                         "of known traffic), then --steps BML steps of the first lattice")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -121,6 +124,27 @@ def main() -> int:
     dev = torch.device("cuda:0")
     wl = workloads.MEDIUM if args.workload == "medium" else workloads.LARGE
     layout = 0 if args.layout == "u8" else 1
+
+    if args.probe:
+        a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)                       # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
+        lt = wl.lattices[0]
+        lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=max(args.steps, 1),
+                        device=dev)
+        tun = load_tuning(wl.name, layout, lt.n)
+        if tun:
+            lat.set_tuning(*tun)
+        lat.step(args.steps)
+        torch.cuda.synchronize()
+        tr, tp, wpb = lat.tuning()
+        print(json.dumps({"probe": wl.name, "layout": args.layout, "steps": args.steps,
+                          "cells": lt.n * lt.n, "t_phases": tp, "tile_rows": tr,
+                          "waves_per_block": wpb, "kernel_hash": kernel_hash()}), flush=True)
+        lat.close()
+        return 0
 
     def make_lattices(lay):
         lats = []

@@ -1,0 +1,175 @@
+"""Autotuner for the BML step kernels.
+
+For a lattice size and layout (or a batch of lattices) it times candidate
+launch shapes -- strip height, phases per HBM pass (temporal-block depth)
+and waves per block -- with HIP events on the library's stream, and keeps
+the fastest.  Every candidate must reproduce the reference candidate's final
+cells and every per-step count bit for bit (the bit-exactness gate): a
+candidate that differs is reported and never selected.  Results go to a JSON
+cache keyed by GPU architecture, layout and size, which `Lattice`/`Batch`
+users (and bench.py) read back.
+
+Usage: python -m paper_1804_07981_amd.autotune --sizes 4096 32768
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .batch import Batch
+from .lattice import Lattice
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def arch() -> str:
+    return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+
+
+def key(layout: int, n) -> str:
+    return f"{arch()}/{'u8' if layout == L.BML_LAYOUT_U8 else 'bp'}/{n}"
+
+
+def load(path: str = CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save(cache: dict, path: str = CACHE) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(layout: int, n, path: str = CACHE):
+    """(tile_rows, t_phases, waves_per_block) from the cache, or None."""
+    e = load(path).get(key(layout, n))
+    if not e:
+        return None
+    return int(e["tile_rows"]), int(e["t_phases"]), int(e["waves_per_block"])
+
+
+def _stats_array(rec):
+    return np.stack([rec["n_lr"], rec["moved_lr"], rec["n_tb"], rec["moved_tb"]], axis=1)
+
+
+def tune_lattice(n: int, layout: int, strip_rows=(0, 32, 64, 128, 256),
+                 t_phases=(2, 4, 8, 12, 16), waves=(2, 4), steps: int | None = None,
+                 rho: float = 0.3, seed: int = 7, log=print) -> dict:
+    """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice."""
+    if steps is None:
+        # about 4e10 cell-steps per measurement, at least 48 steps
+        steps = int(max(48, min(2000, 4e10 / (n * n))))
+        steps -= steps % 48
+    ref = None
+    results = []
+    for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
+        with Lattice(n, rho, seed, layout=layout, stats_cap=steps) as lat:
+            lat.set_tuning(tr, tp, w)
+            lat.step(steps)                      # warm-up (and the checked run)
+            torch.cuda.synchronize()
+            got = (lat.cells(), _stats_array(lat.stats(0, steps)))
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(lat.stream)
+            lat.step(steps)
+            e1.record(lat.stream)
+            torch.cuda.synchronize()
+            dt = e0.elapsed_time(e1) / 1e3
+        if ref is None:
+            ref = got
+            exact = True
+        else:
+            exact = np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+        gcups = n * n * steps / dt / 1e9
+        results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
+                        "gcups": gcups, "exact": exact})
+        log(f"  n={n} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS"
+            + ("" if exact else "  DIFFERS FROM THE REFERENCE -- rejected"))
+    ok = [r for r in results if r["exact"]]
+    best = max(ok, key=lambda r: r["gcups"])
+    return {"best": best, "all": results, "steps": steps,
+            "rejected": [r for r in results if not r["exact"]]}
+
+
+def tune_batch(ns, rhos, seeds, name: str, strip_rows=(16, 32, 64, 128),
+               t_phases=(4, 8, 12, 16), waves=(2, 4), steps: int = 256, log=print) -> dict:
+    """Fastest batch tuning for a set of lattices (checked like tune_lattice)."""
+    ref = None
+    results = []
+    cells = float(np.sum(np.asarray(ns, dtype=np.float64) ** 2))
+    for sr, tp, w in itertools.product(strip_rows, t_phases, waves):
+        with Batch(ns, rhos, seeds, trace_steps=2 * steps) as bt:
+            bt.set_tuning(sr, tp, w)
+            bt.run(steps)
+            bt.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(bt.stream)
+            bt.run(steps)
+            e1.record(bt.stream)
+            bt.synchronize()
+            dt = e0.elapsed_time(e1) / 1e3
+            got = (bt.trace(), [bt.cells(b) for b in (0, len(ns) // 2, len(ns) - 1)])
+        if ref is None:
+            ref = got
+            exact = True
+        else:
+            exact = np.array_equal(got[0], ref[0]) and all(
+                np.array_equal(a, b) for a, b in zip(got[1], ref[1]))
+        gcups = cells * steps / dt / 1e9
+        results.append({"tile_rows": sr, "t_phases": tp, "waves_per_block": w,
+                        "gcups": gcups, "exact": exact})
+        log(f"  batch {name} rows={sr} T={tp} w={w}: {gcups:.0f} GCUPS"
+            + ("" if exact else "  DIFFERS FROM THE REFERENCE -- rejected"))
+    ok = [r for r in results if r["exact"]]
+    return {"best": max(ok, key=lambda r: r["gcups"]), "all": results, "steps": steps,
+            "rejected": [r for r in results if not r["exact"]]}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description="tune the BML step kernels")
+    ap.add_argument("--sizes", type=int, nargs="*", default=[4096, 32768])
+    ap.add_argument("--layouts", nargs="*", default=["u8", "bp"])
+    ap.add_argument("--batch", action="store_true", help="also tune the 512-lattice sweep")
+    ap.add_argument("--cache", default=CACHE)
+    ap.add_argument("--quick", action="store_true", help="fewer candidates")
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    cache = load(args.cache)
+    kw = dict(strip_rows=(0, 64, 256), t_phases=(4, 8, 16), waves=(4,)) if args.quick else {}
+    for n in args.sizes:
+        for lay in args.layouts:
+            layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
+            r = tune_lattice(n, layout, **kw)
+            cache[key(layout, n)] = dict(r["best"], steps=r["steps"],
+                                         rejected=len(r["rejected"]))
+            print(json.dumps({"key": key(layout, n), **r["best"]}), flush=True)
+            if r["rejected"]:
+                print(f"bit-exactness gate rejected {len(r['rejected'])} candidates",
+                      file=sys.stderr)
+    if args.batch:
+        import workloads
+        lats = workloads.SWEEP.lattices
+        r = tune_batch([l.n for l in lats], [l.rho for l in lats], [l.seed for l in lats],
+                       "sweep512")
+        cache[key(L.BML_LAYOUT_BITPLANE, "sweep512")] = dict(r["best"], steps=r["steps"],
+                                                            rejected=len(r["rejected"]))
+        print(json.dumps({"key": key(L.BML_LAYOUT_BITPLANE, "sweep512"), **r["best"]}),
+              flush=True)
+    save(cache, args.cache)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

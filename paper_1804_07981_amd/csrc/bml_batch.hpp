@@ -233,6 +233,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                 const uint32_t s = step0 + (uint32_t)k;
                 if (lane == 0 && v && s < (uint32_t)a.trace_steps)
                     atomicAdd(&a.trace[((size_t)li * a.trace_steps + s) * 2 + q], v);
+                __builtin_amdgcn_sched_barrier(0);   // one reduction at a time
             }
         }
     }

@@ -250,6 +250,9 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                 for (int off = 32; off >= 1; off >>= 1)
                     v += (uint32_t)__shfl_xor((int)v, off, 64);
                 wtot[k][q] += (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+                // One reduction at a time: run together they would set the
+                // register peak of the whole kernel.
+                __builtin_amdgcn_sched_barrier(0);
             }
     }
 

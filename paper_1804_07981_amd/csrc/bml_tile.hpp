@@ -16,18 +16,18 @@ namespace bml {
 
 // ---- cross-lane moves (one 64-lane wavefront) -----------------------------
 
-// Lane l receives the value of lane l+1 (lane 63 receives 0).
+// Lane l receives the value of lane l+1 (lane 63 receives 0: bound_ctrl
+// writes zero where the source lane is out of range, so the destination
+// needs no initialisation).
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */,
-                                                 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
 }
 
 // Lane l receives the value of lane l-1 (lane 0 receives 0).
 __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */,
-                                                 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
 }
 
 // ---- the two phases on a register tile ------------------------------------
