@@ -94,12 +94,92 @@ def cpu_baseline(n: int, rho: float, seed: int, target_s: float = 15.0):
                       f"{dt:.1f} s (plain C oracle, -O3, OpenMP row split)"}
 
 
+def bench_sweep(args, B, workloads, dev) -> int:
+    """512 lattices of uneven N and rho, 4096 steps each, in one batch: a
+    captured 512-step graph replayed 8 times; against plain per-lattice runs
+    through the single-lattice API."""
+    import numpy as np
+    import torch
+    wl = workloads.SWEEP
+    ns = [l.n for l in wl.lattices]
+    rhos = [l.rho for l in wl.lattices]
+    seeds = [l.seed for l in wl.lattices]
+    cells = float(np.sum(np.asarray(ns, dtype=np.float64) ** 2))
+    chunk = 512
+    tun = load_tuning(wl.name, 1, "sweep512")
+    times = []
+    for rep in range(args.warmup + args.steps):
+        with B.Batch(ns, rhos, seeds, layout=1, trace_steps=wl.steps, device=dev) as bt:
+            if tun:
+                bt.set_tuning(*tun)
+            bt.capture(chunk)
+            bt.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(bt.stream)
+            for _ in range(wl.steps // chunk):
+                bt.replay()
+            e1.record(bt.stream)
+            bt.synchronize()
+            if rep >= args.warmup:
+                times.append(e0.elapsed_time(e1) / 1e3)
+            bt.check()
+    batch_s = float(np.mean(times))
+    value = cells * wl.steps / batch_s / 1e9
+    idx = list(range(len(ns))) if args.plain_sample is None else list(
+        np.linspace(0, len(ns) - 1, args.plain_sample).astype(int))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_cells = 0.0
+    for b in idx:
+        with B.Lattice(ns[b], rhos[b], seeds[b], layout=1, stats_cap=wl.steps, device=dev) as lat:
+            lat.step(wl.steps)
+            lat.stats(0, wl.steps)
+        plain_cells += float(ns[b]) ** 2
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) * (cells / plain_cells)
+    out = {"metric": "GCUPS (cell updates/s); density-sweep time vs plain", "value": round(value, 1),
+           "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(batch_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bitplane", "data": "synthetic (SplitMix64 iid lattices)",
+           "config": {"workload": wl.name, "lattices": len(ns), "steps_per_lattice": wl.steps,
+                      "graph_steps": chunk, "tuning": tun},
+           "sweep": {"batched_wall_s": batch_s, "plain_per_lattice_wall_s": plain_s,
+                     "plain_measured_lattices": len(idx), "gain": plain_s / batch_s}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_early_exit(args) -> int:
+    """The learned early-exit density sweep (512 x 512 lattices, 141
+    densities x 64 seeds, 20000 steps): labels, GPU training, held-out
+    error and wall time against plain runs and the exact stop rule."""
+    from paper_1804_07981_amd import early_exit as ee
+    ns, rhos, seeds, split = ee.c4_lattices()
+    rep = ee.experiment(ns, rhos, seeds, split, plain_sample=args.plain_sample or 96,
+                        log=lambda m: print(m, file=sys.stderr, flush=True))
+    t3 = rep["batch_exact_stop_mlp"]["wall_s"]
+    out = {"metric": "density-sweep wall time vs plain per-lattice full runs", "value":
+           round(rep["gain_vs_plain"], 2), "unit": "x faster", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": round(t3 * 1e3, 1), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bitplane+fp32/bf16",
+           "data": "synthetic (SplitMix64 iid lattices)",
+           "config": {"workload": "bml-early-exit-512x512-141rho-64seeds-20000steps"},
+           "early_exit": rep}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["medium", "large"], default="medium")
+    ap.add_argument("--workload", choices=["medium", "large", "sweep", "early-exit"],
+                    default="medium")
+    ap.add_argument("--plain-sample", type=int, default=None,
+                    help="sweep/early-exit: time plain per-lattice runs on this many "
+                         "lattices and scale to all")
     ap.add_argument("--layout", choices=["u8", "bitplane"], default="u8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
@@ -122,6 +202,10 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.workload == "sweep":
+        return bench_sweep(args, B, workloads, dev)
+    if args.workload == "early-exit":
+        return bench_early_exit(args)
     wl = workloads.MEDIUM if args.workload == "medium" else workloads.LARGE
     layout = 0 if args.layout == "u8" else 1
 

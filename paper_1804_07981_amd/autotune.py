@@ -68,8 +68,8 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 32, 64, 128, 256),
                  rho: float = 0.3, seed: int = 7, log=print) -> dict:
     """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice."""
     if steps is None:
-        # about 4e10 cell-steps per measurement, at least 48 steps
-        steps = int(max(48, min(2000, 4e10 / (n * n))))
+        # about 4e9 cell-steps per measurement, at least 48 steps
+        steps = int(max(48, min(2000, 4e9 / (n * n))))
         steps -= steps % 48
     ref = None
     results = []
