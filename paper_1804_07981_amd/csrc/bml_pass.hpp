@@ -74,11 +74,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint3
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Cache-policy bits of the state loads and stores (0 = default).
+#ifndef BML_LOAD_AUX
+#define BML_LOAD_AUX 0
+#endif
+#ifndef BML_STORE_AUX
+#define BML_STORE_AUX 0
+#endif
+
 template <int IO, int K>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
     static_assert(K >= 1 && K <= MAX_K, "bad steps per pass");
-    constexpr int D = 8;                      // rows prefetched ahead of the pipeline
+    // Rows prefetched ahead of the pipeline: a byte row is 2 KB per
+    // wavefront, so four of them keep enough in flight and save registers.
+    constexpr int D = IO == IO_U8 ? 4 : 8;
     constexpr int NW = IO == IO_U8 ? 8 : 2;   // dwords one lane loads per row
     const int lane = threadIdx.x & 63;
     // Wave-uniform values must be visibly uniform so that strip and row
@@ -131,13 +141,16 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         uint32_t ring[D][NW];
         auto issue = [&](uint32_t (&dstw)[NW], uint32_t off) {
             if constexpr (IO == IO_U8) {
-                const u32x4 u0 = __builtin_amdgcn_raw_buffer_load_b128(src, voff, off, 0);
-                const u32x4 u1 = __builtin_amdgcn_raw_buffer_load_b128(src, voff + 16, off, 0);
+                const u32x4 u0 =
+                    __builtin_amdgcn_raw_buffer_load_b128(src, voff, off, BML_LOAD_AUX);
+                const u32x4 u1 =
+                    __builtin_amdgcn_raw_buffer_load_b128(src, voff + 16, off, BML_LOAD_AUX);
                 dstw[0] = u0.x; dstw[1] = u0.y; dstw[2] = u0.z; dstw[3] = u0.w;
                 dstw[4] = u1.x; dstw[5] = u1.y; dstw[6] = u1.z; dstw[7] = u1.w;
             } else {
-                dstw[0] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off, 0);
-                dstw[1] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off + plane_bytes, 0);
+                dstw[0] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off, BML_LOAD_AUX);
+                dstw[1] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off + plane_bytes,
+                                                               BML_LOAD_AUX);
             }
         };
 #pragma unroll
@@ -210,14 +223,15 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                             uint32_t b[8];
                             planes_to_bytes(bl[K - 1], bt[K - 1], b);
                             __builtin_amdgcn_raw_buffer_store_b128(
-                                (u32x4){b[0], b[1], b[2], b[3]}, dst, voff, st_off, 0);
+                                (u32x4){b[0], b[1], b[2], b[3]}, dst, voff, st_off, BML_STORE_AUX);
                             __builtin_amdgcn_raw_buffer_store_b128(
-                                (u32x4){b[4], b[5], b[6], b[7]}, dst, voff + 16, st_off, 0);
+                                (u32x4){b[4], b[5], b[6], b[7]}, dst, voff + 16, st_off, BML_STORE_AUX);
                         } else {
                             __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1], dst, voff, st_off,
-                                                                  0);
+                                                                  BML_STORE_AUX);
                             __builtin_amdgcn_raw_buffer_store_b32(bt[K - 1], dst, voff,
-                                                                  st_off + plane_bytes, 0);
+                                                                  st_off + plane_bytes,
+                                                                  BML_STORE_AUX);
                         }
                     }
                     st_off += row_bytes;
