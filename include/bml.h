@@ -114,13 +114,15 @@ int bml_get_cells(bml_lattice *L, uint8_t *out_host);
 int bml_initial_counts(const bml_lattice *L, uint64_t *n_lr, uint64_t *n_tb);
 
 /* Launch shape of the step kernels.  Each wavefront streams down a strip of
- * the lattice 62 words (1984 cells) wide and `tile_rows` output rows tall
- * (plus t_phases/2 halo rows above and below), advancing every row
- * t_phases/2 steps per pass (t_phases even, 2..16).  tile_rows = 0 picks the
- * strip height from the occupancy of the device; otherwise 8 <= tile_rows
- * <= 65504.  waves_per_block = 1, 2 or 4.  A negative tile_rows, or a
- * t_phases / waves_per_block <= 0, keeps the current value.  Results do not
- * depend on the tuning; only speed does.  EINVAL on any other value. */
+ * the lattice `tile_rows` output rows tall (plus t_phases/2 halo rows above
+ * and below), advancing every row t_phases/2 steps per pass (t_phases even,
+ * 2..16).  A strip is 62 words (1984 cells) wide, or, for N = 2048 and 4096,
+ * the whole row (one wavefront holds a row, so x needs no halo).
+ * tile_rows = 0 picks the strip height from the occupancy of the device;
+ * otherwise 1 <= tile_rows <= 65504.  waves_per_block = 1, 2 or 4.  A
+ * negative tile_rows, or a t_phases / waves_per_block <= 0, keeps the
+ * current value.  Results do not depend on the tuning; only speed does.
+ * EINVAL on any other value. */
 int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases,
                    int32_t waves_per_block);
 int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,

@@ -12,7 +12,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbml.so")
 SOURCES = ["bml_lattice.hip", "bml_pass_u8_lo.hip", "bml_pass_u8_hi.hip",
-           "bml_pass_bp_lo.hip", "bml_pass_bp_hi.hip", "bml_batch.hip",
+           "bml_pass_bp_lo.hip", "bml_pass_bp_hi.hip", "bml_pass_u8_row1.hip",
+           "bml_pass_u8_row2.hip", "bml_pass_bp_row1.hip", "bml_pass_bp_row2.hip",
+           "bml_batch.hip",
            "bml_batch_u8.hip", "bml_batch_bp.hip", "bml_mlp.hip"]
 
 HIPCC_FLAGS = [

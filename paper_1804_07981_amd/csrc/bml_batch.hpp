@@ -149,13 +149,13 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
             }
         }
 
-        Level lv[K];
-        uint32_t bl[K], bt[K];
+        Level<1> lv[K];
+        uint32_t bl[K][1], bt[K][1];
         uint32_t acc[K][2];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            lv[k].L = lv[k].T = lv[k].mvp = 0;
-            bl[k] = bt[k] = 0;
+            lv[k].L[0] = lv[k].T[0] = lv[k].mvp[0] = 0;
+            bl[k][0] = bt[k][0] = 0;
             acc[k][0] = acc[k][1] = 0;
         }
 
@@ -166,14 +166,14 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                 const int t = t0 + dd;
                 if (!FULL && t >= total_it)
                     break;
-                uint32_t L0 = 0, T0 = 0;
+                uint32_t L0[1] = {0}, T0[1] = {0};
                 if (FULL || t < total_in) {
                     if constexpr (IO == IO_U8) {
-                        bytes_to_planes(ring[dd], L0, T0);
-                        asm("" : "+v"(L0), "+v"(T0));
+                        bytes_to_planes(ring[dd], L0[0], T0[0]);
+                        asm("" : "+v"(L0[0]), "+v"(T0[0]));
                     } else {
-                        L0 = ring[dd][0];
-                        T0 = ring[dd][1];
+                        L0[0] = ring[dd][0];
+                        T0[0] = ring[dd][1];
                     }
                     if (FULL || t + D < total_in) {
                         issue(ring[dd], ld_off);
@@ -182,29 +182,32 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                 }
 #pragma unroll
                 for (int k = K - 1; k >= 0; --k) {
-                    const LevelOut o = level_push(lv[k], k ? bl[k - 1] : L0, k ? bt[k - 1] : T0);
+                    if (!FULL && (t < 3 * k || t > h + 2 * K - 1 + k))
+                        continue;   // level idle in the prologue / drain
+                    const LevelOut<1> o =
+                        level_push<1, false>(lv[k], k ? bl[k - 1] : L0, k ? bt[k - 1] : T0);
                     const int rh = t - 2 * k - K;
                     if (FULL || (rh >= 0 && rh < h))
-                        acc[k][0] += __builtin_popcount(o.mv_h);
+                        acc[k][0] += __builtin_popcount(o.mv_h[0]);
                     if (FULL || (rh >= 1 && rh <= h))
-                        acc[k][1] += __builtin_popcount(o.mv_v);
+                        acc[k][1] += __builtin_popcount(o.mv_v[0]);
                     asm("" : "+v"(acc[k][0]), "+v"(acc[k][1]));
-                    bl[k] = o.L;
-                    bt[k] = o.T;
+                    bl[k][0] = o.L[0];
+                    bt[k][0] = o.T[0];
                 }
                 if (FULL || (t >= 3 * K - 1 && t < 3 * K - 1 + h)) {
                     if (lane_ok) {
                         if constexpr (IO == IO_U8) {
                             uint32_t b[8];
-                            planes_to_bytes(bl[K - 1], bt[K - 1], b);
+                            planes_to_bytes(bl[K - 1][0], bt[K - 1][0], b);
                             __builtin_amdgcn_raw_buffer_store_b128(
                                 (u32x4){b[0], b[1], b[2], b[3]}, dst, voff + st_off, 0, 0);
                             __builtin_amdgcn_raw_buffer_store_b128(
                                 (u32x4){b[4], b[5], b[6], b[7]}, dst, voff + st_off + 16, 0, 0);
                         } else {
-                            __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1], dst, voff + st_off,
+                            __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1][0], dst, voff + st_off,
                                                                   0, 0);
-                            __builtin_amdgcn_raw_buffer_store_b32(bt[K - 1], dst, voff + st_off,
+                            __builtin_amdgcn_raw_buffer_store_b32(bt[K - 1][0], dst, voff + st_off,
                                                                   plane_bytes, 0);
                         }
                     }

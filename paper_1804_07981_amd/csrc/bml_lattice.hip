@@ -192,16 +192,31 @@ __global__ void zero_words_kernel(uint32_t *p, int64_t count)
 // Kernel table
 // ============================================================================
 
+// fn[mode][io][k]: mode 0 = tile mode (any N), mode m = 1, 2 = row mode
+// for N = 2048 m (the wavefront holds a whole row, m words per lane).
+constexpr int PASS_MODES = 3;
+
 struct KernelTable {
-    PassFn fn[2][MAX_K + 1] = {};
+    PassFn fn[PASS_MODES][2][MAX_K + 1] = {};
     KernelTable()
     {
-        pass_table_u8_lo(fn[IO_U8]);
-        pass_table_u8_hi(fn[IO_U8]);
-        pass_table_bp_lo(fn[IO_BP]);
-        pass_table_bp_hi(fn[IO_BP]);
+        pass_table_u8_lo(fn[0][IO_U8]);
+        pass_table_u8_hi(fn[0][IO_U8]);
+        pass_table_bp_lo(fn[0][IO_BP]);
+        pass_table_bp_hi(fn[0][IO_BP]);
+        pass_table_u8_row1(fn[1][IO_U8]);
+        pass_table_bp_row1(fn[1][IO_BP]);
+        pass_table_u8_row2(fn[2][IO_U8]);
+        pass_table_bp_row2(fn[2][IO_BP]);
     }
 };
+
+// Row mode when a row is exactly 64 or 128 words (one wavefront).
+static int pass_mode(int n)
+{
+    const int words = n / 32;
+    return words == 64 ? 1 : words == 128 ? 2 : 0;
+}
 
 static const KernelTable &kernels()
 {
@@ -210,22 +225,22 @@ static const KernelTable &kernels()
 }
 
 // Resident blocks per CU of a pass kernel at `threads` threads per block.
-static int resident_blocks(int io, int k, int threads, int *out)
+static int resident_blocks(int mode, int io, int k, int threads, int *out)
 {
     static std::mutex mu;
-    static int cache[8][2][MAX_K + 1][3];   // [dev][io][k][log2 wpb]
+    static int cache[8][PASS_MODES][2][MAX_K + 1][3];   // [dev][mode][io][k][log2 wpb]
     int dev = 0;
     BML_HIP(hipGetDevice(&dev));
     int wl = threads == 64 ? 0 : threads == 128 ? 1 : 2;
     std::lock_guard<std::mutex> lock(mu);
-    int *c = dev < 8 ? &cache[dev][io][k][wl] : nullptr;
+    int *c = dev < 8 ? &cache[dev][mode][io][k][wl] : nullptr;
     if (c && *c > 0) {
         *out = *c;
         return BML_OK;
     }
     int nb = 0;
     BML_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(kernels().fn[io][k]), threads, 0));
+        &nb, reinterpret_cast<const void *>(kernels().fn[mode][io][k]), threads, 0));
     if (nb < 1)
         nb = 1;
     if (c)
@@ -535,8 +550,8 @@ int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases, int32_t 
     const int R = tile_rows >= 0 ? tile_rows : L->tile_rows;
     const int T = t_phases > 0 ? t_phases : L->t_phases;
     const int W = waves_per_block > 0 ? waves_per_block : L->wpb;
-    if (R != 0 && (R < 8 || R > 65504))
-        return fail(BML_EINVAL, "tile_rows=%d must be 0 (auto) or in [8, 65504]", R);
+    if (R > 65504)
+        return fail(BML_EINVAL, "tile_rows=%d must be 0 (auto) or in [1, 65504]", R);
     if (T < 2 || T > 2 * MAX_K || T % 2)
         return fail(BML_EINVAL, "t_phases=%d must be even in [2, %d]", T, 2 * MAX_K);
     if (W != 1 && W != 2 && W != 4)
@@ -573,7 +588,8 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
     a.scratch = L->d_scratch;
     a.n = L->n;
     a.words = L->n / 32;
-    a.tiles_x = (a.words + TILE_WORDS - 1) / TILE_WORDS;
+    const int mode = pass_mode(L->n);
+    a.tiles_x = mode ? 1 : (a.words + TILE_WORDS - 1) / TILE_WORDS;
     a.rec_mask = 0;
     for (int j = 0; j < MAX_K; ++j) {
         a.slot[j] = 0;
@@ -584,7 +600,7 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
     }
     const int threads = 64 * L->wpb;
     int per_cu = 1;
-    int rc = resident_blocks(io, k, threads, &per_cu);
+    int rc = resident_blocks(mode, io, k, threads, &per_cu);
     if (rc)
         return rc;
     const int64_t max_blocks = (int64_t)per_cu * L->dev.cu_count;
@@ -612,7 +628,7 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
             grid = max_blocks / 8 * 8;
     }
     a.xcd_split = (grid >= 8 && grid % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(kernels().fn[io][k], dim3((unsigned)grid), dim3(threads), 0, L->stream,
+    hipLaunchKernelGGL(kernels().fn[mode][io][k], dim3((unsigned)grid), dim3(threads), 0, L->stream,
                        a);
     BML_HIP(hipGetLastError());
     L->cur ^= 1;

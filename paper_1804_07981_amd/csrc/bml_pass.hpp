@@ -1,27 +1,31 @@
 // bml_pass.hpp -- the temporally blocked BML step kernel (gfx950).
 //
-// One wavefront holds a tile of R = VR + 2K lattice rows x 64 words (2048
-// cells) in VGPRs as two bitplanes and advances it K steps (2K phases)
-// before writing its VR middle rows back, so each HBM pass costs one read
-// and one write of the state for K steps (temporal blocking).  Neighbours across the tile edge come from a
-// periodic halo: K rows above and below and one word on each side (lanes 0
-// and 63), addressed modulo N, so no ghost cells are ever stored (the ghost
-// cells of Marzolla, arXiv:1804.07981, Sec. 3, become modular addressing of
-// the halo).  Each phase invalidates one more halo row on each side
-// (vertical) and one more bit in lanes 0 and 63 (horizontal), so the VR
-// middle rows of lanes 1..62 are exact after K steps; only those are written
-// and counted.  VR is 32 or 64 and divides N, so every tile row is full.
+// One launch advances the lattice K steps (2K phases) with one read and one
+// write of the state (temporal blocking).  The lattice is cut into strips
+// of H output rows; a wavefront streams its strip top to bottom through a
+// pipeline of K levels held in VGPRs, level k turning rows after k steps
+// into rows after k + 1 steps (bml_tile.hpp).  The strip is read with K
+// halo rows above and below, addressed modulo N, so no ghost cells are ever
+// stored (the ghost cells of Marzolla, arXiv:1804.07981, Sec. 3, become
+// modular addressing of the halo); each step invalidates one more halo row
+// at each end, so exactly the H strip rows leave the last level exact.
+//
+// Columns: in tile mode a wavefront covers 62 words (lanes 1..62) plus a
+// halo word on each side (lanes 0 and 63), whose edge bits go stale one cell
+// per step, far from the exact words for K <= 8.  In row mode (N = 2048 or
+// 4096) the wavefront holds a whole row, one or two words per lane, and the
+// lane moves wrap around the wavefront, so x is periodic with no halo lanes
+// and no tile of a row is left partly used.
 //
 // Memory access: buffer loads/stores with the per-lane word offset in a VGPR
-// and the row offset in an SGPR, so an in-flight row costs no address
-// registers.  Byte lattices are read 32 bytes per lane (two dwordx4) in
-// chunks of rows, one chunk in flight while the previous one is packed into
-// bitplanes; bitplane lattices are read straight into the tile registers.
+// and the row offset in an SGPR; rows are prefetched D rows ahead of the
+// pipeline into a register ring.  Byte lattices are converted to bitplanes
+// in registers after loading and back before storing.
 //
-// Grids are persistent: every wavefront walks a strided list of tiles.
+// Grids are persistent: every wavefront walks a strided list of strips.
 // Blocks are dispatched round-robin over the 8 XCDs, so block b is mapped to
-// the (b % 8)-th eighth of every round of tiles: each XCD works on a band of
-// vertically adjacent tiles, which share halo rows in that XCD's L2.
+// the (b % 8)-th eighth of every round of strips: each XCD works on a band
+// of vertically adjacent strips, which share halo rows in that XCD's L2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -73,6 +77,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint3
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // Cache-policy bits of the state loads and stores (0 = default).
 #ifndef BML_LOAD_AUX
@@ -81,15 +86,26 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 #ifndef BML_STORE_AUX
 #define BML_STORE_AUX 0
 #endif
+#ifndef BML_U8_RING
+#define BML_U8_RING 4      // byte rows prefetched per wavefront
+#endif
 
-template <int IO, int K>
+// ROW = 0: tile mode, any N; a wavefront covers 62 words plus a halo lane
+// on each side.  ROW = m > 0: row mode for N = 2048 m; the wavefront holds a
+// whole row, m words per lane, and the lane moves wrap around it (periodic
+// in x without halo lanes, every lane exact).
+template <int IO, int K, int ROW>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
     static_assert(K >= 1 && K <= MAX_K, "bad steps per pass");
+    static_assert(ROW >= 0 && ROW <= 2, "row mode holds at most 2 words per lane");
+    constexpr int WL = ROW ? ROW : 1;        // words per lane
+    constexpr bool WRAP = ROW > 0;
     // Rows prefetched ahead of the pipeline: a byte row is 2 KB per
-    // wavefront, so four of them keep enough in flight and save registers.
-    constexpr int D = IO == IO_U8 ? 4 : 8;
-    constexpr int NW = IO == IO_U8 ? 8 : 2;   // dwords one lane loads per row
+    // wavefront and word per lane, so four (two at 2 words per lane) keep
+    // enough in flight and save registers.
+    constexpr int D = IO == IO_U8 ? (WL > 1 ? 2 : BML_U8_RING) : 8;
+    constexpr int NW = (IO == IO_U8 ? 8 : 2) * WL;   // dwords one lane loads per row
     const int lane = threadIdx.x & 63;
     // Wave-uniform values must be visibly uniform so that strip and row
     // offsets live in SGPRs (buffer soffset) rather than per-lane VGPRs.
@@ -123,10 +139,17 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         const int h = min(H, a.n - row_a);              // output rows of this strip
         const int total_in = h + 2 * K;                 // input rows streamed
         const int total_it = h + 3 * K - 1;             // pipeline iterations
-        const int w0 = tx * TILE_WORDS;
-        const int vwords = min(TILE_WORDS, a.words - w0);
-        const uint32_t word = (uint32_t)((w0 + lane - 1 + a.words) % a.words);
-        const bool lane_ok = lane >= 1 && lane <= vwords;
+        uint32_t word;   // first word of this lane
+        bool lane_ok;    // lane holds exact output words
+        if constexpr (ROW > 0) {
+            word = (uint32_t)(lane * WL);
+            lane_ok = true;
+        } else {
+            const int w0 = tx * TILE_WORDS;
+            const int vwords = min(TILE_WORDS, a.words - w0);
+            word = (uint32_t)((w0 + lane - 1 + a.words) % a.words);
+            lane_ok = lane >= 1 && lane <= vwords;
+        }
         const uint32_t voff = IO == IO_U8 ? word * 32u : word * 4u;
 
         // Byte offset of input row t (lattice row row_a - K + t, periodic).
@@ -139,18 +162,26 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
             return x >= plane_bytes ? x - plane_bytes : x;
         };
         uint32_t ring[D][NW];
+        // Row layout in the ring: u8: 8 dwords (32 cells) per word; bp: the
+        // WL LR words, then the WL TB words.
         auto issue = [&](uint32_t (&dstw)[NW], uint32_t off) {
             if constexpr (IO == IO_U8) {
-                const u32x4 u0 =
-                    __builtin_amdgcn_raw_buffer_load_b128(src, voff, off, BML_LOAD_AUX);
-                const u32x4 u1 =
-                    __builtin_amdgcn_raw_buffer_load_b128(src, voff + 16, off, BML_LOAD_AUX);
-                dstw[0] = u0.x; dstw[1] = u0.y; dstw[2] = u0.z; dstw[3] = u0.w;
-                dstw[4] = u1.x; dstw[5] = u1.y; dstw[6] = u1.z; dstw[7] = u1.w;
-            } else {
+#pragma unroll
+                for (int j = 0; j < 2 * WL; ++j) {
+                    const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(src, voff + 16 * j,
+                                                                          off, BML_LOAD_AUX);
+                    dstw[4 * j + 0] = u.x; dstw[4 * j + 1] = u.y;
+                    dstw[4 * j + 2] = u.z; dstw[4 * j + 3] = u.w;
+                }
+            } else if constexpr (WL == 1) {
                 dstw[0] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off, BML_LOAD_AUX);
                 dstw[1] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off + plane_bytes,
                                                                BML_LOAD_AUX);
+            } else {
+                const u32x2 l = __builtin_amdgcn_raw_buffer_load_b64(src, voff, off, BML_LOAD_AUX);
+                const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(src, voff, off + plane_bytes,
+                                                                     BML_LOAD_AUX);
+                dstw[0] = l.x; dstw[1] = l.y; dstw[2] = t.x; dstw[3] = t.y;
             }
         };
 #pragma unroll
@@ -166,13 +197,14 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         // k steps) and emits it one row higher after k+1 steps.  Levels are
         // visited from K-1 down to 0 so each reads its input before level
         // k-1 overwrites it; within one iteration the levels are independent.
-        Level lv[K];
-        uint32_t bl[K], bt[K];   // bl/bt[k]: last output of level k
+        Level<WL> lv[K];
+        uint32_t bl[K][WL], bt[K][WL];   // bl/bt[k]: last output of level k
         uint32_t acc[K][4];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            lv[k].L = lv[k].T = lv[k].mvp = 0;
-            bl[k] = bt[k] = 0;
+#pragma unroll
+            for (int i = 0; i < WL; ++i)
+                lv[k].L[i] = lv[k].T[i] = lv[k].mvp[i] = bl[k][i] = bt[k][i] = 0;
             acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0;
         }
 
@@ -183,14 +215,20 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                 const int t = t0 + d;
                 if (!FULL && t >= total_it)
                     break;
-                uint32_t L0 = 0, T0 = 0;
+                uint32_t L0[WL], T0[WL];
+#pragma unroll
+                for (int i = 0; i < WL; ++i)
+                    L0[i] = T0[i] = 0;
                 if (FULL || t < total_in) {
-                    if constexpr (IO == IO_U8) {
-                        bytes_to_planes(ring[d], L0, T0);
-                        asm("" : "+v"(L0), "+v"(T0));
-                    } else {
-                        L0 = ring[d][0];
-                        T0 = ring[d][1];
+#pragma unroll
+                    for (int i = 0; i < WL; ++i) {
+                        if constexpr (IO == IO_U8) {
+                            bytes_to_planes(&ring[d][8 * i], L0[i], T0[i]);
+                            asm("" : "+v"(L0[i]), "+v"(T0[i]));
+                        } else {
+                            L0[i] = ring[d][i];
+                            T0[i] = ring[d][WL + i];
+                        }
                     }
                     if (FULL || t + D < total_in) {
                         issue(ring[d], ld_off);
@@ -199,39 +237,67 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                 }
 #pragma unroll
                 for (int k = K - 1; k >= 0; --k) {
-                    const LevelOut o = level_push(lv[k], k ? bl[k - 1] : L0, k ? bt[k - 1] : T0);
+                    // Level k only matters for 3k <= t <= h + 2K - 1 + k:
+                    // it first needs two rows of state before emitting
+                    // its first exact row (k + 1 after k + 1 steps), and
+                    // its last exact row is h + 2K - 2 - k.  Outside that
+                    // window (prologue and drain only) the uniform branch
+                    // skips it; its stale outputs are never read because
+                    // level k + 1 is then idle too.
+                    if (!FULL && (t < 3 * k || t > h + 2 * K - 1 + k))
+                        continue;
+                    const LevelOut<WL> o =
+                        level_push<WL, WRAP>(lv[k], k ? bl[k - 1] : L0, k ? bt[k - 1] : T0);
                     const int rh = t - 2 * k - K;   // H row relative to row_a
-                    if (FULL || (rh >= 0 && rh < h)) {
-                        acc[k][0] += __builtin_popcount(o.l_h);
-                        acc[k][1] += __builtin_popcount(o.mv_h);
-                    }
-                    if (FULL || (rh >= 1 && rh <= h)) {
-                        acc[k][2] += __builtin_popcount(o.T);
-                        acc[k][3] += __builtin_popcount(o.mv_v);
+#pragma unroll
+                    for (int i = 0; i < WL; ++i) {
+                        if (FULL || (rh >= 0 && rh < h)) {
+                            acc[k][0] += __builtin_popcount(o.l_h[i]);
+                            acc[k][1] += __builtin_popcount(o.mv_h[i]);
+                        }
+                        if (FULL || (rh >= 1 && rh <= h)) {
+                            acc[k][2] += __builtin_popcount(o.T[i]);
+                            acc[k][3] += __builtin_popcount(o.mv_v[i]);
+                        }
                     }
                     // Opaque after each row: stops the adds from being
                     // reassociated into one tree per macro-iteration, which
                     // would keep every popcount of it live.
                     asm("" : "+v"(acc[k][0]), "+v"(acc[k][1]), "+v"(acc[k][2]),
                         "+v"(acc[k][3]));
-                    bl[k] = o.L;
-                    bt[k] = o.T;
+#pragma unroll
+                    for (int i = 0; i < WL; ++i) {
+                        bl[k][i] = o.L[i];
+                        bt[k][i] = o.T[i];
+                    }
                 }
                 if (FULL || (t >= 3 * K - 1 && t < 3 * K - 1 + h)) {
                     if (lane_ok) {
                         if constexpr (IO == IO_U8) {
-                            uint32_t b[8];
-                            planes_to_bytes(bl[K - 1], bt[K - 1], b);
-                            __builtin_amdgcn_raw_buffer_store_b128(
-                                (u32x4){b[0], b[1], b[2], b[3]}, dst, voff, st_off, BML_STORE_AUX);
-                            __builtin_amdgcn_raw_buffer_store_b128(
-                                (u32x4){b[4], b[5], b[6], b[7]}, dst, voff + 16, st_off, BML_STORE_AUX);
-                        } else {
-                            __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1], dst, voff, st_off,
+#pragma unroll
+                            for (int i = 0; i < WL; ++i) {
+                                uint32_t b[8];
+                                planes_to_bytes(bl[K - 1][i], bt[K - 1][i], b);
+                                __builtin_amdgcn_raw_buffer_store_b128(
+                                    (u32x4){b[0], b[1], b[2], b[3]}, dst, voff + 32 * i, st_off,
+                                    BML_STORE_AUX);
+                                __builtin_amdgcn_raw_buffer_store_b128(
+                                    (u32x4){b[4], b[5], b[6], b[7]}, dst, voff + 32 * i + 16,
+                                    st_off, BML_STORE_AUX);
+                            }
+                        } else if constexpr (WL == 1) {
+                            __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1][0], dst, voff, st_off,
                                                                   BML_STORE_AUX);
-                            __builtin_amdgcn_raw_buffer_store_b32(bt[K - 1], dst, voff,
+                            __builtin_amdgcn_raw_buffer_store_b32(bt[K - 1][0], dst, voff,
                                                                   st_off + plane_bytes,
                                                                   BML_STORE_AUX);
+                        } else {
+                            __builtin_amdgcn_raw_buffer_store_b64(
+                                (u32x2){bl[K - 1][0], bl[K - 1][1]}, dst, voff, st_off,
+                                BML_STORE_AUX);
+                            __builtin_amdgcn_raw_buffer_store_b64(
+                                (u32x2){bt[K - 1][0], bt[K - 1][1]}, dst, voff,
+                                st_off + plane_bytes, BML_STORE_AUX);
                         }
                     }
                     st_off += row_bytes;
@@ -317,17 +383,22 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         __hip_atomic_store(&a.scratch->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Fills tab[k] (k = KLO..KHI) with pass_kernel<IO, k>.
-template <int IO, int KLO, int... Ks>
+// Fills tab[k] (k = KLO..KHI) with pass_kernel<IO, k, ROW>.
+template <int IO, int ROW, int KLO, int... Ks>
 inline void fill_pass_table(PassFn *tab, std::integer_sequence<int, Ks...>)
 {
-    ((tab[KLO + Ks] = pass_kernel<IO, KLO + Ks>), ...);
+    ((tab[KLO + Ks] = pass_kernel<IO, KLO + Ks, ROW>), ...);
 }
 
-// Defined in one translation unit per (layout, range of K).
-void pass_table_u8_lo(PassFn *tab);   // K = 1..4
-void pass_table_u8_hi(PassFn *tab);   // K = 5..8
+// Defined in one translation unit per (layout, mode, range of K); tab has
+// MAX_K + 1 entries.
+void pass_table_u8_lo(PassFn *tab);    // tile mode, K = 1..4
+void pass_table_u8_hi(PassFn *tab);    // tile mode, K = 5..8
 void pass_table_bp_lo(PassFn *tab);
 void pass_table_bp_hi(PassFn *tab);
+void pass_table_u8_row1(PassFn *tab);  // row mode, N = 2048, K = 1..8
+void pass_table_u8_row2(PassFn *tab);  // row mode, N = 4096
+void pass_table_bp_row1(PassFn *tab);
+void pass_table_bp_row2(PassFn *tab);
 
 } // namespace bml

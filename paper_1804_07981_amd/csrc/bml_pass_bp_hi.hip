@@ -7,7 +7,7 @@ namespace bml {
 
 void pass_table_bp_hi(PassFn *tab)
 {
-    fill_pass_table<IO_BP, 5>(tab, std::make_integer_sequence<int, 4>{});
+    fill_pass_table<IO_BP, 0, 5>(tab, std::make_integer_sequence<int, 4>{});
 }
 
 } // namespace bml

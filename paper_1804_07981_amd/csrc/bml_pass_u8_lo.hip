@@ -7,7 +7,7 @@ namespace bml {
 
 void pass_table_u8_lo(PassFn *tab)
 {
-    fill_pass_table<IO_U8, 1>(tab, std::make_integer_sequence<int, 4>{});
+    fill_pass_table<IO_U8, 0, 1>(tab, std::make_integer_sequence<int, 4>{});
 }
 
 } // namespace bml

@@ -1,12 +1,12 @@
 // bml_tile.hpp -- device building blocks of the BML step kernels (gfx950).
 //
-// A wavefront holds a tile of the lattice in VGPRs as two bitplanes: lane l
-// owns one 32-cell word column (bit b = cell 32w+b, least significant bit =
-// leftmost cell), register index r one row.  The horizontal phase needs the
-// words of the lanes on either side (DPP wave_shl/wave_shr by one lane, then
-// a funnel shift); the vertical phase only needs the rows above and below,
-// which are in the same lane.  Phase rules: Marzolla, arXiv:1804.07981,
-// Sec. 2 case tables; synchronous update as in Sec. 3.
+// A wavefront streams lattice rows through VGPRs as two bitplanes: lane l
+// owns WL consecutive 32-cell words of a row (bit b of word w = cell 32w+b,
+// least significant bit = leftmost cell).  The horizontal phase needs the
+// words of the lanes on either side (DPP moves by one lane, then a funnel
+// shift); the vertical phase only needs the rows above and below, which pass
+// through the same lane.  Phase rules: Marzolla, arXiv:1804.07981, Sec. 2
+// case tables; synchronous update as in Sec. 3.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,83 +15,55 @@
 namespace bml {
 
 // ---- cross-lane moves (one 64-lane wavefront) -----------------------------
+//
+// WRAP = false: lane l receives lane l+1 (or l-1), and the lane past the end
+// receives 0 (bound_ctrl writes zero where the source lane is out of range,
+// so the destination needs no initialisation).  WRAP = true: the wavefront is
+// a ring (wave_rol / wave_ror), for rows that exactly fill it.
 
-// Lane l receives the value of lane l+1 (lane 63 receives 0: bound_ctrl
-// writes zero where the source lane is out of range, so the destination
-// needs no initialisation).
+template <bool WRAP>
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, WRAP ? 0x134 /* wave_rol:1 */
+                                                           : 0x130 /* wave_shl:1 */,
+                                              0xF, 0xF, true);
 }
 
-// Lane l receives the value of lane l-1 (lane 0 receives 0).
+template <bool WRAP>
 __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, WRAP ? 0x13C /* wave_ror:1 */
+                                                           : 0x138 /* wave_shr:1 */,
+                                              0xF, 0xF, true);
 }
 
-// ---- the two phases on a register tile ------------------------------------
-//
-// L[r], T[r]: LR and TB planes of tile row r.  Rows [lo, hi) are updated; the
-// rows outside that range are stale halo.  Counting covers rows
-// [cnt_lo, cnt_hi) only.  All bounds are compile-time constants.
-
-// Horizontal phase of one row.  A car moves when the cell to its right is
-// EMPTY: mv = L & (E shifted one cell left); the new LR plane drops the
-// movers and sets their destinations (mv shifted one cell right).
-__device__ __forceinline__ uint32_t h_row(uint32_t &L, uint32_t T)
+// Horizontal phase of one row (WL words per lane).  A car moves when the
+// cell to its right is EMPTY: mv = L & (E shifted one cell left); the new LR
+// plane drops the movers and sets their destinations (mv shifted one cell
+// right).  Word i's right neighbour is word i+1 of the same lane, or word 0
+// of the next lane; its left neighbour is word i-1, or the last word of the
+// previous lane.
+template <int WL, bool WRAP>
+__device__ __forceinline__ void h_row(uint32_t (&L)[WL], const uint32_t (&T)[WL],
+                                      uint32_t (&mv)[WL])
 {
-    const uint32_t E = ~(L | T);
-    const uint32_t e_right = __builtin_amdgcn_alignbit(from_next_lane(E), E, 1);
-    const uint32_t mv = L & e_right;
-    const uint32_t arrive = __builtin_amdgcn_alignbit(mv, from_prev_lane(mv), 31);
-    L = (L & ~mv) | arrive;
-    // Opaque new state: stops the compiler from carrying pieces of this
-    // expression (e.g. L & ~mv) into the vertical phase as extra live values.
-    asm("" : "+v"(L));
-    return mv;
-}
-
-template <int R, int lo, int hi, int cnt_lo, int cnt_hi>
-__device__ __forceinline__ void h_phase(uint32_t (&L)[R], const uint32_t (&T)[R],
-                                        uint32_t &moved, uint32_t &cars)
-{
+    uint32_t E[WL];
 #pragma unroll
-    for (int r = lo; r < hi; ++r) {
-        const uint32_t mv = h_row(L[r], T[r]);
-        if (r >= cnt_lo && r < cnt_hi) {
-            moved += __builtin_popcount(mv);
-            cars += __builtin_popcount(L[r]);
-            // Count now: keeps the compiler from sinking the popcounts to
-            // their single use, which would hold every row's mask live.
-            asm volatile("" : "+v"(moved), "+v"(cars));
-        }
-    }
-}
-
-// Vertical phase.  A TB car at row r moves when row r+1 is EMPTY there:
-// mv[r] = T[r] & ~(L[r+1] | T[r+1]); the new T[r] drops mv[r] and gains the
-// arrivals mv[r-1].  Rows are visited top-down so that T[r+1] is still the
-// pre-phase value when mv[r] is formed.  Row lo keeps its movers out but
-// receives nothing (its upper neighbour is stale), so it becomes stale too;
-// the caller shrinks [lo, hi) by one row per phase.
-template <int R, int lo, int hi, int cnt_lo, int cnt_hi>
-__device__ __forceinline__ void v_phase(const uint32_t (&L)[R], uint32_t (&T)[R],
-                                        uint32_t &moved, uint32_t &cars)
-{
-    uint32_t prev = 0;
+    for (int i = 0; i < WL; ++i)
+        E[i] = ~(L[i] | T[i]);
+    const uint32_t e_next = from_next_lane<WRAP>(E[0]);
 #pragma unroll
-    for (int r = lo; r < hi - 1; ++r) {
-        const uint32_t mv = T[r] & ~(L[r + 1] | T[r + 1]);
-        const uint32_t nt = (T[r] & ~mv) | prev;
-        T[r] = nt;
-        asm("" : "+v"(T[r]));
-        prev = mv;
-        if (r >= cnt_lo && r < cnt_hi) {
-            moved += __builtin_popcount(mv);
-            cars += __builtin_popcount(nt);
-            asm volatile("" : "+v"(moved), "+v"(cars));
-        }
+    for (int i = 0; i < WL; ++i)
+        mv[i] = L[i] & __builtin_amdgcn_alignbit(i + 1 < WL ? E[i + 1] : e_next, E[i], 1);
+    const uint32_t mv_prev = from_prev_lane<WRAP>(mv[WL - 1]);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+        const uint32_t arrive = __builtin_amdgcn_alignbit(mv[i], i ? mv[i - 1] : mv_prev, 31);
+        L[i] = (L[i] & ~mv[i]) | arrive;
+        // Opaque new state: stops the compiler from carrying pieces of this
+        // expression (e.g. L & ~mv) into the vertical phase as extra live
+        // values.
+        asm("" : "+v"(L[i]));
     }
 }
 
@@ -102,93 +74,84 @@ __device__ __forceinline__ void v_phase(const uint32_t (&L)[R], uint32_t (&T)[R]
 // to bottom.  On receiving row r it applies the horizontal phase to r (row
 // local), then completes the vertical phase of the row above, r-1, which
 // needs the post-H rows r-2 (through its movers, kept as mvp), r-1 (kept)
-// and r; it hands row r-1 after s+1 steps to the next level.
+// and r; it hands row r-1 after s+1 steps to the next level.  A TB car of
+// row r-1 moves when row r is EMPTY there after the horizontal phase.
+template <int WL>
 struct Level {
-    uint32_t L, T;   // pending row r-1 after the horizontal phase
-    uint32_t mvp;    // TB movers of row r-2 (they arrive in row r-1)
+    uint32_t L[WL], T[WL];   // pending row r-1 after the horizontal phase
+    uint32_t mvp[WL];        // TB movers of row r-2 (they arrive in row r-1)
 };
 
+template <int WL>
 struct LevelOut {
-    uint32_t L, T;       // row r-1 after the step
-    uint32_t mv_h, l_h;  // LR movers and new LR plane of row r (H phase)
-    uint32_t mv_v;       // TB movers of row r-1 (V phase)
+    uint32_t L[WL], T[WL];       // row r-1 after the step
+    uint32_t mv_h[WL], l_h[WL];  // LR movers and new LR plane of row r (H phase)
+    uint32_t mv_v[WL];           // TB movers of row r-1 (V phase)
 };
 
-__device__ __forceinline__ LevelOut level_push(Level &lv, uint32_t L_in, uint32_t T_in)
+template <int WL, bool WRAP>
+__device__ __forceinline__ LevelOut<WL> level_push(Level<WL> &lv, const uint32_t (&L_in)[WL],
+                                                   const uint32_t (&T_in)[WL])
 {
-    LevelOut o;
-    uint32_t L = L_in;
-    o.mv_h = h_row(L, T_in);
-    o.l_h = L;
-    const uint32_t mv = lv.T & ~(L | T_in);
-    uint32_t t_new = (lv.T & ~mv) | lv.mvp;
-    asm("" : "+v"(t_new));
-    o.L = lv.L;
-    o.T = t_new;
-    o.mv_v = mv;
-    lv.L = L;
-    lv.T = T_in;
-    lv.mvp = mv;
+    LevelOut<WL> o;
+    uint32_t L[WL];
+#pragma unroll
+    for (int i = 0; i < WL; ++i)
+        L[i] = L_in[i];
+    h_row<WL, WRAP>(L, T_in, o.mv_h);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+        o.l_h[i] = L[i];
+        const uint32_t mv = lv.T[i] & ~(L[i] | T_in[i]);
+        uint32_t t_new = (lv.T[i] & ~mv) | lv.mvp[i];
+        asm("" : "+v"(t_new));
+        o.L[i] = lv.L[i];
+        o.T[i] = t_new;
+        o.mv_v[i] = mv;
+        lv.L[i] = L[i];
+        lv.T[i] = T_in[i];
+        lv.mvp[i] = mv;
+    }
     return o;
 }
 
 // ---- byte cells <-> bitplane words -----------------------------------------
 //
 // Byte j of a 32-byte chunk (cells 32w .. 32w+31) holds 0, 1 or 2; bit 0 of
-// the byte says LR, bit 1 says TB.
+// the byte says LR, bit 1 says TB.  d[q] holds cells 4q .. 4q+3 (byte j of
+// the dword is cell 4q + j) and bit c of a plane word is cell 32w + c.
 
-// Moves the bit at position p = 8k + q (k = p >> 3, q = p & 7) to position
-// 4q + k, i.e. rotates the 5-bit position index left by two, using four
-// delta swaps (each exchanges two index bits).
-__host__ __device__ __forceinline__ uint32_t delta_swap(uint32_t x, int s, uint32_t m)
+// Byte-wise dot products gather four cells at a time: with one bit kept per
+// byte (mask m), weights 1, 2, 4, 8 on the low dword and 16 .. 128 on the
+// high one put the eight cells of two dwords into one byte of the plane
+// (times 2 for the TB bit).
+__device__ __forceinline__ uint32_t gather_cells8(uint32_t lo, uint32_t hi, uint32_t m)
 {
-    const uint32_t t = ((x >> s) ^ x) & m;
-    return x ^ t ^ (t << s);
+    const uint32_t h = __builtin_amdgcn_udot4(hi & m, 0x80402010u, 0u, false);
+    return __builtin_amdgcn_udot4(lo & m, 0x08040201u, h, false);
 }
 
-__host__ __device__ __forceinline__ uint32_t index_rotl2(uint32_t x)
+__device__ __forceinline__ void bytes_to_planes(const uint32_t *d, uint32_t &lr, uint32_t &tb)
 {
-    x = delta_swap(x, 1, 0x22222222u);
-    x = delta_swap(x, 2, 0x0c0c0c0cu);
-    x = delta_swap(x, 7, 0x00aa00aau);
-    x = delta_swap(x, 14, 0x0000ccccu);
-    return x;
+    constexpr uint32_t M_LR = 0x01010101u, M_TB = 0x02020202u;
+    lr = gather_cells8(d[0], d[1], M_LR) | (gather_cells8(d[2], d[3], M_LR) << 8) |
+         (gather_cells8(d[4], d[5], M_LR) << 16) | (gather_cells8(d[6], d[7], M_LR) << 24);
+    tb = (gather_cells8(d[0], d[1], M_TB) >> 1) | (gather_cells8(d[2], d[3], M_TB) << 7) |
+         (gather_cells8(d[4], d[5], M_TB) << 15) | (gather_cells8(d[6], d[7], M_TB) << 23);
 }
 
-// Inverse of index_rotl2: position 4q + k goes back to 8k + q.
-__host__ __device__ __forceinline__ uint32_t index_rotl3(uint32_t x)
+// The inverse spreads a nibble over the four bytes of a dword: n * 0x204081
+// is n + (n << 7) + (n << 14) + (n << 21), four copies that cannot overlap,
+// so bit i of n lands on bit 8i (and, with 0x408102, on bit 8i + 1); the
+// masks drop the other copies' bits.
+__device__ __forceinline__ void planes_to_bytes(uint32_t lr, uint32_t tb, uint32_t *d)
 {
-    x = delta_swap(x, 1, 0x22222222u);
-    x = delta_swap(x, 3, 0x0a0a0a0au);
-    x = delta_swap(x, 6, 0x00cc00ccu);
-    x = delta_swap(x, 12, 0x0000f0f0u);
-    return x;
-}
-
-// d[q] holds cells 4q .. 4q+3 (byte k = cell 4q + k).
-__host__ __device__ __forceinline__ void bytes_to_planes(const uint32_t (&d)[8],
-                                                         uint32_t &lr, uint32_t &tb)
-{
-    uint32_t a = 0, b = (d[0] >> 1) & 0x01010101u;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-        a |= (d[q] & 0x01010101u) << q;
-#pragma unroll
-    for (int q = 1; q < 8; ++q)
-        b |= (d[q] & 0x02020202u) << (q - 1);
-    lr = index_rotl2(a);
-    tb = index_rotl2(b);
-}
-
-__host__ __device__ __forceinline__ void planes_to_bytes(uint32_t lr, uint32_t tb,
-                                                         uint32_t (&d)[8])
-{
-    const uint32_t a = index_rotl3(lr);
-    const uint32_t b = index_rotl3(tb);
-    d[0] = (a & 0x01010101u) | ((b << 1) & 0x02020202u);
-#pragma unroll
-    for (int q = 1; q < 8; ++q)
-        d[q] = ((a >> q) & 0x01010101u) | ((b >> (q - 1)) & 0x02020202u);
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t nl = (lr >> (4 * q)) & 15u;
+        const uint32_t nt = (tb >> (4 * q)) & 15u;
+        d[q] = ((nl * 0x00204081u) & 0x01010101u) | ((nt * 0x00408102u) & 0x02020202u);
+    }
 }
 
 } // namespace bml

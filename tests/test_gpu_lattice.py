@@ -90,7 +90,7 @@ def test_small_every_step(B, layout):
 
 # (strip rows, phases per pass, waves per block); 0 strip rows = automatic.
 TUNINGS = [(0, 2, 4), (8, 2, 4), (32, 4, 1), (64, 8, 2), (0, 16, 4), (40, 16, 1),
-           (24, 6, 2), (200, 10, 4)]
+           (24, 6, 2), (200, 10, 4), (3, 12, 4)]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -232,7 +232,7 @@ def test_errors_and_free(B):
     assert e.value.code == B.BML_EINVAL
     lat = make(B, 64)
     with pytest.raises(B.BmlError) as e:
-        lat.set_tuning(4, 0, 0)
+        lat.set_tuning(65536, 0, 0)
     assert e.value.code == B.BML_EINVAL
     with pytest.raises(B.BmlError):
         lat.set_tuning(0, 3, 0)
@@ -262,6 +262,64 @@ def test_pack_unpack_roundtrip(B):
     assert np.array_equal(planes[: n * n // 32].reshape(n, n // 32), lr)
     assert np.array_equal(planes[n * n // 32:].reshape(n, n // 32), tb)
     assert np.array_equal(d_back.cpu().numpy(), g)
+
+
+# --- row mode: N = 2048 and 4096 (a whole row per wavefront) ----------------
+
+ROW_TUNINGS = [(0, 2, 4), (8, 4, 4), (16, 16, 4), (24, 10, 2), (4096, 12, 1), (40, 14, 4),
+               (8, 16, 1), (0, 6, 2), (1, 16, 4), (3, 8, 2)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("n", [2048, 4096])
+@pytest.mark.parametrize("tuning", ROW_TUNINGS, ids=[f"vr{a}_t{b}_w{c}" for a, b, c in ROW_TUNINGS])
+def test_row_mode_all_counts(B, layout, n, tuning):
+    """Row lengths of 64 and 128 words put a whole row in one wavefront with
+    wrapping lane moves; strips of several heights (some not dividing N),
+    every pass length, and runs that end mid-pass."""
+    rng = np.random.default_rng(hash((layout, n) + tuning) % 2**32)
+    steps = int(rng.integers(1, 3 * tuning[1]))
+    rho = float(rng.choice([0.1, 0.3, 0.38, 0.5, 0.9]))
+    seed = int(rng.integers(0, 2**32))
+    say(f"row mode n={n} steps={steps} rho={rho} seed={seed} layout={layout} tuning={tuning}")
+    g0 = oracle.init_cells(n, seed, rho)
+    want, wst = oracle.run(g0, steps, n_threads=HOST_THREADS)
+    with make(B, n, rho, seed, layout, cap=64, tuning=tuning) as lat:
+        lat.step(steps)
+        got = lat.cells()
+        if not np.array_equal(got, want):
+            bad = np.argwhere(got != want)
+            pytest.fail(f"{len(bad)} cells differ, first at {bad[0]}")
+        assert np.array_equal(stats_array(lat.stats(0, steps)), wst)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_row_mode_wrap_cars(B, layout, n):
+    """Cars that cross the periodic seam (last word of the row, lane 63, to
+    the first, lane 0) and the seam between a lane's two words: a lone LR car
+    starting at the right edge and a lone TB car at the bottom edge are back
+    home after N steps, and a jam across the seam matches the oracle."""
+    say(f"row mode wrap n={n} layout={layout}")
+    g = np.zeros((n, n), np.uint8)
+    g[5, n - 1] = 1          # LR car about to wrap in x
+    g[n - 1, 37] = 2         # TB car about to wrap in y
+    g[100, 2046:2051] = 1    # cars across lanes 31/32 (n = 4096: word seam)
+    g[101, 63:66] = 2
+    g[200, n - 3:] = 1
+    g[200, :2] = 2           # blocked by a TB car just across the x seam
+    want, wst = oracle.run(g, 3 * n // 2, n_threads=HOST_THREADS)
+    with make(B, n, layout=layout, cells=g, cap=64) as lat:
+        lat.step(n)
+        lat.step(n // 2)
+        assert np.array_equal(lat.cells(), want)
+        assert np.array_equal(stats_array(lat.stats(3 * n // 2 - 64, 64)), wst[-64:])
+    lone = np.zeros((n, n), np.uint8)
+    lone[7, n - 1] = 1
+    lone[n - 1, 9] = 2
+    with make(B, n, layout=layout, cells=lone, cap=8) as lat:
+        lat.step(n)
+        assert np.array_equal(lat.cells(), lone)
 
 
 # --- the 4096 x 4096 workload, whole lattice --------------------------------
