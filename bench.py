@@ -46,16 +46,20 @@ def bytes_per_cell_step(layout: int, k: int) -> float:
     return per_cell_pass / k
 
 
-def load_tuning(workload: str, layout: int, n: int):
+def load_tuning(layout: int, n, group: str | None = None):
+    """Autotuned (tile_rows, t_phases, waves_per_block): the entry for the
+    group of lattices run together (e.g. the four concurrent 4096 lattices),
+    else the one for a lone lattice of side n, else None."""
     path = os.path.join(ROOT, "paper_1804_07981_amd", "tune_cache.json")
     if os.path.exists(path):
         try:
             with open(path) as f:
                 cache = json.load(f)
-            key = f"gfx950/{'u8' if layout == 0 else 'bp'}/{n}"
-            if key in cache:
-                t = cache[key]
-                return int(t["tile_rows"]), int(t["t_phases"]), int(t["waves_per_block"])
+            lay = "u8" if layout == 0 else "bp"
+            for key in ([f"gfx950/{lay}/{group}"] if group else []) + [f"gfx950/{lay}/{n}"]:
+                if key in cache:
+                    t = cache[key]
+                    return int(t["tile_rows"]), int(t["t_phases"]), int(t["waves_per_block"])
         except (OSError, ValueError, KeyError):
             pass
     return None
@@ -106,7 +110,7 @@ def bench_sweep(args, B, workloads, dev) -> int:
     seeds = [l.seed for l in wl.lattices]
     cells = float(np.sum(np.asarray(ns, dtype=np.float64) ** 2))
     chunk = 512
-    tun = load_tuning(wl.name, 1, "sweep512")
+    tun = load_tuning(1, "sweep512")
     times = []
     for rep in range(args.warmup + args.steps):
         with B.Batch(ns, rhos, seeds, layout=1, trace_steps=wl.steps, device=dev) as bt:
@@ -207,6 +211,8 @@ def main() -> int:
     if args.workload == "early-exit":
         return bench_early_exit(args)
     wl = workloads.MEDIUM if args.workload == "medium" else workloads.LARGE
+    # the lattices of a multi-lattice workload run concurrently, tuned as a group
+    group = workloads.MEDIUM_GROUP if len(wl.lattices) > 1 else None
     layout = 0 if args.layout == "u8" else 1
 
     if args.probe:
@@ -218,7 +224,7 @@ def main() -> int:
         lt = wl.lattices[0]
         lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=max(args.steps, 1),
                         device=dev)
-        tun = load_tuning(wl.name, layout, lt.n)
+        tun = load_tuning(layout, lt.n, group)
         if tun:
             lat.set_tuning(*tun)
         lat.step(args.steps)
@@ -238,7 +244,7 @@ def main() -> int:
             stream = torch.cuda.Stream(dev) if concurrent else torch.cuda.current_stream(dev)
             lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps, device=dev,
                             stream=stream)
-            tun = load_tuning(wl.name, lay, lt.n)
+            tun = load_tuning(lay, lt.n, group if concurrent else None)
             if tun:
                 lat.set_tuning(*tun)
             lats.append(lat)
@@ -340,7 +346,7 @@ def main() -> int:
                 for i, lt in enumerate(wl.lattices):
                     with B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps,
                                    device=dev) as lat:
-                        tun = load_tuning(wl.name, lay, lt.n)
+                        tun = load_tuning(lay, lt.n)
                         if tun:
                             lat.set_tuning(*tun)
                         lat.step(wl.steps)

@@ -9,7 +9,7 @@ candidate that differs is reported and never selected.  Results go to a JSON
 cache keyed by GPU architecture, layout and size, which `Lattice`/`Batch`
 users (and bench.py) read back.
 
-Usage: python -m paper_1804_07981_amd.autotune --sizes 4096 32768
+Usage: python -m paper_1804_07981_amd.autotune --sizes 4096 32768 [--medium] [--batch]
 """
 from __future__ import annotations
 
@@ -63,7 +63,7 @@ def _stats_array(rec):
     return np.stack([rec["n_lr"], rec["moved_lr"], rec["n_tb"], rec["moved_tb"]], axis=1)
 
 
-def tune_lattice(n: int, layout: int, strip_rows=(0, 32, 64, 128, 256),
+def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
                  t_phases=(2, 4, 8, 12, 16), waves=(2, 4), steps: int | None = None,
                  rho: float = 0.3, seed: int = 7, log=print) -> dict:
     """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice."""
@@ -99,6 +99,60 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 32, 64, 128, 256),
     ok = [r for r in results if r["exact"]]
     best = max(ok, key=lambda r: r["gcups"])
     return {"best": best, "all": results, "steps": steps,
+            "rejected": [r for r in results if not r["exact"]]}
+
+
+def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 32, 48),
+               t_phases=(8, 10, 12, 14, 16), waves=(2, 4), steps: int = 480, log=print) -> dict:
+    """Fastest common tuning for lattices (n, rho, seed) that run at the
+    same time, one stream each (as a workload of independent lattices runs):
+    the GPU is shared, so the best strip height differs from a lone
+    lattice's.  Every lattice's cells and counts must match the reference
+    candidate's (the bit-exactness gate)."""
+    ref = None
+    results = []
+    cells = float(sum(n * n for n, _, _ in specs))
+    for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
+        lats = [Lattice(n, rho, seed, layout=layout, stats_cap=steps,
+                        stream=torch.cuda.Stream()) for n, rho, seed in specs]
+        try:
+            for lat in lats:
+                lat.set_tuning(tr, tp, w)
+                lat.step(steps)                  # warm-up (and the checked run)
+            torch.cuda.synchronize()
+            try:
+                got = [(lat.cells(), _stats_array(lat.stats(0, steps))) for lat in lats]
+            except L.BmlError as e:              # e.g. car counts not conserved
+                log(f"  group {name} layout={layout} rows={tr} T={tp} w={w}: {e} -- rejected")
+                results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
+                                "gcups": 0.0, "exact": False, "error": str(e)})
+                continue
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in lats]
+            for lat, (e0, _) in zip(lats, evs):
+                e0.record(lat.stream)
+            for lat in lats:
+                lat.step(steps)
+            for lat, (_, e1) in zip(lats, evs):
+                e1.record(lat.stream)
+            torch.cuda.synchronize()
+            dt = max(e0.elapsed_time(e1) for e0, e1 in evs) / 1e3
+        finally:
+            for lat in lats:
+                lat.close()
+        if ref is None:
+            ref = got
+            exact = True
+        else:
+            exact = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+                        for a, b in zip(got, ref))
+        gcups = cells * steps / dt / 1e9
+        results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
+                        "gcups": gcups, "exact": exact})
+        log(f"  group {name} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS"
+            + ("" if exact else "  DIFFERS FROM THE REFERENCE -- rejected"))
+    ok = [r for r in results if r["exact"]]
+    return {"best": max(ok, key=lambda r: r["gcups"]), "all": results, "steps": steps,
             "rejected": [r for r in results if not r["exact"]]}
 
 
@@ -142,6 +196,8 @@ def main(argv=None) -> int:
     ap.add_argument("--sizes", type=int, nargs="*", default=[4096, 32768])
     ap.add_argument("--layouts", nargs="*", default=["u8", "bp"])
     ap.add_argument("--batch", action="store_true", help="also tune the 512-lattice sweep")
+    ap.add_argument("--medium", action="store_true",
+                    help="also tune the four concurrent 4096x4096 lattices as a group")
     ap.add_argument("--cache", default=CACHE)
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
     args = ap.parse_args(argv)
@@ -158,6 +214,15 @@ def main(argv=None) -> int:
             if r["rejected"]:
                 print(f"bit-exactness gate rejected {len(r['rejected'])} candidates",
                       file=sys.stderr)
+    if args.medium:
+        import workloads
+        specs = [(l.n, l.rho, l.seed) for l in workloads.MEDIUM.lattices]
+        for lay in args.layouts:
+            layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
+            r = tune_group(specs, layout, workloads.MEDIUM_GROUP)
+            k = key(layout, workloads.MEDIUM_GROUP)
+            cache[k] = dict(r["best"], steps=r["steps"], rejected=len(r["rejected"]))
+            print(json.dumps({"key": k, **r["best"]}), flush=True)
     if args.batch:
         import workloads
         lats = workloads.SWEEP.lattices

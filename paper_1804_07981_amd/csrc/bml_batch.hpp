@@ -74,7 +74,7 @@ template <int IO, int K>
 __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
 {
     static_assert(K >= 1 && K <= MAX_K, "bad steps per pass");
-    constexpr int D = 8;
+    constexpr int D = IO == IO_U8 ? BML_U8_RING : BML_BP_RING;   // prefetched rows
     constexpr int NW = IO == IO_U8 ? 8 : 2;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -229,14 +229,10 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                uint32_t v = lane_ok ? acc[k][q] : 0u;
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1)
-                    v += (uint32_t)__shfl_xor((int)v, off, 64);
+                const uint32_t v = wave_total(lane_ok ? acc[k][q] : 0u);
                 const uint32_t s = step0 + (uint32_t)k;
                 if (lane == 0 && v && s < (uint32_t)a.trace_steps)
                     atomicAdd(&a.trace[((size_t)li * a.trace_steps + s) * 2 + q], v);
-                __builtin_amdgcn_sched_barrier(0);   // one reduction at a time
             }
         }
     }

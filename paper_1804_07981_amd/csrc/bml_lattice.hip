@@ -357,6 +357,7 @@ struct bml_lattice {
     uint64_t n_lr0 = 0, n_tb0 = 0;
     int32_t tile_rows = 0, t_phases = 8, wpb = 4;   // tile_rows: strip rows (0 = auto)
     int32_t last_strip_rows = 0;                    // strip height of the last pass
+    int32_t auto_rows[MAX_K + 1][3] = {};           // automatic strip height per (k, wpb)
     DeviceInfo dev;
     unsigned long long *d_counts = nullptr;   // library scratch: 2 counters
     PassScratch *d_scratch = nullptr;         // library scratch: stats reduction
@@ -578,6 +579,38 @@ int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
 }
 
 // One kernel pass of k steps starting at global step `step0`.
+// Automatic strip height.  A wavefront's time is (rounds of strips it
+// takes) x (cost of one strip); a strip of h rows costs about K h + K^2 + K
+// level-rows of pipeline work (its idle levels skipped) plus the conversion
+// of h + 2K input rows and h output rows (a byte row costs about as much as
+// 1.5 / 1.8 level-rows, a bitplane row almost nothing).  Short strips give
+// more waves to spread over the device but pay the halo and pipeline
+// fill more often; the rounds term is what punishes a strip count just
+// above a multiple of the resident wave count.  Tries every strip count.
+static int auto_strip_rows(int n, int tiles_x, int k, int64_t waves, int io)
+{
+    const double c_in = io == IO_U8 ? 1.5 : 0.1, c_out = io == IO_U8 ? 1.8 : 0.1;
+    int best_h = n;
+    double best = 0;
+    int last_h = 0;
+    for (int strips = 1; strips <= n; ++strips) {
+        const int h = (n + strips - 1) / strips;
+        if (h == last_h)
+            continue;
+        last_h = h;
+        const int s = (n + h - 1) / h;   // strips at this height
+        const int64_t items = (int64_t)s * tiles_x;
+        const int64_t rounds = (items + waves - 1) / waves;
+        const double cost = (double)rounds * ((double)k * h + (double)k * k + k +
+                                              c_in * (h + 2 * k) + c_out * h);
+        if (best == 0 || cost < best) {
+            best = cost;
+            best_h = h;
+        }
+    }
+    return best_h;
+}
+
 static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
 {
     const int io = L->layout == BML_LAYOUT_U8 ? IO_U8 : IO_BP;
@@ -604,16 +637,14 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
     if (rc)
         return rc;
     const int64_t max_blocks = (int64_t)per_cu * L->dev.cu_count;
-    // Strip height: the tuned value, or by default enough strips for about
-    // two rounds of resident waves, but at least 4K rows so that the 2K halo
-    // rows of a strip stay a minor overhead.
+    // Strip height: the tuned value, or the automatic one for this pass
+    // length and block size.
     int H = L->tile_rows;
     if (H <= 0) {
-        const int64_t target_items = 2 * max_blocks * L->wpb;
-        H = (int)std::min<int64_t>(L->n, ((int64_t)L->n * a.tiles_x + target_items - 1) /
-                                             target_items);
-        H = std::max(H, std::min(4 * k, L->n));
-        H = (H + 7) / 8 * 8;
+        int32_t &cached = L->auto_rows[k][L->wpb == 1 ? 0 : L->wpb == 2 ? 1 : 2];
+        if (cached <= 0)
+            cached = auto_strip_rows(L->n, a.tiles_x, k, max_blocks * L->wpb, io);
+        H = cached;
     }
     H = std::min(H, L->n);
     a.strip_rows = H;

@@ -86,8 +86,24 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #ifndef BML_STORE_AUX
 #define BML_STORE_AUX 0
 #endif
+#ifndef BML_LEVEL_BARRIER
+#define BML_LEVEL_BARRIER 0
+#endif
+// Rows prefetched ahead of the pipeline (register ring depth) for byte and
+// bitplane rows, one or two words per lane.  Deeper rings hide more memory
+// latency but cost VGPRs; these keep every variant within 256 VGPRs (no
+// accumulation-register spills) and at two or more waves per SIMD.
 #ifndef BML_U8_RING
-#define BML_U8_RING 4      // byte rows prefetched per wavefront
+#define BML_U8_RING 4
+#endif
+#ifndef BML_BP_RING
+#define BML_BP_RING 8
+#endif
+#ifndef BML_U8_RING2
+#define BML_U8_RING2 1
+#endif
+#ifndef BML_BP_RING2
+#define BML_BP_RING2 2
 #endif
 
 // ROW = 0: tile mode, any N; a wavefront covers 62 words plus a halo lane
@@ -101,10 +117,8 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     static_assert(ROW >= 0 && ROW <= 2, "row mode holds at most 2 words per lane");
     constexpr int WL = ROW ? ROW : 1;        // words per lane
     constexpr bool WRAP = ROW > 0;
-    // Rows prefetched ahead of the pipeline: a byte row is 2 KB per
-    // wavefront and word per lane, so four (two at 2 words per lane) keep
-    // enough in flight and save registers.
-    constexpr int D = IO == IO_U8 ? (WL > 1 ? 2 : BML_U8_RING) : 8;
+    constexpr int D = IO == IO_U8 ? (WL > 1 ? BML_U8_RING2 : BML_U8_RING)
+                                  : (WL > 1 ? BML_BP_RING2 : BML_BP_RING);
     constexpr int NW = (IO == IO_U8 ? 8 : 2) * WL;   // dwords one lane loads per row
     const int lane = threadIdx.x & 63;
     // Wave-uniform values must be visibly uniform so that strip and row
@@ -270,6 +284,9 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                         bl[k][i] = o.L[i];
                         bt[k][i] = o.T[i];
                     }
+#if BML_LEVEL_BARRIER
+                    __builtin_amdgcn_sched_barrier(0);
+#endif
                 }
                 if (FULL || (t >= 3 * K - 1 && t < 3 * K - 1 + h)) {
                     if (lane_ok) {
@@ -324,16 +341,8 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint32_t v = lane_ok ? acc[k][q] : 0u;
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1)
-                    v += (uint32_t)__shfl_xor((int)v, off, 64);
-                wtot[k][q] += (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-                // One reduction at a time: run together they would set the
-                // register peak of the whole kernel.
-                __builtin_amdgcn_sched_barrier(0);
-            }
+            for (int q = 0; q < 4; ++q)
+                wtot[k][q] += wave_total(lane_ok ? acc[k][q] : 0u);
     }
 
     // Counts: wave -> block (LDS) -> one of 8 device-wide stripes (block b

@@ -37,6 +37,25 @@ __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v)
                                               0xF, 0xF, true);
 }
 
+// Sum of v over the 64 lanes of the wavefront, as a wave-uniform value.
+// DPP adds inside each 16-lane row (swap pairs, swap halves of quads, then
+// rotate the row by 4 and by 8 lanes) leave every lane with its row's sum;
+// the four row sums are then read from lanes 0, 16, 32 and 48.  No LDS
+// round trips, so many such sums can be in flight together.
+__device__ __forceinline__ uint32_t wave_total(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1 /* quad_perm 1,0,3,2 */, 0xF, 0xF,
+                                            false);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E /* quad_perm 2,3,0,1 */, 0xF, 0xF,
+                                            false);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x124 /* row_ror:4 */, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128 /* row_ror:8 */, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
 // Horizontal phase of one row (WL words per lane).  A car moves when the
 // cell to its right is EMPTY: mv = L & (E shifted one cell left); the new LR
 // plane drops the movers and sets their destinations (mv shifted one cell
@@ -121,23 +140,37 @@ __device__ __forceinline__ LevelOut<WL> level_push(Level<WL> &lv, const uint32_t
 // the byte says LR, bit 1 says TB.  d[q] holds cells 4q .. 4q+3 (byte j of
 // the dword is cell 4q + j) and bit c of a plane word is cell 32w + c.
 
-// Byte-wise dot products gather four cells at a time: with one bit kept per
-// byte (mask m), weights 1, 2, 4, 8 on the low dword and 16 .. 128 on the
-// high one put the eight cells of two dwords into one byte of the plane
-// (times 2 for the TB bit).
-__device__ __forceinline__ uint32_t gather_cells8(uint32_t lo, uint32_t hi, uint32_t m)
+// Gathering bit 0 (or bit 1) of every byte with shifts leaves the bit of
+// cell 4q + k at position 8k + q; index_rotl2 moves it to 4q + k, i.e. it
+// rotates the 5-bit position index left by two with four delta swaps (each
+// exchanges two index bits).  Plain shifts and masks only: the conversion
+// stays on the ordinary 32-bit VALU instructions.
+__device__ __forceinline__ uint32_t delta_swap(uint32_t x, int s, uint32_t m)
 {
-    const uint32_t h = __builtin_amdgcn_udot4(hi & m, 0x80402010u, 0u, false);
-    return __builtin_amdgcn_udot4(lo & m, 0x08040201u, h, false);
+    const uint32_t t = ((x >> s) ^ x) & m;
+    return x ^ t ^ (t << s);
+}
+
+__device__ __forceinline__ uint32_t index_rotl2(uint32_t x)
+{
+    x = delta_swap(x, 1, 0x22222222u);
+    x = delta_swap(x, 2, 0x0c0c0c0cu);
+    x = delta_swap(x, 7, 0x00aa00aau);
+    x = delta_swap(x, 14, 0x0000ccccu);
+    return x;
 }
 
 __device__ __forceinline__ void bytes_to_planes(const uint32_t *d, uint32_t &lr, uint32_t &tb)
 {
-    constexpr uint32_t M_LR = 0x01010101u, M_TB = 0x02020202u;
-    lr = gather_cells8(d[0], d[1], M_LR) | (gather_cells8(d[2], d[3], M_LR) << 8) |
-         (gather_cells8(d[4], d[5], M_LR) << 16) | (gather_cells8(d[6], d[7], M_LR) << 24);
-    tb = (gather_cells8(d[0], d[1], M_TB) >> 1) | (gather_cells8(d[2], d[3], M_TB) << 7) |
-         (gather_cells8(d[4], d[5], M_TB) << 15) | (gather_cells8(d[6], d[7], M_TB) << 23);
+    uint32_t a = 0, b = (d[0] >> 1) & 0x01010101u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        a |= (d[q] & 0x01010101u) << q;
+#pragma unroll
+    for (int q = 1; q < 8; ++q)
+        b |= (d[q] & 0x02020202u) << (q - 1);
+    lr = index_rotl2(a);
+    tb = index_rotl2(b);
 }
 
 // The inverse spreads a nibble over the four bytes of a dword: n * 0x204081
