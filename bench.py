@@ -211,7 +211,7 @@ def main() -> int:
     if args.workload == "early-exit":
         return bench_early_exit(args)
     wl = workloads.MEDIUM if args.workload == "medium" else workloads.LARGE
-    # the lattices of a multi-lattice workload run concurrently, tuned as a group
+    # the lattices of a multi-lattice workload run in joint launches, tuned as a group
     group = workloads.MEDIUM_GROUP if len(wl.lattices) > 1 else None
     layout = 0 if args.layout == "u8" else 1
 
@@ -236,41 +236,49 @@ def main() -> int:
         lat.close()
         return 0
 
-    def make_lattices(lay, concurrent):
+    def make_lattices(lay, mode):
+        """mode "joint": every lattice on one stream, advanced together by
+        joint launches (bml_step_group); "streams": one stream per lattice,
+        their launches overlapping; "single": the current stream."""
         lats = []
+        shared = torch.cuda.Stream(dev) if mode == "joint" else None
         for lt in wl.lattices:
-            # Independent lattices run on streams of their own so that their
-            # kernels share the GPU (one lattice alone cannot fill it).
-            stream = torch.cuda.Stream(dev) if concurrent else torch.cuda.current_stream(dev)
+            stream = (shared if mode == "joint" else
+                      torch.cuda.Stream(dev) if mode == "streams" else
+                      torch.cuda.current_stream(dev))
             lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps, device=dev,
                             stream=stream)
-            tun = load_tuning(lay, lt.n, group if concurrent else None)
+            tun = load_tuning(lay, lt.n, group if mode == "joint" else None)
             if tun:
                 lat.set_tuning(*tun)
             lats.append(lat)
         return lats
 
-    def run_job(lats):
-        for lat in lats:
-            lat.step(wl.steps)
+    def run_job(lats, mode):
+        if mode == "joint":
+            B.step_group(lats, wl.steps)
+        else:
+            for lat in lats:
+                lat.step(wl.steps)
 
-    def time_layout(lay, steps, warmup, concurrent=True):
-        lats = make_lattices(lay, concurrent and len(wl.lattices) > 1)
+    def time_layout(lay, steps, warmup, mode):
+        lats = make_lattices(lay, mode)
         for _ in range(warmup):
-            run_job(lats)
+            run_job(lats, mode)
         torch.cuda.synchronize()
+        streams = list({id(lat.stream): lat.stream for lat in lats}.values())
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in lats]
+               for _ in streams]
         t0 = time.perf_counter()
-        for lat, (e0, _) in zip(lats, evs):
-            e0.record(lat.stream)
+        for st, (e0, _) in zip(streams, evs):
+            e0.record(st)
         for _ in range(steps):
-            run_job(lats)
-        for lat, (_, e1) in zip(lats, evs):
-            e1.record(lat.stream)
+            run_job(lats, mode)
+        for st, (_, e1) in zip(streams, evs):
+            e1.record(st)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        # Busy time of each lattice's stream; they overlap when concurrent.
+        # Busy time of each stream (they overlap in "streams" mode).
         per_stream = [e0.elapsed_time(e1) / 1e3 for e0, e1 in evs]
         gpu_s = max(per_stream)
         # Every recorded count must still show the initial car numbers.
@@ -278,25 +286,27 @@ def main() -> int:
             lat.stats(lat.steps_done - wl.steps, wl.steps)
         tr, tp, wpb = lats[0].tuning()
         k = tp // 2
-        launches_per_lattice = -(-wl.steps // k) * steps
+        passes = -(-wl.steps // k) * steps
+        launches = passes if mode == "joint" else passes * len(lats)
         cells = sum(lt.n * lt.n for lt in wl.lattices)
         for lat in lats:
             lat.close()
         return {"gpu_s": gpu_s, "wall_s": wall, "k": k, "tile_rows": tr, "wpb": wpb,
-                "launches": launches_per_lattice * len(lats), "cells": cells,
-                "avg_launch_s": sum(per_stream) / (launches_per_lattice * len(lats)),
-                "streams": len(lats) if concurrent else 1,
+                "launches": launches, "cells": cells, "mode": mode,
+                "lattices_per_launch": len(lats) if mode == "joint" else 1,
+                "avg_launch_s": sum(per_stream) / launches,
                 "gcups": cells * wl.steps * steps / gpu_s / 1e9}
 
-    res = time_layout(layout, args.steps, args.warmup)
+    main_mode = "joint" if len(wl.lattices) > 1 else "single"
+    res = time_layout(layout, args.steps, args.warmup, main_mode)
     total_cell_steps = res["cells"] * wl.steps * args.steps
     value = total_cell_steps / res["gpu_s"] / 1e9
     ms_per_step = res["gpu_s"] * 1e3 / args.steps
 
     k = res["k"]
     per_launch_s = res["avg_launch_s"]
-    per_lattice_cells = res["cells"] / len(wl.lattices)
-    alg_bytes = bytes_per_cell_step(layout, k) * per_lattice_cells * k
+    launch_cells = res["cells"] / len(wl.lattices) * res["lattices_per_launch"]
+    alg_bytes = bytes_per_cell_step(layout, k) * launch_cells * k
     achieved = alg_bytes / per_launch_s / 1e9
     kname = f"pass_{args.layout}_{wl.lattices[0].n}"
     traffic = traffic_from_profile(kname, alg_bytes)
@@ -304,12 +314,11 @@ def main() -> int:
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "kernel": f"pass_kernel<{args.layout}, K={k}> (strip rows "
-                          f"{res['tile_rows'] or 'auto'}, {res['wpb']} waves/block)",
+                          f"{res['tile_rows'] or 'auto'}, {res['wpb']} waves/block, "
+                          f"{res['lattices_per_launch']} lattice(s) per launch)",
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_us": round(per_launch_s * 1e6, 2),
-                "concurrent_streams": res["streams"],
-                "aggregate_algorithmic_gbs": round(
-                    alg_bytes * res["launches"] / res["gpu_s"] / 1e9, 1)}
+                "effective_gbs": round(value * 1e9 * bytes_per_cell_step(layout, 1) / 1e9, 1)}
 
     out = {
         "metric": "GCUPS (cell updates/s) + % HBM roofline",
@@ -335,10 +344,14 @@ def main() -> int:
 
     if not args.no_variants:
         other = 1 - layout
-        r2 = time_layout(other, 1, 1)
+        r2 = time_layout(other, 1, 1, main_mode)
         out["variants"] = {("bitplane" if other else "u8"): {
             "gcups": round(r2["gcups"], 2), "t_phases": 2 * r2["k"],
-            "tile_rows": r2["tile_rows"], "streams": r2["streams"]}}
+            "tile_rows": r2["tile_rows"], "mode": r2["mode"]}}
+        if main_mode == "joint":
+            # the same lattices on one stream each, launches overlapping
+            r3 = time_layout(layout, 1, 1, "streams")
+            out["variants"]["separate_streams_gcups"] = round(r3["gcups"], 2)
         if len(wl.lattices) > 1:
             # each density alone, one stream (the single-lattice figure)
             per = {}

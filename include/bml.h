@@ -97,6 +97,17 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed,
  * min(n_steps, stats_cap) steps of this call are kept in the ring. */
 int bml_step(bml_lattice *L, int64_t n_steps);
 
+/* Advance `count` lattices (1..8) by n_steps each in joint launches: every
+ * kernel pass advances all of them, their strips spread over the device as
+ * one grid (several small lattices fill the GPU better together than one
+ * after another or on separate streams).  The handles must be distinct and
+ * share N, layout, tuning (bml_set_tuning), device and stream; their step
+ * counts and stats rings may differ, and each lattice's ring and counts
+ * behave exactly as if bml_step had been called on it alone.  Results are
+ * identical to stepping each lattice alone.  EINVAL on a bad count, a
+ * repeated handle or a mismatch, ESTATE on an invalid handle. */
+int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps);
+
 /* Copy the counts of steps first_step .. first_step+count-1 (global step
  * numbers, 0 = the first step after bml_init) to out_host.  The steps must
  * have been run and still be in the ring: first_step >= steps_done -

@@ -15,7 +15,7 @@ from ._lib import (BML_EBADARG, BML_ECORRUPT, BML_EDEVICE, BML_EINVAL,
                    BML_OK, STEP_STATS_DTYPE, BmlError, bml_current_state,
                    bml_free, bml_get_cells, bml_get_tuning, bml_init,
                    bml_initial_counts, bml_last_error, bml_pack, bml_set_tuning,
-                   bml_state_bytes, bml_stats, bml_step, bml_step_count,
+                   bml_state_bytes, bml_stats, bml_step, bml_step_count, bml_step_group,
                    bml_unpack, exported_symbols, lib, library_path,
                    bml_batch_arena_bytes, bml_batch_init, bml_batch_set_tuning,
                    bml_batch_set_active, bml_batch_run, bml_batch_capture,
@@ -26,13 +26,14 @@ from ._lib import (BML_EBADARG, BML_ECORRUPT, BML_EDEVICE, BML_EINVAL,
                    bml_mlp_grad, bml_mlp_train_step, bml_mlp_forward, bml_mlp_infer_bf16,
                    BML_MLP_INPUTS, BML_MLP_HIDDEN, BML_MLP_PARAMS, BML_MLP_MAX_BATCH)
 from .batch import Batch
-from .lattice import Lattice
+from .lattice import Lattice, step_group
 
 __all__ = [
     "BML_OK", "BML_EINVAL", "BML_EDEVICE", "BML_ERANGE", "BML_ESTATE",
     "BML_ECORRUPT", "BML_EBADARG", "BML_LAYOUT_U8", "BML_LAYOUT_BITPLANE",
     "STEP_STATS_DTYPE", "BmlError", "Lattice", "lib", "library_path",
     "exported_symbols", "bml_state_bytes", "bml_init", "bml_step", "bml_stats",
+    "bml_step_group", "step_group",
     "bml_get_cells", "bml_initial_counts", "bml_set_tuning", "bml_get_tuning",
     "bml_step_count", "bml_current_state", "bml_free", "bml_last_error",
     "bml_pack", "bml_unpack", "Batch", "bml_batch_arena_bytes", "bml_batch_init",

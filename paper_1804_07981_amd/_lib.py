@@ -49,6 +49,7 @@ _SIGNATURES = {
     "bml_init": ([ctypes.POINTER(_vp), _i32, _i32, _u64, _dbl, _vp, _vp, _vp, _vp,
                   _i64, _vp], ctypes.c_int),
     "bml_step": ([_vp, _i64], ctypes.c_int),
+    "bml_step_group": ([ctypes.POINTER(_vp), _i32, _i64], ctypes.c_int),
     "bml_stats": ([_vp, _i64, _i64, _vp], ctypes.c_int),
     "bml_get_cells": ([_vp, _vp], ctypes.c_int),
     "bml_initial_counts": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
@@ -167,6 +168,13 @@ def bml_init(n: int, layout: int, seed: int, rho: float, cells_host, d_state_a,
 
 def bml_step(handle: int, n_steps: int) -> None:
     _check(lib().bml_step(handle, n_steps))
+
+
+def bml_step_group(handles, n_steps: int) -> None:
+    """Advance several lattices (same size, layout, tuning and stream) in
+    joint launches."""
+    arr = (_vp * len(handles))(*[int(h) for h in handles])
+    _check(lib().bml_step_group(arr, len(handles), n_steps))
 
 
 def bml_stats(handle: int, first_step: int, count: int, check: bool = True) -> np.ndarray:

@@ -24,7 +24,7 @@ import torch
 
 from . import _lib as L
 from .batch import Batch
-from .lattice import Lattice
+from .lattice import Lattice, step_group
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
@@ -104,39 +104,37 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
 
 def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 32, 48),
                t_phases=(8, 10, 12, 14, 16), waves=(2, 4), steps: int = 480, log=print) -> dict:
-    """Fastest common tuning for lattices (n, rho, seed) that run at the
-    same time, one stream each (as a workload of independent lattices runs):
-    the GPU is shared, so the best strip height differs from a lone
-    lattice's.  Every lattice's cells and counts must match the reference
-    candidate's (the bit-exactness gate)."""
+    """Fastest common tuning for lattices (n, rho, seed) of one size that are
+    advanced together by joint launches (bml_step_group): a launch spreads
+    the strips of all of them over the device, so the best strip height
+    differs from a lone lattice's.  Every lattice's cells and counts must
+    match the reference candidate's (the bit-exactness gate)."""
     ref = None
     results = []
     cells = float(sum(n * n for n, _, _ in specs))
     for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
-        lats = [Lattice(n, rho, seed, layout=layout, stats_cap=steps,
-                        stream=torch.cuda.Stream()) for n, rho, seed in specs]
+        stream = torch.cuda.Stream()
+        lats = [Lattice(n, rho, seed, layout=layout, stats_cap=steps, stream=stream)
+                for n, rho, seed in specs]
         try:
             for lat in lats:
                 lat.set_tuning(tr, tp, w)
-                lat.step(steps)                  # warm-up (and the checked run)
+            step_group(lats, steps)                  # warm-up (and the checked run)
             torch.cuda.synchronize()
             try:
                 got = [(lat.cells(), _stats_array(lat.stats(0, steps))) for lat in lats]
-            except L.BmlError as e:              # e.g. car counts not conserved
+            except L.BmlError as e:                  # e.g. car counts not conserved
                 log(f"  group {name} layout={layout} rows={tr} T={tp} w={w}: {e} -- rejected")
                 results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
                                 "gcups": 0.0, "exact": False, "error": str(e)})
                 continue
-            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                   for _ in lats]
-            for lat, (e0, _) in zip(lats, evs):
-                e0.record(lat.stream)
-            for lat in lats:
-                lat.step(steps)
-            for lat, (_, e1) in zip(lats, evs):
-                e1.record(lat.stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            step_group(lats, steps)
+            e1.record(stream)
             torch.cuda.synchronize()
-            dt = max(e0.elapsed_time(e1) for e0, e1 in evs) / 1e3
+            dt = e0.elapsed_time(e1) / 1e3
         finally:
             for lat in lats:
                 lat.close()
@@ -197,7 +195,7 @@ def main(argv=None) -> int:
     ap.add_argument("--layouts", nargs="*", default=["u8", "bp"])
     ap.add_argument("--batch", action="store_true", help="also tune the 512-lattice sweep")
     ap.add_argument("--medium", action="store_true",
-                    help="also tune the four concurrent 4096x4096 lattices as a group")
+                    help="also tune the four 4096x4096 lattices advanced by joint launches")
     ap.add_argument("--cache", default=CACHE)
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
     args = ap.parse_args(argv)

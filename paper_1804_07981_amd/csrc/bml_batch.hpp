@@ -237,12 +237,15 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
         }
     }
 
-    // The last block to finish advances the device-side step and pass.
+    // The last block to finish advances the device-side step and pass.  By
+    // then every block has read them (each reads them first and takes its
+    // ticket last); the next launch sees the new values after the kernel
+    // boundary.  Only the ticket is shared during the launch, through a
+    // device-scope atomic, so no device-wide fence is needed.
     __shared__ uint32_t is_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t t = __hip_atomic_fetch_add(&a.ctr->ticket, 1u, __ATOMIC_ACQ_REL,
+        const uint32_t t = __hip_atomic_fetch_add(&a.ctr->ticket, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
         is_last = (t == gridDim.x - 1) ? 1u : 0u;
     }
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
     if (is_last && threadIdx.x == 0) {
         a.ctr->step = step0 + (uint32_t)K;
         a.ctr->pass = pass + 1u;
-        __hip_atomic_store(&a.ctr->ticket, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.ctr->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

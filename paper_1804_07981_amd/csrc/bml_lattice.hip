@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <new>
 #include <string>
@@ -611,26 +612,36 @@ static int auto_strip_rows(int n, int tiles_x, int k, int64_t waves, int io)
     return best_h;
 }
 
-static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
+// One launch: lattices G[0..count) (same size, layout, tuning and stream)
+// advance k steps.  Lattice i is at global step step0[i]; steps at or after
+// rec_from[i] have their counts recorded in its ring.
+static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step0,
+                    const int64_t *rec_from)
 {
+    bml_lattice *L = G[0];
     const int io = L->layout == BML_LAYOUT_U8 ? IO_U8 : IO_BP;
     PassArgs a;
-    a.src = L->buf[L->cur];
-    a.dst = L->buf[L->cur ^ 1];
-    a.stats = L->stats;
-    a.scratch = L->d_scratch;
+    std::memset(&a, 0, sizeof a);
+    a.n_lat = count;
+    a.any_rec = 0;
+    for (int i = 0; i < count; ++i) {
+        PassLattice &pl = a.lat[i];
+        pl.src = G[i]->buf[G[i]->cur];
+        pl.dst = G[i]->buf[G[i]->cur ^ 1];
+        pl.stats = G[i]->stats;
+        pl.scratch = G[i]->d_scratch;
+        pl.rec_mask = 0;
+        for (int j = 0; j < k; ++j)
+            if (step0[i] + j >= rec_from[i]) {
+                pl.rec_mask |= 1u << j;
+                pl.slot[j] = (int32_t)((step0[i] + j) % G[i]->cap);
+            }
+        a.any_rec |= pl.rec_mask;
+    }
     a.n = L->n;
     a.words = L->n / 32;
     const int mode = pass_mode(L->n);
     a.tiles_x = mode ? 1 : (a.words + TILE_WORDS - 1) / TILE_WORDS;
-    a.rec_mask = 0;
-    for (int j = 0; j < MAX_K; ++j) {
-        a.slot[j] = 0;
-        if (j < k && step0 + j >= rec_from) {
-            a.rec_mask |= 1u << j;
-            a.slot[j] = (int32_t)((step0 + j) % L->cap);
-        }
-    }
     const int threads = 64 * L->wpb;
     int per_cu = 1;
     int rc = resident_blocks(mode, io, k, threads, &per_cu);
@@ -638,18 +649,26 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
         return rc;
     const int64_t max_blocks = (int64_t)per_cu * L->dev.cu_count;
     // Strip height: the tuned value, or the automatic one for this pass
-    // length and block size.
+    // length, block size and group size (a group spreads count times as
+    // many strips over the device).
     int H = L->tile_rows;
     if (H <= 0) {
         int32_t &cached = L->auto_rows[k][L->wpb == 1 ? 0 : L->wpb == 2 ? 1 : 2];
-        if (cached <= 0)
-            cached = auto_strip_rows(L->n, a.tiles_x, k, max_blocks * L->wpb, io);
-        H = cached;
+        if (count > 1 || cached <= 0) {
+            const int h = auto_strip_rows(L->n, a.tiles_x * count, k, max_blocks * L->wpb, io);
+            if (count > 1)
+                H = h;
+            else
+                cached = h;
+        }
+        if (count == 1)
+            H = cached;
     }
     H = std::min(H, L->n);
     a.strip_rows = H;
     a.n_tiles = a.tiles_x * ((L->n + H - 1) / H);
-    const int64_t tile_blocks = (a.n_tiles + L->wpb - 1) / L->wpb;
+    const int64_t items = (int64_t)a.n_tiles * count;
+    const int64_t tile_blocks = (items + L->wpb - 1) / L->wpb;
     // Even out the rounds: every wavefront gets ceil(items / waves) items.
     const int64_t rounds = (tile_blocks + max_blocks - 1) / max_blocks;
     int64_t grid = (tile_blocks + rounds - 1) / rounds;
@@ -659,11 +678,39 @@ static int run_pass(bml_lattice *L, int k, int64_t step0, int64_t rec_from)
             grid = max_blocks / 8 * 8;
     }
     a.xcd_split = (grid >= 8 && grid % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(kernels().fn[mode][io][k], dim3((unsigned)grid), dim3(threads), 0, L->stream,
-                       a);
+    hipLaunchKernelGGL(kernels().fn[mode][io][k], dim3((unsigned)grid), dim3(threads), 0,
+                       L->stream, a);
     BML_HIP(hipGetLastError());
-    L->cur ^= 1;
-    L->last_strip_rows = H;
+    for (int i = 0; i < count; ++i) {
+        G[i]->cur ^= 1;
+        G[i]->last_strip_rows = H;
+    }
+    return BML_OK;
+}
+
+// Advances lattices G[0..count) by n_steps in joint launches.
+static int step_group(bml_lattice *const *G, int count, int64_t n_steps)
+{
+    int64_t end[MAX_GROUP], rec_from[MAX_GROUP], s[MAX_GROUP];
+    for (int i = 0; i < count; ++i) {
+        end[i] = G[i]->steps_done + n_steps;
+        // earlier steps of this call would be overwritten in the ring
+        rec_from[i] = end[i] - std::min<int64_t>(n_steps, G[i]->cap);
+        s[i] = G[i]->steps_done;
+    }
+    const int K = G[0]->t_phases / 2;
+    int64_t done = 0;
+    while (done < n_steps) {
+        const int k = (int)std::min<int64_t>(K, n_steps - done);
+        int rc = run_pass(G, count, k, s, rec_from);
+        if (rc)
+            return rc;
+        done += k;
+        for (int i = 0; i < count; ++i) {
+            s[i] += k;
+            G[i]->steps_done = s[i];
+        }
+    }
     return BML_OK;
 }
 
@@ -676,20 +723,35 @@ int bml_step(bml_lattice *L, int64_t n_steps)
         return fail(BML_EINVAL, "n_steps must be >= 0");
     if (n_steps == 0)
         return BML_OK;
-    const int64_t end = L->steps_done + n_steps;
-    const int64_t kept = std::min<int64_t>(n_steps, L->cap);
-    const int64_t rec_from = end - kept;   // earlier steps of this call would be overwritten
-    const int K = L->t_phases / 2;
-    int64_t s = L->steps_done;
-    while (s < end) {
-        const int k = (int)std::min<int64_t>(K, end - s);
-        int rc = run_pass(L, k, s, rec_from);
-        if (rc)
-            return rc;
-        s += k;
-        L->steps_done = s;
+    bml_lattice *G[1] = {L};
+    return step_group(G, 1, n_steps);
+}
+
+int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps)
+{
+    clear_error();
+    if (!handles || count < 1 || count > MAX_GROUP)
+        return fail(BML_EINVAL, "count=%d must be in [1, %d]", count, MAX_GROUP);
+    if (n_steps < 0)
+        return fail(BML_EINVAL, "n_steps must be >= 0");
+    for (int i = 0; i < count; ++i) {
+        if (!live(handles[i]))
+            return fail(BML_ESTATE, "handle %d is invalid", i);
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == handles[i])
+                return fail(BML_EINVAL, "handle %d appears twice", i);
+        const bml_lattice *L0 = handles[0], *Li = handles[i];
+        if (Li->n != L0->n || Li->layout != L0->layout)
+            return fail(BML_EINVAL, "lattice %d differs in size or layout from lattice 0", i);
+        if (Li->tile_rows != L0->tile_rows || Li->t_phases != L0->t_phases ||
+            Li->wpb != L0->wpb)
+            return fail(BML_EINVAL, "lattice %d has another tuning than lattice 0", i);
+        if (Li->stream != L0->stream || Li->dev.device != L0->dev.device)
+            return fail(BML_EINVAL, "lattice %d is on another stream or device", i);
     }
-    return BML_OK;
+    if (n_steps == 0)
+        return BML_OK;
+    return step_group(handles, count, n_steps);
 }
 
 int bml_stats(bml_lattice *L, int64_t first_step, int64_t count, bml_step_stats *out_host)

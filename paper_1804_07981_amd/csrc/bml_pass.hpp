@@ -50,19 +50,32 @@ struct PassScratch {
     uint32_t ticket;
 };
 
-struct PassArgs {
+constexpr int MAX_GROUP = 8;    // lattices advanced by one launch
+
+// One lattice of a launch.
+struct PassLattice {
     const void *src;
     void *dst;
     uint32_t *stats;         // caller's ring, 4 u32 per slot
-    PassScratch *scratch;
+    PassScratch *scratch;    // its stats reduction scratch
+    uint32_t rec_mask;       // bit k set: record the counts of step k of this pass
+    int32_t slot[MAX_K];     // ring slot of step k
+    int32_t pad;
+};
+
+// A launch advances n_lat lattices of the same size and layout by K steps;
+// their work items (strips) are numbered lattice-major in one list, so one
+// grid spreads the strips of all of them evenly over the device.
+struct PassArgs {
+    PassLattice lat[MAX_GROUP];
+    int32_t n_lat;
     int32_t n;               // lattice side
     int32_t words;           // n / 32
     int32_t tiles_x;         // column blocks across a row (62 words each)
-    int32_t n_tiles;         // tiles_x * ceil(n / strip_rows) work items
+    int32_t n_tiles;         // tiles_x * ceil(n / strip_rows) work items per lattice
     int32_t strip_rows;      // output rows per strip
     int32_t xcd_split;       // 1: gridDim.x % 8 == 0, give each XCD a band of tiles
-    uint32_t rec_mask;       // bit k set: record the counts of step k of this pass
-    int32_t slot[MAX_K];     // ring slot of step k
+    uint32_t any_rec;        // OR of the lattices' rec_mask
 };
 
 using PassFn = void (*)(PassArgs);
@@ -137,18 +150,47 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     const uint32_t row_bytes = IO == IO_U8 ? n : (uint32_t)a.words * 4u;
     const uint32_t plane_bytes = row_bytes * n;   // lattice bytes (one plane)
     const uint32_t state_bytes = IO == IO_U8 ? plane_bytes : 2u * plane_bytes;
-    const __amdgpu_buffer_rsrc_t src = make_rsrc(a.src, state_bytes);
-    const __amdgpu_buffer_rsrc_t dst = make_rsrc(a.dst, state_bytes);
     const int H = a.strip_rows;
 
-    uint32_t wtot[K][4];   // wave totals (uniform)
+    // Counts: wave totals (uniform) of the lattice being worked on, moved
+    // to the block's LDS slot of that lattice when the wave changes lattice
+    // and at the end.
+    __shared__ uint32_t red[MAX_GROUP][MAX_K * 4];
+    __shared__ uint32_t is_last;
+    for (int i = threadIdx.x; i < MAX_GROUP * MAX_K * 4; i += blockDim.x)
+        (&red[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t wtot[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k)
         wtot[k][0] = wtot[k][1] = wtot[k][2] = wtot[k][3] = 0;
+    int cur = -1;   // lattice of wtot
+    auto flush = [&]() {
+        if (cur >= 0 && lane == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (wtot[k][q])
+                        atomicAdd(&red[cur][k * 4 + q], wtot[k][q]);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            wtot[k][0] = wtot[k][1] = wtot[k][2] = wtot[k][3] = 0;
+    };
 
-    for (int item = first; item < a.n_tiles; item += total_waves) {
-        const int sy = item / a.tiles_x;
-        const int tx = item - sy * a.tiles_x;
+    const int all_items = a.n_lat * a.n_tiles;
+    for (int item = first; item < all_items; item += total_waves) {
+        const int li = item / a.n_tiles;               // lattice of this item
+        const int local = item - li * a.n_tiles;
+        if (li != cur) {
+            flush();
+            cur = li;
+        }
+        const __amdgpu_buffer_rsrc_t src = make_rsrc(a.lat[li].src, state_bytes);
+        const __amdgpu_buffer_rsrc_t dst = make_rsrc(a.lat[li].dst, state_bytes);
+        const int sy = local / a.tiles_x;
+        const int tx = local - sy * a.tiles_x;
         const int row_a = sy * H;                       // first output row
         const int h = min(H, a.n - row_a);              // output rows of this strip
         const int total_in = h + 2 * K;                 // input rows streamed
@@ -345,51 +387,49 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                 wtot[k][q] += wave_total(lane_ok ? acc[k][q] : 0u);
     }
 
-    // Counts: wave -> block (LDS) -> one of 8 device-wide stripes (block b
-    // adds to stripe b % 8) -> the last block to finish sums the stripes,
-    // writes the ring slots and clears the scratch for the next launch.
-    if (a.rec_mask == 0)
+    // Counts: wave -> block (LDS, per lattice) -> one of 8 device-wide
+    // stripes of each lattice (block b adds to stripe b % 8) -> the last
+    // block to finish sums the stripes, writes the ring slots and clears the
+    // scratch for the next launch.  The launch's ticket lives in the first
+    // lattice's scratch.
+    if (a.any_rec == 0)
         return;
-    __shared__ uint32_t red[MAX_K * 4];
-    __shared__ uint32_t is_last;
-    if (threadIdx.x < MAX_K * 4)
-        red[threadIdx.x] = 0;
+    flush();
     __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (wtot[k][q])
-                    atomicAdd(&red[k * 4 + q], wtot[k][q]);
+    const int n_counts = a.n_lat * K * 4;
+    for (int i = threadIdx.x; i < n_counts; i += blockDim.x) {
+        const int l = i / (K * 4), j = i - l * (K * 4);
+        if (red[l][j])
+            __hip_atomic_fetch_add(&a.lat[l].scratch->acc[blockIdx.x % ACC_STRIPES][0][0] + j,
+                                   red[l][j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // Every thread's stripe additions must be complete before the ticket
+    // says this block is done; the last block reads the stripes only with
+    // atomics, issued after it has seen the final ticket.
+    wait_vector_memory();
     __syncthreads();
-    uint32_t *stripe = &a.scratch->acc[blockIdx.x % ACC_STRIPES][0][0];
-    if (threadIdx.x < K * 4 && red[threadIdx.x])
-        __hip_atomic_fetch_add(&stripe[threadIdx.x], red[threadIdx.x], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
+    PassScratch *const ticket_owner = a.lat[0].scratch;
     if (threadIdx.x == 0) {
-        const uint32_t t = __hip_atomic_fetch_add(&a.scratch->ticket, 1u, __ATOMIC_ACQ_REL,
+        const uint32_t t = __hip_atomic_fetch_add(&ticket_owner->ticket, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
         is_last = (t == gridDim.x - 1) ? 1u : 0u;
     }
     __syncthreads();
     if (!is_last)
         return;
-    if (threadIdx.x < K * 4) {
-        const int k = threadIdx.x >> 2, q = threadIdx.x & 3;
+    for (int i = threadIdx.x; i < n_counts; i += blockDim.x) {
+        const int l = i / (K * 4), j = i - l * (K * 4);
+        const int k = j >> 2, q = j & 3;
         uint32_t sum = 0;
 #pragma unroll
-        for (int st = 0; st < ACC_STRIPES; ++st) {
-            uint32_t *p = &a.scratch->acc[st][k][q];
-            sum += __hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if ((a.rec_mask >> k) & 1u)
-            a.stats[(size_t)a.slot[k] * 4 + q] = sum;
+        for (int st = 0; st < ACC_STRIPES; ++st)
+            sum += __hip_atomic_exchange(&a.lat[l].scratch->acc[st][0][0] + j, 0u,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((a.lat[l].rec_mask >> k) & 1u)
+            a.lat[l].stats[(size_t)a.lat[l].slot[k] * 4 + q] = sum;
     }
     if (threadIdx.x == 0)
-        __hip_atomic_store(&a.scratch->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ticket_owner->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Fills tab[k] (k = KLO..KHI) with pass_kernel<IO, k, ROW>.

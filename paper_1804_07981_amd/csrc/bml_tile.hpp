@@ -37,6 +37,17 @@ __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v)
                                               0xF, 0xF, true);
 }
 
+// Waits until every vector memory operation this wavefront has issued,
+// atomics included, has completed.  The last-block detection of the step
+// kernels communicates only through device-scope atomics (performed at the
+// device's coherence point), so it needs this completion order but no
+// cache-wide write-back or invalidation, which an acquire/release fence at
+// device scope would add on every block (each XCD has its own L2).
+__device__ __forceinline__ void wait_vector_memory()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // Sum of v over the 64 lanes of the wavefront, as a wave-uniform value.
 // DPP adds inside each 16-lane row (swap pairs, swap halves of quads, then
 // rotate the row by 4 and by 8 lanes) leave every lane with its row's sum;

@@ -84,3 +84,9 @@ class Lattice:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def step_group(lattices, n_steps: int) -> None:
+    """Advance lattices of one size, layout and tuning that share a stream
+    by n_steps each, in joint launches (bml_step_group)."""
+    B.bml_step_group([lat.handle for lat in lattices], n_steps)

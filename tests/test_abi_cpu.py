@@ -97,3 +97,14 @@ def test_init_rejects_bad_cell_values_without_gpu(B):
     rc = lib.bml_init(ctypes.byref(h), 64, 0, 0, 0.3, cells.ctypes.data, 1 << 20, 1 << 21,
                       1 << 22, 16, None)
     assert rc == B.BML_EINVAL and "value 3" in B.bml_last_error()
+
+
+def test_step_group_rejects_bad_arguments_without_gpu(B):
+    lib = ctypes.CDLL(B.library_path())
+    lib.bml_step_group.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                   ctypes.c_int64]
+    arr = (ctypes.c_void_p * 9)()
+    assert lib.bml_step_group(None, 1, 1) == B.BML_EINVAL
+    assert lib.bml_step_group(arr, 0, 1) == B.BML_EINVAL
+    assert lib.bml_step_group(arr, 9, 1) == B.BML_EINVAL      # more than 8 lattices
+    assert lib.bml_step_group(arr, 2, 1) == B.BML_ESTATE      # NULL handles

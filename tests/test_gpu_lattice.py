@@ -322,6 +322,78 @@ def test_row_mode_wrap_cars(B, layout, n):
         assert np.array_equal(lat.cells(), lone)
 
 
+# --- joint launches of several lattices (bml_step_group) -------------------
+
+GROUP_CASES = [(4096, BP, (16, 16, 4), 4), (4096, U8, (8, 12, 2), 4), (2144, U8, (0, 6, 4), 3),
+               (224, BP, (24, 16, 1), 8), (2048, U8, (0, 2, 4), 2), (96, U8, (3, 14, 4), 5)]
+
+
+@pytest.mark.parametrize("n,layout,tuning,count", GROUP_CASES,
+                         ids=[f"n{n}_l{l}_vr{t[0]}_t{t[1]}_w{t[2]}_x{c}"
+                              for n, l, t, c in GROUP_CASES])
+def test_step_group_matches_each_alone(B, n, layout, tuning, count):
+    """Lattices advanced together in joint launches, with different
+    histories (some stepped alone first) and stats rings of different sizes,
+    end where the oracle puts each of them, and each ring holds that
+    lattice's own counts."""
+    import torch
+    rng = np.random.default_rng(n * 31 + layout)
+    stream = torch.cuda.Stream()
+    rhos = [0.25, 0.35, 0.38, 0.45, 0.9, 0.1, 0.5, 0.3][:count]
+    seeds = [int(x) for x in rng.integers(0, 2**32, count)]
+    caps = [64, 30, 64, 7, 64, 5, 64, 64][:count]
+    pre = [0, 3, 5, 0, 1, 2, 0, 7][:count]
+    steps = int(rng.integers(1, 3 * tuning[1]))
+    say(f"group n={n} layout={layout} tuning={tuning} count={count} steps={steps}")
+    lats = [B.Lattice(n, r, sd, layout=layout, stats_cap=c, stream=stream)
+            for r, sd, c in zip(rhos, seeds, caps)]
+    try:
+        for lat, p in zip(lats, pre):
+            lat.set_tuning(*tuning)
+            if p:
+                lat.step(p)
+        B.step_group(lats, steps)
+        for lat, r, sd, c, p in zip(lats, rhos, seeds, caps, pre):
+            want, wst = oracle.run(oracle.init_cells(n, sd, r), p + steps, n_threads=HOST_THREADS)
+            assert lat.steps_done == p + steps
+            got = lat.cells()
+            if not np.array_equal(got, want):
+                bad = np.argwhere(got != want)
+                pytest.fail(f"rho={r}: {len(bad)} cells differ, first at {bad[0]}")
+            m = min(c, steps)
+            assert np.array_equal(stats_array(lat.stats(p + steps - m, m)), wst[-m:]), r
+    finally:
+        for lat in lats:
+            lat.close()
+
+
+def test_step_group_rejects_mismatches(B):
+    import torch
+    stream = torch.cuda.Stream()
+    a = B.Lattice(64, 0.3, 1, stream=stream)
+    b = B.Lattice(64, 0.3, 2, stream=stream)
+    c = B.Lattice(96, 0.3, 3, stream=stream)
+    d = B.Lattice(64, 0.3, 4, layout=BP, stream=stream)
+    e = B.Lattice(64, 0.3, 5, stream=torch.cuda.Stream())
+    try:
+        for bad in ([a, a], [a, c], [a, d], [a, e]):
+            with pytest.raises(B.BmlError) as err:
+                B.step_group(bad, 1)
+            assert err.value.code == B.BML_EINVAL
+        b.set_tuning(-1, 4, 0)
+        with pytest.raises(B.BmlError) as err:
+            B.step_group([a, b], 1)
+        assert err.value.code == B.BML_EINVAL
+        assert a.steps_done == 0 and b.steps_done == 0
+        b.set_tuning(-1, a.tuning()[1], 0)
+        B.step_group([a, b], 0)
+        B.step_group([a, b], 2)
+        assert a.steps_done == 2 and b.steps_done == 2
+    finally:
+        for lat in (a, b, c, d, e):
+            lat.close()
+
+
 # --- the 4096 x 4096 workload, whole lattice --------------------------------
 
 @pytest.mark.parametrize("layout", LAYOUTS)

@@ -72,7 +72,7 @@ MEDIUM = Workload(
     tuple(Lattice(4096, r, k + 1) for k, r in enumerate(DENSITIES_4096)),
     10000,
     "four 4096x4096 lattices, uint8 and 2-bitplane forms")
-# Tuning-cache name of the four lattices run concurrently (one stream each).
+# Tuning-cache name of the four lattices advanced together by joint launches.
 MEDIUM_GROUP = "medium4"
 
 # Large single lattice: 32768 x 32768 (1 GiB of uint8 cells), rho 0.30,
