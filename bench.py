@@ -81,6 +81,72 @@ def traffic_from_profile(name: str, launches_bytes: float):
     return d.get("hbm_bytes_per_launch")
 
 
+def _pmc_per_dispatch(csv_dir: str, counter: str) -> dict:
+    """{dispatch id: (kernel name, summed counter value)} from a rocprofv3
+    --pmc output directory."""
+    import csv
+    out = {}
+    for root, _, files in os.walk(csv_dir):
+        for fn in files:
+            if not fn.endswith("counter_collection.csv"):
+                continue
+            with open(os.path.join(root, fn)) as f:
+                for r in csv.DictReader(f):
+                    if r["Counter_Name"] != counter:
+                        continue
+                    d = int(r["Dispatch_Id"])
+                    name, v = out.get(d, (r["Kernel_Name"], 0.0))
+                    out[d] = (name, v + float(r["Counter_Value"]))
+    return out
+
+
+def pmc_summary(probe_log: str, fetch_dir: str, write_dir: str) -> int:
+    """HBM bytes per launch of the step kernel from FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch), each scaled so that the 1 GiB copy the probe runs
+    first reads as 1 GiB fetched and 1 GiB written."""
+    probe = None
+    with open(probe_log) as f:
+        for line in f:
+            if line.startswith("{") and '"probe"' in line:
+                probe = json.loads(line)
+    if probe is None:
+        print("no probe line in " + probe_log, file=sys.stderr)
+        return 1
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        disp = _pmc_per_dispatch(d, counter)
+        copies = [v for name, v in disp.values() if "copy" in name.lower()]
+        passes = [v for name, v in disp.values() if "pass_kernel" in name]
+        if not copies or not passes:
+            print(f"{counter}: copy or pass_kernel dispatches missing", file=sys.stderr)
+            return 1
+        copy_kib = max(copies)
+        res[counter] = {"copy_kib": copy_kib, "scale": (1 << 20) / copy_kib,
+                        "pass_kib_per_dispatch": sum(passes) / len(passes),
+                        "dispatches": len(passes)}
+    layout = 0 if probe["layout"] == "u8" else 1
+    k = probe["t_phases"] // 2
+    alg = bytes_per_cell_step(layout, k) * probe["cells_per_launch"] * k
+    hbm = sum(r["pass_kib_per_dispatch"] * 1024 * r["scale"] for r in res.values())
+    out = {"kernel": f"pass_kernel<{probe['layout']}, K={k}>", "probe": probe,
+           "kernel_hash": probe["kernel_hash"],
+           "fetch_kib_per_dispatch": res["FETCH_SIZE"]["pass_kib_per_dispatch"],
+           "write_kib_per_dispatch": res["WRITE_SIZE"]["pass_kib_per_dispatch"],
+           "copy_calibration": {"bytes": 1 << 30,
+                                "fetch_kib": res["FETCH_SIZE"]["copy_kib"],
+                                "write_kib": res["WRITE_SIZE"]["copy_kib"],
+                                "fetch_scale": res["FETCH_SIZE"]["scale"],
+                                "write_scale": res["WRITE_SIZE"]["scale"]},
+           "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": alg,
+           "ratio_to_algorithmic": hbm / alg,
+           "dispatches": res["FETCH_SIZE"]["dispatches"]}
+    path = os.path.join(PROFILES, f"pass_{probe['layout']}_{probe['n']}.traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+    return 0
+
+
 def cpu_baseline(n: int, rho: float, seed: int, target_s: float = 15.0):
     import oracle
     threads = min(os.cpu_count() or 1, 16)
@@ -191,7 +257,13 @@ def main() -> int:
     ap.add_argument("--probe", action="store_true",
                     help="for counter runs: a 1 GiB device copy (the calibration kernel "
                          "of known traffic), then --steps BML steps of the first lattice")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("PROBE_LOG", "FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU: turn two rocprofv3 --pmc runs of --probe (FETCH_SIZE, "
+                         "WRITE_SIZE) into profiles/pass_<layout>_<n>.traffic.json")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        return pmc_summary(*args.pmc_summary)
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -221,19 +293,25 @@ def main() -> int:
         b.copy_(a)                       # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del a, b
-        lt = wl.lattices[0]
-        lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=max(args.steps, 1),
-                        device=dev)
-        tun = load_tuning(layout, lt.n, group)
-        if tun:
-            lat.set_tuning(*tun)
-        lat.step(args.steps)
+        # the launch shape the benchmark times: all lattices of the workload
+        # in joint launches, with the same tuning
+        stream = torch.cuda.Stream(dev)
+        lats = [B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=max(args.steps, 1),
+                          device=dev, stream=stream) for lt in wl.lattices]
+        tun = load_tuning(layout, wl.lattices[0].n, group)
+        for lat in lats:
+            if tun:
+                lat.set_tuning(*tun)
+        B.step_group(lats, args.steps)
         torch.cuda.synchronize()
-        tr, tp, wpb = lat.tuning()
+        tr, tp, wpb = lats[0].tuning()
         print(json.dumps({"probe": wl.name, "layout": args.layout, "steps": args.steps,
-                          "cells": lt.n * lt.n, "t_phases": tp, "tile_rows": tr,
-                          "waves_per_block": wpb, "kernel_hash": kernel_hash()}), flush=True)
-        lat.close()
+                          "n": wl.lattices[0].n, "lattices_per_launch": len(lats),
+                          "cells_per_launch": sum(lt.n * lt.n for lt in wl.lattices),
+                          "t_phases": tp, "tile_rows": tr, "waves_per_block": wpb,
+                          "kernel_hash": kernel_hash()}), flush=True)
+        for lat in lats:
+            lat.close()
         return 0
 
     def make_lattices(lay, mode):
