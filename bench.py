@@ -46,6 +46,22 @@ def bytes_per_cell_step(layout: int, k: int) -> float:
     return per_cell_pass / k
 
 
+ALU_PEAK_LANE_OPS = 256 * 4 * 64 / 4 * 2.4e9   # CUs x SIMDs x lanes / clocks per op x clock
+
+
+def alu_roofline(layout: int, k: int, gcups: float) -> dict:
+    """Algorithmic lane-ops of the bitwise rule: 9 logic ops per 32-cell
+    word and step plus 4 popcount-adds for the per-step counts; the byte
+    layout adds its in-register conversion, about 80 lane-ops per word per
+    pass of k steps."""
+    per_cell_step = (13 + (80.0 / k if layout == 0 else 0.0)) / 32
+    achieved = gcups * 1e9 * per_cell_step
+    return {"bound": "alu", "achieved": round(achieved / 1e12, 2),
+            "peak": round(ALU_PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
+            "frac": round(achieved / ALU_PEAK_LANE_OPS, 4),
+            "lane_ops_per_cell_step": round(per_cell_step, 4)}
+
+
 def load_tuning(layout: int, n, group: str | None = None):
     """Autotuned (tile_rows, t_phases, waves_per_block): the entry for the
     group of lattices run together (e.g. the four concurrent 4096 lattices),
@@ -396,7 +412,9 @@ def main() -> int:
                           f"{res['lattices_per_launch']} lattice(s) per launch)",
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_us": round(per_launch_s * 1e6, 2),
-                "effective_gbs": round(value * 1e9 * bytes_per_cell_step(layout, 1) / 1e9, 1)}
+                "effective_gbs": round(value * 1e9 * bytes_per_cell_step(layout, 1) / 1e9, 1),
+                # the same launches against the plain-ALU ceiling
+                "alu": alu_roofline(layout, k, value)}
 
     out = {
         "metric": "GCUPS (cell updates/s) + % HBM roofline",
