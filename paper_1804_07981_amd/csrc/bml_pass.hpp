@@ -213,14 +213,19 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         // output row.  Each advance moves one row: one conditional wrap.
         uint32_t ld_off = (uint32_t)((row_a - K + a.n) % a.n) * row_bytes;
         uint32_t st_off = (uint32_t)row_a * row_bytes;
+        // The offsets are wave-uniform; readfirstlane keeps them visibly so
+        // (the compiler may otherwise compute the wrap with vector min/sub
+        // and then wrap every buffer load in a loop over distinct offsets).
         auto advance = [&](uint32_t o) {
             const uint32_t x = o + row_bytes;
-            return x >= plane_bytes ? x - plane_bytes : x;
+            return (uint32_t)__builtin_amdgcn_readfirstlane(
+                (int)(x >= plane_bytes ? x - plane_bytes : x));
         };
         uint32_t ring[D][NW];
         // Row layout in the ring: u8: 8 dwords (32 cells) per word; bp: the
         // WL LR words, then the WL TB words.
-        auto issue = [&](uint32_t (&dstw)[NW], uint32_t off) {
+        auto issue = [&](uint32_t (&dstw)[NW], uint32_t off_) {
+            const uint32_t off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off_);
             if constexpr (IO == IO_U8) {
 #pragma unroll
                 for (int j = 0; j < 2 * WL; ++j) {
@@ -331,6 +336,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 #endif
                 }
                 if (FULL || (t >= 3 * K - 1 && t < 3 * K - 1 + h)) {
+                    const uint32_t so = (uint32_t)__builtin_amdgcn_readfirstlane((int)st_off);
                     if (lane_ok) {
                         if constexpr (IO == IO_U8) {
 #pragma unroll
@@ -338,25 +344,25 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                                 uint32_t b[8];
                                 planes_to_bytes(bl[K - 1][i], bt[K - 1][i], b);
                                 __builtin_amdgcn_raw_buffer_store_b128(
-                                    (u32x4){b[0], b[1], b[2], b[3]}, dst, voff + 32 * i, st_off,
+                                    (u32x4){b[0], b[1], b[2], b[3]}, dst, voff + 32 * i, so,
                                     BML_STORE_AUX);
                                 __builtin_amdgcn_raw_buffer_store_b128(
                                     (u32x4){b[4], b[5], b[6], b[7]}, dst, voff + 32 * i + 16,
-                                    st_off, BML_STORE_AUX);
+                                    so, BML_STORE_AUX);
                             }
                         } else if constexpr (WL == 1) {
-                            __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1][0], dst, voff, st_off,
+                            __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1][0], dst, voff, so,
                                                                   BML_STORE_AUX);
                             __builtin_amdgcn_raw_buffer_store_b32(bt[K - 1][0], dst, voff,
-                                                                  st_off + plane_bytes,
+                                                                  so + plane_bytes,
                                                                   BML_STORE_AUX);
                         } else {
                             __builtin_amdgcn_raw_buffer_store_b64(
-                                (u32x2){bl[K - 1][0], bl[K - 1][1]}, dst, voff, st_off,
+                                (u32x2){bl[K - 1][0], bl[K - 1][1]}, dst, voff, so,
                                 BML_STORE_AUX);
                             __builtin_amdgcn_raw_buffer_store_b64(
                                 (u32x2){bt[K - 1][0], bt[K - 1][1]}, dst, voff,
-                                st_off + plane_bytes, BML_STORE_AUX);
+                                so + plane_bytes, BML_STORE_AUX);
                         }
                     }
                     st_off += row_bytes;
