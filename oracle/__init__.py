@@ -58,6 +58,10 @@ def lib() -> ctypes.CDLL:
         L.bmlo_thresholds.restype = None
         L.bmlo_init_cells.argtypes = [i64, i64, u64, dbl, vp]
         L.bmlo_init_cells.restype = None
+        L.bmlo_thresholds_asym.argtypes = [dbl, dbl, vp, vp]
+        L.bmlo_thresholds_asym.restype = None
+        L.bmlo_init_cells_asym.argtypes = [i64, i64, u64, dbl, dbl, vp]
+        L.bmlo_init_cells_asym.restype = None
         L.bmlo_phase_h.argtypes = [i64, i64, vp, vp]
         L.bmlo_phase_h.restype = i64
         L.bmlo_phase_v.argtypes = [i64, i64, vp, vp]
@@ -105,6 +109,24 @@ def init_cells(n: int, seed: int, rho: float, cols: int | None = None) -> np.nda
     cols = n if cols is None else cols
     out = np.empty((n, cols), dtype=np.uint8)
     lib().bmlo_init_cells(n, cols, seed & (2**64 - 1), float(rho), _ptr(out))
+    return out
+
+
+def thresholds_asym(rho_lr: float, rho_tb: float) -> tuple[int, int]:
+    a = ctypes.c_uint64()
+    b = ctypes.c_uint64()
+    lib().bmlo_thresholds_asym(float(rho_lr), float(rho_tb), ctypes.byref(a), ctypes.byref(b))
+    return int(a.value), int(b.value)
+
+
+def init_cells_asym(rows: int, cols: int, seed: int, rho_lr: float, rho_tb: float
+                    ) -> np.ndarray:
+    """Asymmetric random lattice (Sec. 2's unequal LR/TB numbers): cell
+    i*cols+j is LR w.p. rho_lr, TB w.p. rho_tb, else EMPTY, from the same
+    SplitMix64 draw as init_cells."""
+    out = np.empty((rows, cols), dtype=np.uint8)
+    lib().bmlo_init_cells_asym(rows, cols, seed & (2**64 - 1), float(rho_lr), float(rho_tb),
+                               _ptr(out))
     return out
 
 

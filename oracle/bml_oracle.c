@@ -79,6 +79,29 @@ void bmlo_init_cells(int64_t rows, int64_t cols, uint64_t seed, double rho,
     }
 }
 
+/* Asymmetric placement (Sec. 2 lists an unequal number of LR and TB cars
+ * among the extensions of the model): LR w.p. rho_lr, TB w.p. rho_tb, from
+ * the same uniform u as above: LR if u < floor(rho_lr 2^53), else TB if
+ * u < floor((rho_lr + rho_tb) 2^53).  rho_lr = rho_tb = rho/2 gives exactly
+ * the thresholds of bmlo_thresholds(rho). */
+void bmlo_thresholds_asym(double rho_lr, double rho_tb, uint64_t *thr_lr, uint64_t *thr_tb)
+{
+    *thr_lr = (uint64_t)ldexp(rho_lr, 53);
+    *thr_tb = (uint64_t)ldexp(rho_lr + rho_tb, 53);
+}
+
+void bmlo_init_cells_asym(int64_t rows, int64_t cols, uint64_t seed, double rho_lr,
+                          double rho_tb, uint8_t *cells)
+{
+    uint64_t thr_lr, thr_tb;
+    bmlo_thresholds_asym(rho_lr, rho_tb, &thr_lr, &thr_tb);
+    int64_t total = rows * cols;
+    for (int64_t k = 0; k < total; k++) {
+        uint64_t u = bmlo_splitmix64(seed, (uint64_t)k) >> 11;
+        cells[k] = (u < thr_lr) ? LR : (u < thr_tb) ? TB : EMPTY;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* The two phases.  Each reads only `cur` and writes only `next`            */
 /* (synchronous update, Sec. 3).  Returns the number of cars that moved,    */

@@ -33,6 +33,8 @@ MUTATIONS = [
      "if (c == TB)\n                    b |= 1u << (31 - bit);"),
     ("stats fields swapped", "stats[4 * s + 1] = (uint32_t)moved_lr;",
      "stats[4 * s + 1] = (uint32_t)moved_tb;"),
+    ("asymmetric TB threshold without the LR share", "*thr_tb = (uint64_t)ldexp(rho_lr + rho_tb, 53);",
+     "*thr_tb = (uint64_t)ldexp(rho_tb, 53);"),
 ]
 
 

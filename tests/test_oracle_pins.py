@@ -286,6 +286,48 @@ def test_init_fractions(rho):
         assert abs(frac - p) <= 5 * sigma + 1e-12
 
 
+# --- asymmetric placement (unequal LR and TB numbers, Sec. 2 extensions) ---
+
+def _floor_times_2_53(x: float) -> int:
+    """floor(x * 2^53) in exact rational arithmetic."""
+    from fractions import Fraction
+    return int(Fraction(x) * 2**53)
+
+
+@pytest.mark.parametrize("rho_lr,rho_tb", [(0.1, 0.3), (0.3, 0.1), (0.0, 0.45), (0.25, 0.0),
+                                           (0.6, 0.4), (1 / 3, 1 / 7)])
+def test_asym_thresholds_and_cells(rho_lr, rho_tb):
+    thr_lr, thr_tb = oracle.thresholds_asym(rho_lr, rho_tb)
+    assert thr_lr == _floor_times_2_53(rho_lr)
+    assert thr_tb == _floor_times_2_53(rho_lr + rho_tb)     # the sum rounded as IEEE double
+    g = oracle.init_cells_asym(6, 40, 777, rho_lr, rho_tb)
+    for k in range(g.size):
+        u = oracle.splitmix64(777, k) >> 11
+        want = LR if u < thr_lr else (TB if u < thr_tb else EMPTY)
+        assert g.ravel()[k] == want
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.17, 0.37, 0.5, 1.0])
+def test_asym_with_equal_halves_is_the_symmetric_draw(rho):
+    assert oracle.thresholds_asym(rho / 2, rho / 2) == oracle.thresholds(rho)
+    assert np.array_equal(oracle.init_cells_asym(40, 96, 3, rho / 2, rho / 2),
+                          oracle.init_cells(40, 3, rho, cols=96))
+
+
+@pytest.mark.parametrize("rho_lr,rho_tb", [(0.05, 0.3), (0.35, 0.15), (0.0, 0.2), (0.5, 0.5)])
+def test_asym_fractions(rho_lr, rho_tb):
+    g = oracle.init_cells_asym(256, 384, 41, rho_lr, rho_tb)
+    n = g.size
+    for kind, p in ((LR, rho_lr), (TB, rho_tb)):
+        frac = (g == kind).sum() / n
+        sigma = np.sqrt(max(p * (1 - p), 1e-12) / n)
+        assert abs(frac - p) <= 5 * sigma + 1e-12
+    if rho_lr == 0:
+        assert not (g == LR).any()
+    if rho_lr + rho_tb == 1:
+        assert not (g == EMPTY).any()
+
+
 # --- bitplane definition ---------------------------------------------------
 
 def test_pack_layout_and_roundtrip():
