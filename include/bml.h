@@ -91,11 +91,40 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed,
              void *d_state_b, bml_step_stats *d_stats, int64_t stats_cap,
              void *hip_stream);
 
+/* Rectangular and asymmetric lattices (Sec. 2 lists an unequal number of LR
+ * and TB cars among the model's extensions; the rules of Sec. 2 apply
+ * unchanged to `rows` x `cols` cells with both directions periodic).
+ *   rows         32..65504 (any count); cols: a multiple of 32 in
+ *                [32, 65504].  Cells are row-major, cell k = i*cols + j; a
+ *                bitplane row is cols/32 words, each plane rows*cols/32 words.
+ *   rho_lr, rho_tb  when cells_host is NULL: cell k is LR if
+ *                u < floor(rho_lr * 2^53), else TB if
+ *                u < floor((rho_lr + rho_tb) * 2^53) (the sum rounded as an
+ *                IEEE double), else EMPTY, with u as for bml_init; both >= 0
+ *                and their sum <= 1.  bml_init(n, rho) is exactly
+ *                bml_init_rect(n, n, rho/2, rho/2).
+ * Everything else (buffers, ring, stream, errors, later calls) is as for
+ * bml_init; bml_get_cells returns rows*cols bytes; bml_step_group needs
+ * equal rows and cols. */
+int bml_state_bytes_rect(int32_t rows, int32_t cols, int32_t layout, size_t *bytes);
+int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
+                  uint64_t seed, double rho_lr, double rho_tb, const uint8_t *cells_host,
+                  void *d_state_a, void *d_state_b, bml_step_stats *d_stats,
+                  int64_t stats_cap, void *hip_stream);
+
 /* Advance the lattice by n_steps steps (n_steps >= 0), asynchronously on the
  * handle's stream.  Each kernel pass advances every tile by up to
  * t_phases/2 steps (see bml_set_tuning).  Only the counts of the last
  * min(n_steps, stats_cap) steps of this call are kept in the ring. */
 int bml_step(bml_lattice *L, int64_t n_steps);
+
+/* Device-to-device copy of `bytes` (a multiple of 16) from d_src to d_dst
+ * (256-byte aligned, not overlapping), asynchronously on hip_stream, with a
+ * plain streaming kernel.  Not part of the automaton: it is the bandwidth
+ * reference that benchmarks report next to the step kernels (a kernel that
+ * reads and writes every byte once).  EINVAL on bad arguments, EDEVICE on a
+ * HIP failure. */
+int bml_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream);
 
 /* Advance `count` lattices (1..8) by n_steps each in joint launches: every
  * kernel pass advances all of them, their strips spread over the device as
@@ -116,7 +145,7 @@ int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps);
 int bml_stats(bml_lattice *L, int64_t first_step, int64_t count,
               bml_step_stats *out_host);
 
-/* Copy the current lattice to out_host as N*N row-major bytes (values 0..2),
+/* Copy the current lattice to out_host as N*N (rows*cols) row-major bytes (values 0..2),
  * whatever the layout (a bitplane lattice is unpacked on the device first).
  * Synchronises the stream. */
 int bml_get_cells(bml_lattice *L, uint8_t *out_host);

@@ -48,8 +48,12 @@ _SIGNATURES = {
     "bml_state_bytes": ([_i32, _i32, ctypes.POINTER(_sz)], ctypes.c_int),
     "bml_init": ([ctypes.POINTER(_vp), _i32, _i32, _u64, _dbl, _vp, _vp, _vp, _vp,
                   _i64, _vp], ctypes.c_int),
+    "bml_state_bytes_rect": ([_i32, _i32, _i32, ctypes.POINTER(_sz)], ctypes.c_int),
+    "bml_init_rect": ([ctypes.POINTER(_vp), _i32, _i32, _i32, _u64, _dbl, _dbl, _vp, _vp, _vp,
+                       _vp, _i64, _vp], ctypes.c_int),
     "bml_step": ([_vp, _i64], ctypes.c_int),
     "bml_step_group": ([ctypes.POINTER(_vp), _i32, _i64], ctypes.c_int),
+    "bml_copy": ([_vp, _vp, _sz, _vp], ctypes.c_int),
     "bml_stats": ([_vp, _i64, _i64, _vp], ctypes.c_int),
     "bml_get_cells": ([_vp, _vp], ctypes.c_int),
     "bml_initial_counts": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
@@ -166,8 +170,34 @@ def bml_init(n: int, layout: int, seed: int, rho: float, cells_host, d_state_a,
     return int(h.value)
 
 
+def bml_state_bytes_rect(rows: int, cols: int, layout: int) -> int:
+    out = _sz()
+    _check(lib().bml_state_bytes_rect(rows, cols, layout, ctypes.byref(out)))
+    return int(out.value)
+
+
+def bml_init_rect(rows: int, cols: int, layout: int, seed: int, rho_lr: float, rho_tb: float,
+                  cells_host, d_state_a, d_state_b, d_stats, stats_cap: int, stream) -> int:
+    """Rectangular / asymmetric lattice; returns the opaque handle."""
+    h = _vp()
+    cells = None
+    if cells_host is not None:
+        cells = np.ascontiguousarray(cells_host, dtype=np.uint8)
+        if cells.size != rows * cols:
+            raise BmlError(BML_EINVAL, f"cells_host must hold {rows}*{cols} bytes")
+    _check(lib().bml_init_rect(ctypes.byref(h), rows, cols, layout, seed & (2**64 - 1),
+                               float(rho_lr), float(rho_tb), _ptr(cells), _ptr(d_state_a),
+                               _ptr(d_state_b), _ptr(d_stats), stats_cap, _stream_ptr(stream)))
+    return int(h.value)
+
+
 def bml_step(handle: int, n_steps: int) -> None:
     _check(lib().bml_step(handle, n_steps))
+
+
+def bml_copy(d_dst, d_src, nbytes: int, stream=None) -> None:
+    """Streaming device copy (the bandwidth reference of the benchmarks)."""
+    _check(lib().bml_copy(_ptr(d_dst), _ptr(d_src), nbytes, _stream_ptr(stream)))
 
 
 def bml_step_group(handles, n_steps: int) -> None:
@@ -187,8 +217,8 @@ def bml_stats(handle: int, first_step: int, count: int, check: bool = True) -> n
     return out
 
 
-def bml_get_cells(handle: int, n: int) -> np.ndarray:
-    out = np.empty((n, n), dtype=np.uint8)
+def bml_get_cells(handle: int, n: int, cols: int | None = None) -> np.ndarray:
+    out = np.empty((n, n if cols is None else cols), dtype=np.uint8)
     _check(lib().bml_get_cells(handle, out.ctypes.data))
     return out
 

@@ -356,9 +356,10 @@ int bml_batch_init(bml_batch **out, int32_t count, const int32_t *n, const doubl
         hipMalloc(&B->d_counts, (size_t)count * 2 * sizeof(unsigned long long)) != hipSuccess)
         return bail(fail(BML_EDEVICE, "hipMalloc of batch scratch failed"));
     for (int b = 0; b < count; ++b) {
-        if ((rc = launch_init(B->buf[0][b], n[b], layout, seed[b], rho[b], B->stream)))
+        if ((rc = launch_init(B->buf[0][b], n[b], n[b], layout, seed[b], rho[b] * 0.5, rho[b] * 0.5,
+                               B->stream)))
             return bail(rc);
-        if ((rc = launch_count(B->buf[0][b], n[b], layout, B->d_counts + 2 * b, B->stream)))
+        if ((rc = launch_count(B->buf[0][b], n[b], n[b], layout, B->d_counts + 2 * b, B->stream)))
             return bail(rc);
     }
     std::vector<unsigned long long> h((size_t)count * 2);
@@ -543,7 +544,7 @@ int bml_batch_get_cells(bml_batch *B, int32_t idx, uint8_t *out_host)
     }
     void *tmp = nullptr;
     BML_HIP(hipMalloc(&tmp, cells));
-    bool ok = launch_unpack((const uint32_t *)state, (uint8_t *)tmp, n, B->stream) == BML_OK &&
+    bool ok = launch_unpack((const uint32_t *)state, (uint8_t *)tmp, n, n, B->stream) == BML_OK &&
               hipMemcpyAsync(out_host, tmp, cells, hipMemcpyDeviceToHost, B->stream) ==
                   hipSuccess &&
               hipStreamSynchronize(B->stream) == hipSuccess;
@@ -559,7 +560,7 @@ int bml_batch_check(bml_batch *B)
     if (!batch_live(B))
         return fail(BML_ESTATE, "invalid batch handle");
     for (int b = 0; b < B->count; ++b) {
-        int rc = launch_count(B->buf[lattice_parity(B, b)][b], B->n[b], B->layout,
+        int rc = launch_count(B->buf[lattice_parity(B, b)][b], B->n[b], B->n[b], B->layout,
                               B->d_counts + 2 * b, B->stream);
         if (rc)
             return rc;

@@ -213,9 +213,9 @@ struct KernelTable {
 };
 
 // Row mode when a row is exactly 64 or 128 words (one wavefront).
-static int pass_mode(int n)
+static int pass_mode(int cols)
 {
-    const int words = n / 32;
+    const int words = cols / 32;
     return words == 64 ? 1 : words == 128 ? 2 : 0;
 }
 
@@ -269,29 +269,30 @@ int launch_zero(uint32_t *p, int64_t words, hipStream_t stream)
     return BML_OK;
 }
 
-int launch_init(void *state, int32_t n, int32_t layout, uint64_t seed, double rho,
-                hipStream_t stream)
+int launch_init(void *state, int32_t rows, int32_t cols, int32_t layout, uint64_t seed,
+                double rho_lr, double rho_tb, hipStream_t stream)
 {
-    const int32_t words = n / 32;
+    const int32_t words = cols / 32;
     unsigned grid;
-    int rc = launch_1d_grid((int64_t)n * words, 256, &grid);
+    int rc = launch_1d_grid((int64_t)rows * words, 256, &grid);
     if (rc)
         return rc;
-    // Thresholds on the 53-bit uniform, truncated from IEEE double.
-    const uint64_t thr_lr = (uint64_t)ldexp(rho * 0.5, 53);
-    const uint64_t thr_tb = (uint64_t)ldexp(rho, 53);
+    // Thresholds on the 53-bit uniform, truncated from IEEE double: LR below
+    // rho_lr, TB below rho_lr + rho_tb (for rho/2 each: rho/2 and rho).
+    const uint64_t thr_lr = (uint64_t)ldexp(rho_lr, 53);
+    const uint64_t thr_tb = (uint64_t)ldexp(rho_lr + rho_tb, 53);
     if (layout == BML_LAYOUT_U8)
-        hipLaunchKernelGGL(init_kernel<IO_U8>, dim3(grid), dim3(256), 0, stream, state, n, words,
-                           seed, thr_lr, thr_tb);
+        hipLaunchKernelGGL(init_kernel<IO_U8>, dim3(grid), dim3(256), 0, stream, state, rows,
+                           words, seed, thr_lr, thr_tb);
     else
-        hipLaunchKernelGGL(init_kernel<IO_BP>, dim3(grid), dim3(256), 0, stream, state, n, words,
-                           seed, thr_lr, thr_tb);
+        hipLaunchKernelGGL(init_kernel<IO_BP>, dim3(grid), dim3(256), 0, stream, state, rows,
+                           words, seed, thr_lr, thr_tb);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
 
-int launch_count(const void *state, int32_t n, int32_t layout, unsigned long long *counts,
-                 hipStream_t stream)
+int launch_count(const void *state, int32_t rows, int32_t cols, int32_t layout,
+                 unsigned long long *counts, hipStream_t stream)
 {
     int rc = launch_zero((uint32_t *)counts, 4, stream);
     if (rc)
@@ -299,7 +300,7 @@ int launch_count(const void *state, int32_t n, int32_t layout, unsigned long lon
     DeviceInfo dev;
     if ((rc = device_info(&dev)))
         return rc;
-    const int64_t total_words = (int64_t)n * (n / 32);
+    const int64_t total_words = (int64_t)rows * (cols / 32);
     const unsigned grid =
         (unsigned)std::max<int64_t>(1, std::min<int64_t>((total_words + 255) / 256,
                                                          (int64_t)dev.cu_count * 8));
@@ -313,9 +314,10 @@ int launch_count(const void *state, int32_t n, int32_t layout, unsigned long lon
     return BML_OK;
 }
 
-int launch_pack(const uint8_t *cells, uint32_t *planes, int32_t n, hipStream_t stream)
+int launch_pack(const uint8_t *cells, uint32_t *planes, int32_t rows, int32_t cols,
+                hipStream_t stream)
 {
-    const int64_t total_words = (int64_t)n * (n / 32);
+    const int64_t total_words = (int64_t)rows * (cols / 32);
     unsigned grid;
     int rc = launch_1d_grid(total_words, 256, &grid);
     if (rc)
@@ -326,9 +328,10 @@ int launch_pack(const uint8_t *cells, uint32_t *planes, int32_t n, hipStream_t s
     return BML_OK;
 }
 
-int launch_unpack(const uint32_t *planes, uint8_t *cells, int32_t n, hipStream_t stream)
+int launch_unpack(const uint32_t *planes, uint8_t *cells, int32_t rows, int32_t cols,
+                  hipStream_t stream)
 {
-    const int64_t total_words = (int64_t)n * (n / 32);
+    const int64_t total_words = (int64_t)rows * (cols / 32);
     unsigned grid;
     int rc = launch_1d_grid(total_words, 256, &grid);
     if (rc)
@@ -348,7 +351,7 @@ int launch_unpack(const uint32_t *planes, uint8_t *cells, int32_t n, hipStream_t
 using namespace bml;
 
 struct bml_lattice {
-    int32_t n = 0, layout = 0;
+    int32_t rows = 0, cols = 0, layout = 0;
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
     uint32_t *stats = nullptr;
@@ -377,7 +380,7 @@ static bool live(const bml_lattice *L)
 
 static int count_cars(bml_lattice *L, const void *state, uint64_t *n_lr, uint64_t *n_tb)
 {
-    int rc = launch_count(state, L->n, L->layout, L->d_counts, L->stream);
+    int rc = launch_count(state, L->rows, L->cols, L->layout, L->d_counts, L->stream);
     if (rc)
         return rc;
     unsigned long long h[2] = {0, 0};
@@ -392,19 +395,78 @@ extern "C" {
 
 const char *bml_last_error(void) { return g_err; }
 
-int bml_state_bytes(int32_t n, int32_t layout, size_t *bytes)
+int bml_state_bytes_rect(int32_t rows, int32_t cols, int32_t layout, size_t *bytes)
 {
     clear_error();
     if (!bytes)
         return fail(BML_EINVAL, "bytes is NULL");
-    if (!valid_n(n))
-        return fail(BML_EINVAL, "n=%d must be a multiple of 32 in [32, 65504]", n);
+    if (!valid_shape(rows, cols))
+        return fail(BML_EINVAL,
+                    "%d x %d: rows must be in [32, 65504], columns a multiple of 32 in "
+                    "[32, 65504]", rows, cols);
     if (layout == BML_LAYOUT_U8)
-        *bytes = (size_t)n * n;
+        *bytes = (size_t)rows * cols;
     else if (layout == BML_LAYOUT_BITPLANE)
-        *bytes = (size_t)n * n / 4;
+        *bytes = (size_t)rows * cols / 4;
     else
         return fail(BML_EINVAL, "unknown layout %d", layout);
+    return BML_OK;
+}
+
+int bml_state_bytes(int32_t n, int32_t layout, size_t *bytes)
+{
+    clear_error();
+    if (!valid_n(n)) {
+        if (bytes)
+            *bytes = 0;
+        return fail(BML_EINVAL, "n=%d must be a multiple of 32 in [32, 65504]", n);
+    }
+    return bml_state_bytes_rect(n, n, layout, bytes);
+}
+
+// Plain streaming copy: the memory-bandwidth reference the benchmark
+// reports next to the step kernels (what a kernel that only reads and
+// writes each byte once reaches on this device).  Grid-stride, four
+// 16-byte loads in flight per thread before their stores.
+__global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src,
+                                                   uint4 *__restrict__ dst, int64_t n16)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                    d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+int bml_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream)
+{
+    clear_error();
+    if (!d_dst || !d_src)
+        return fail(BML_EINVAL, "bml_copy: NULL buffer");
+    if (!aligned256(d_dst) || !aligned256(d_src) || bytes % 16)
+        return fail(BML_EINVAL, "bml_copy: buffers must be 256-byte aligned and bytes a "
+                                "multiple of 16");
+    const uintptr_t d = (uintptr_t)d_dst, s = (uintptr_t)d_src;
+    if (d < s + bytes && s < d + bytes)
+        return fail(BML_EINVAL, "bml_copy: buffers overlap");
+    if (bytes == 0)
+        return BML_OK;
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc)
+        return rc;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int64_t blocks = std::min<int64_t>((int64_t)dev.cu_count * 8, (n16 + 255) / 256);
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)hip_stream, (const uint4 *)d_src, (uint4 *)d_dst, n16);
+    BML_HIP(hipGetLastError());
     return BML_OK;
 }
 
@@ -444,16 +506,17 @@ int bml_unpack(int32_t n, const uint32_t *d_planes, uint8_t *d_cells, void *hip_
     return BML_OK;
 }
 
-int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double rho,
-             const uint8_t *cells_host, void *d_state_a, void *d_state_b,
-             bml_step_stats *d_stats, int64_t stats_cap, void *hip_stream)
+int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout, uint64_t seed,
+                  double rho_lr, double rho_tb, const uint8_t *cells_host, void *d_state_a,
+                  void *d_state_b, bml_step_stats *d_stats, int64_t stats_cap,
+                  void *hip_stream)
 {
     clear_error();
     if (!out)
         return fail(BML_EINVAL, "out is NULL");
     *out = nullptr;
     size_t bytes = 0;
-    int rc = bml_state_bytes(n, layout, &bytes);
+    int rc = bml_state_bytes_rect(rows, cols, layout, &bytes);
     if (rc)
         return rc;
     if (!d_state_a || !d_state_b || !d_stats)
@@ -469,10 +532,11 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
     }
     if (stats_cap < 1 || stats_cap > 0x7fffffff)
         return fail(BML_EINVAL, "stats_cap=%lld must be in [1, 2^31-1]", (long long)stats_cap);
-    if (!cells_host && !(rho >= 0.0 && rho <= 1.0))
-        return fail(BML_EINVAL, "rho must be in [0, 1]");
+    if (!cells_host && !(rho_lr >= 0.0 && rho_tb >= 0.0 && rho_lr + rho_tb <= 1.0))
+        return fail(BML_EINVAL, "densities must be >= 0 with a sum in [0, 1]");
+    const size_t n_cells = (size_t)rows * cols;
     if (cells_host) {
-        for (size_t k = 0; k < (size_t)n * n; ++k)
+        for (size_t k = 0; k < n_cells; ++k)
             if (cells_host[k] > 2)
                 return fail(BML_EINVAL, "cell %zu has value %d (must be 0, 1 or 2)", k,
                             (int)cells_host[k]);
@@ -481,7 +545,8 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
     bml_lattice *L = new (std::nothrow) bml_lattice();
     if (!L)
         return fail(BML_EDEVICE, "out of host memory");
-    L->n = n;
+    L->rows = rows;
+    L->cols = cols;
     L->layout = layout;
     L->buf[0] = d_state_a;
     L->buf[1] = d_state_b;
@@ -513,7 +578,7 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
         return cleanup(rc);
 
     if (!cells_host) {
-        if ((rc = launch_init(d_state_a, n, layout, seed, rho, L->stream)))
+        if ((rc = launch_init(d_state_a, rows, cols, layout, seed, rho_lr, rho_tb, L->stream)))
             return cleanup(rc);
     } else if (layout == BML_LAYOUT_U8) {
         if (hipMemcpyAsync(d_state_a, cells_host, bytes, hipMemcpyHostToDevice, L->stream) !=
@@ -523,12 +588,12 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
         // The byte lattice is 4x larger than a bitplane state buffer, so it
         // is staged in a temporary device buffer and packed from there.
         void *tmp = nullptr;
-        if (hipMalloc(&tmp, (size_t)n * n) != hipSuccess)
+        if (hipMalloc(&tmp, n_cells) != hipSuccess)
             return cleanup(fail(BML_EDEVICE, "hipMalloc of the staging buffer failed"));
-        bool ok = hipMemcpyAsync(tmp, cells_host, (size_t)n * n, hipMemcpyHostToDevice,
+        bool ok = hipMemcpyAsync(tmp, cells_host, n_cells, hipMemcpyHostToDevice,
                                  L->stream) == hipSuccess &&
-                  launch_pack((const uint8_t *)tmp, (uint32_t *)d_state_a, n, L->stream) ==
-                      BML_OK &&
+                  launch_pack((const uint8_t *)tmp, (uint32_t *)d_state_a, rows, cols,
+                              L->stream) == BML_OK &&
                   hipStreamSynchronize(L->stream) == hipSuccess;
         (void)hipFree(tmp);
         if (!ok)
@@ -542,6 +607,22 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
     }
     *out = L;
     return BML_OK;
+}
+
+int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double rho,
+             const uint8_t *cells_host, void *d_state_a, void *d_state_b,
+             bml_step_stats *d_stats, int64_t stats_cap, void *hip_stream)
+{
+    clear_error();
+    if (out)
+        *out = nullptr;
+    if (!valid_n(n))
+        return fail(BML_EINVAL, "n=%d must be a multiple of 32 in [32, 65504]", n);
+    if (!cells_host && !(rho >= 0.0 && rho <= 1.0))
+        return fail(BML_EINVAL, "rho must be in [0, 1]");
+    // rho/2 + rho/2 == rho exactly, so these are the symmetric thresholds.
+    return bml_init_rect(out, n, n, layout, seed, rho * 0.5, rho * 0.5, cells_host, d_state_a,
+                         d_state_b, d_stats, stats_cap, hip_stream);
 }
 
 int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases, int32_t waves_per_block)
@@ -638,9 +719,9 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
             }
         a.any_rec |= pl.rec_mask;
     }
-    a.n = L->n;
-    a.words = L->n / 32;
-    const int mode = pass_mode(L->n);
+    a.rows = L->rows;
+    a.words = L->cols / 32;
+    const int mode = pass_mode(L->cols);
     a.tiles_x = mode ? 1 : (a.words + TILE_WORDS - 1) / TILE_WORDS;
     const int threads = 64 * L->wpb;
     int per_cu = 1;
@@ -655,7 +736,7 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
     if (H <= 0) {
         int32_t &cached = L->auto_rows[k][L->wpb == 1 ? 0 : L->wpb == 2 ? 1 : 2];
         if (count > 1 || cached <= 0) {
-            const int h = auto_strip_rows(L->n, a.tiles_x * count, k, max_blocks * L->wpb, io);
+            const int h = auto_strip_rows(L->rows, a.tiles_x * count, k, max_blocks * L->wpb, io);
             if (count > 1)
                 H = h;
             else
@@ -664,9 +745,9 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
         if (count == 1)
             H = cached;
     }
-    H = std::min(H, L->n);
+    H = std::min(H, L->rows);
     a.strip_rows = H;
-    a.n_tiles = a.tiles_x * ((L->n + H - 1) / H);
+    a.n_tiles = a.tiles_x * ((L->rows + H - 1) / H);
     const int64_t items = (int64_t)a.n_tiles * count;
     const int64_t tile_blocks = (items + L->wpb - 1) / L->wpb;
     // Even out the rounds: every wavefront gets ceil(items / waves) items.
@@ -741,7 +822,7 @@ int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps)
             if (handles[j] == handles[i])
                 return fail(BML_EINVAL, "handle %d appears twice", i);
         const bml_lattice *L0 = handles[0], *Li = handles[i];
-        if (Li->n != L0->n || Li->layout != L0->layout)
+        if (Li->rows != L0->rows || Li->cols != L0->cols || Li->layout != L0->layout)
             return fail(BML_EINVAL, "lattice %d differs in size or layout from lattice 0", i);
         if (Li->tile_rows != L0->tile_rows || Li->t_phases != L0->t_phases ||
             Li->wpb != L0->wpb)
@@ -791,7 +872,7 @@ int bml_get_cells(bml_lattice *L, uint8_t *out_host)
         return fail(BML_ESTATE, "invalid handle");
     if (!out_host)
         return fail(BML_EINVAL, "out_host is NULL");
-    const size_t cells = (size_t)L->n * L->n;
+    const size_t cells = (size_t)L->rows * L->cols;
     if (L->layout == BML_LAYOUT_U8) {
         BML_HIP(hipMemcpyAsync(out_host, L->buf[L->cur], cells, hipMemcpyDeviceToHost,
                                L->stream));
@@ -800,7 +881,7 @@ int bml_get_cells(bml_lattice *L, uint8_t *out_host)
     }
     void *tmp = nullptr;
     BML_HIP(hipMalloc(&tmp, cells));
-    const int64_t total_words = (int64_t)L->n * (L->n / 32);
+    const int64_t total_words = (int64_t)L->rows * (L->cols / 32);
     unsigned grid;
     int rc = launch_1d_grid(total_words, 256, &grid);
     if (rc) {

@@ -12,7 +12,7 @@
 //
 // Columns: in tile mode a wavefront covers 62 words (lanes 1..62) plus a
 // halo word on each side (lanes 0 and 63), whose edge bits go stale one cell
-// per step, far from the exact words for K <= 8.  In row mode (N = 2048 or
+// per step, far from the exact words for K <= 8.  In row mode (rows of 2048 or
 // 4096) the wavefront holds a whole row, one or two words per lane, and the
 // lane moves wrap around the wavefront, so x is periodic with no halo lanes
 // and no tile of a row is left partly used.
@@ -69,8 +69,8 @@ struct PassLattice {
 struct PassArgs {
     PassLattice lat[MAX_GROUP];
     int32_t n_lat;
-    int32_t n;               // lattice side
-    int32_t words;           // n / 32
+    int32_t rows;            // lattice rows
+    int32_t words;           // 32-cell words per row (columns / 32)
     int32_t tiles_x;         // column blocks across a row (62 words each)
     int32_t n_tiles;         // tiles_x * ceil(n / strip_rows) work items per lattice
     int32_t strip_rows;      // output rows per strip
@@ -119,10 +119,10 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #define BML_BP_RING2 2
 #endif
 
-// ROW = 0: tile mode, any N; a wavefront covers 62 words plus a halo lane
-// on each side.  ROW = m > 0: row mode for N = 2048 m; the wavefront holds a
-// whole row, m words per lane, and the lane moves wrap around it (periodic
-// in x without halo lanes, every lane exact).
+// ROW = 0: tile mode, any row length; a wavefront covers 62 words plus a
+// halo lane on each side.  ROW = m > 0: row mode for rows of 2048 m cells;
+// the wavefront holds a whole row, m words per lane, and the lane moves wrap
+// around it (periodic in x without halo lanes, every lane exact).
 template <int IO, int K, int ROW>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
@@ -146,9 +146,8 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     } else {
         first = blockIdx.x * wpb + wave;
     }
-    const uint32_t n = (uint32_t)a.n;
-    const uint32_t row_bytes = IO == IO_U8 ? n : (uint32_t)a.words * 4u;
-    const uint32_t plane_bytes = row_bytes * n;   // lattice bytes (one plane)
+    const uint32_t row_bytes = (uint32_t)a.words * (IO == IO_U8 ? 32u : 4u);
+    const uint32_t plane_bytes = row_bytes * (uint32_t)a.rows;   // lattice bytes (one plane)
     const uint32_t state_bytes = IO == IO_U8 ? plane_bytes : 2u * plane_bytes;
     const int H = a.strip_rows;
 
@@ -192,7 +191,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         const int sy = local / a.tiles_x;
         const int tx = local - sy * a.tiles_x;
         const int row_a = sy * H;                       // first output row
-        const int h = min(H, a.n - row_a);              // output rows of this strip
+        const int h = min(H, a.rows - row_a);           // output rows of this strip
         const int total_in = h + 2 * K;                 // input rows streamed
         const int total_it = h + 3 * K - 1;             // pipeline iterations
         uint32_t word;   // first word of this lane
@@ -211,7 +210,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         // Byte offset of input row t (lattice row row_a - K + t, periodic).
         // `ld_off` runs D rows ahead of the pipeline; `st_off` is the next
         // output row.  Each advance moves one row: one conditional wrap.
-        uint32_t ld_off = (uint32_t)((row_a - K + a.n) % a.n) * row_bytes;
+        uint32_t ld_off = (uint32_t)((row_a - K + a.rows) % a.rows) * row_bytes;
         uint32_t st_off = (uint32_t)row_a * row_bytes;
         // The offsets are wave-uniform; readfirstlane keeps them visibly so
         // (the compiler may otherwise compute the wrap with vector min/sub

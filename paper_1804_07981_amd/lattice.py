@@ -9,29 +9,46 @@ from . import _lib as B
 
 
 class Lattice:
-    """An N x N periodic BML lattice resident in device memory.
+    """A periodic BML lattice resident in device memory: n x n, or n rows of
+    `cols` cells.
 
     Cells start from SplitMix64 stream `seed` at density `rho` (LR and TB
-    each with probability rho/2), or from `cells` (N x N bytes 0/1/2).
+    each with probability rho/2), or with LR / TB probabilities `rho_lr` /
+    `rho_tb` when given (the asymmetric draw), or from `cells` (rows x cols
+    bytes 0/1/2).
     """
 
     def __init__(self, n: int, rho: float = 0.3, seed: int = 0, *,
                  layout: int = B.BML_LAYOUT_U8, cells: np.ndarray | None = None,
                  stats_cap: int = 4096, device: str | torch.device = "cuda",
-                 stream: torch.cuda.Stream | None = None):
-        self.n = int(n)
+                 stream: torch.cuda.Stream | None = None, cols: int | None = None,
+                 rho_lr: float | None = None, rho_tb: float | None = None):
+        self.n = self.rows = int(n)
+        self.cols = self.rows if cols is None else int(cols)
         self.layout = int(layout)
         self.device = torch.device(device)
-        nbytes = B.bml_state_bytes(self.n, self.layout)
+        square = self.cols == self.rows and rho_lr is None and rho_tb is None
+        nbytes = (B.bml_state_bytes(self.rows, self.layout) if square else
+                  B.bml_state_bytes_rect(self.rows, self.cols, self.layout))
         self.stream = stream or torch.cuda.current_stream(self.device)
         self._bufs = [torch.empty(nbytes, dtype=torch.uint8, device=self.device)
                       for _ in range(2)]
         self.stats_cap = int(stats_cap)
         self._stats = torch.zeros(self.stats_cap * 4, dtype=torch.int32, device=self.device)
+        # the ring's zero fill runs on the current stream; the library works
+        # on self.stream, so the fill must be done before the first step
+        torch.cuda.current_stream(self.device).synchronize()
         with torch.cuda.device(self.device):
-            self.handle = B.bml_init(self.n, self.layout, seed, rho, cells,
-                                     self._bufs[0], self._bufs[1], self._stats,
-                                     self.stats_cap, self.stream)
+            if square:
+                self.handle = B.bml_init(self.rows, self.layout, seed, rho, cells,
+                                         self._bufs[0], self._bufs[1], self._stats,
+                                         self.stats_cap, self.stream)
+            else:
+                lr = rho / 2 if rho_lr is None else rho_lr
+                tb = rho / 2 if rho_tb is None else rho_tb
+                self.handle = B.bml_init_rect(self.rows, self.cols, self.layout, seed, lr, tb,
+                                              cells, self._bufs[0], self._bufs[1], self._stats,
+                                              self.stats_cap, self.stream)
 
     # -- ABI passthroughs -------------------------------------------------
     def step(self, n_steps: int = 1) -> None:
@@ -47,7 +64,7 @@ class Lattice:
         return B.bml_stats(self.handle, first_step, count, check=check)
 
     def cells(self) -> np.ndarray:
-        return B.bml_get_cells(self.handle, self.n)
+        return B.bml_get_cells(self.handle, self.rows, self.cols)
 
     def set_tuning(self, tile_rows: int = -1, t_phases: int = 0,
                    waves_per_block: int = 0) -> None:

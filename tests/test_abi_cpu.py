@@ -108,3 +108,35 @@ def test_step_group_rejects_bad_arguments_without_gpu(B):
     assert lib.bml_step_group(arr, 0, 1) == B.BML_EINVAL
     assert lib.bml_step_group(arr, 9, 1) == B.BML_EINVAL      # more than 8 lattices
     assert lib.bml_step_group(arr, 2, 1) == B.BML_ESTATE      # NULL handles
+
+
+def test_copy_rejects_bad_arguments_without_gpu(B):
+    lib = ctypes.CDLL(B.library_path())
+    lib.bml_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    assert lib.bml_copy(None, None, 16, None) == B.BML_EINVAL
+    assert lib.bml_copy(256, 512, 8, None) == B.BML_EINVAL          # not a multiple of 16
+    assert lib.bml_copy(256 + 16, 4096, 16, None) == B.BML_EINVAL   # misaligned
+    assert lib.bml_copy(4096, 4096 + 256, 512, None) == B.BML_EINVAL  # overlapping
+
+
+@pytest.mark.parametrize("rows,cols,layout", [(31, 64, 0), (64, 48, 0), (65505, 32, 1),
+                                              (64, 65536, 0), (64, 64, 2)])
+def test_state_bytes_rect_rejects(B, rows, cols, layout):
+    with pytest.raises(B.BmlError) as e:
+        B.bml_state_bytes_rect(rows, cols, layout)
+    assert e.value.code == B.BML_EINVAL
+
+
+def test_state_bytes_rect(B):
+    assert B.bml_state_bytes_rect(33, 4096, 0) == 33 * 4096
+    assert B.bml_state_bytes_rect(33, 4096, 1) == 33 * 4096 // 4
+    assert B.bml_state_bytes_rect(64, 64, 1) == B.bml_state_bytes(64, 1)
+
+
+def test_init_rect_rejects_bad_densities_without_gpu(B):
+    lib = B.lib()
+    h = ctypes.c_void_p()
+    for lr, tb in ((-0.1, 0.2), (0.6, 0.5), (float("nan"), 0.1), (0.1, float("nan"))):
+        rc = lib.bml_init_rect(ctypes.byref(h), 64, 64, 0, 1, lr, tb, None, 256, 512 * 1024,
+                               1024 * 1024, 8, None)
+        assert rc == B.BML_EINVAL, (lr, tb)

@@ -394,6 +394,72 @@ def test_step_group_rejects_mismatches(B):
             lat.close()
 
 
+# --- rectangular lattices, unequal LR / TB densities ---------------------
+
+RECT_CASES = [(32, 64, 0.1, 0.3), (96, 160, 0.3, 0.1), (200, 2048, 0.2, 0.15),
+              (33, 4096, 0.05, 0.4), (1000, 96, 0.0, 0.5), (64, 3008, 0.45, 0.45),
+              (517, 224, 0.25, 0.0)]
+RECT_TUNINGS = [(0, 16, 4), (8, 6, 2), (24, 2, 1)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("rows,cols,rho_lr,rho_tb", RECT_CASES,
+                         ids=[f"{r}x{c}_lr{a}_tb{b}" for r, c, a, b in RECT_CASES])
+def test_rect_asym_matches_oracle(B, layout, rows, cols, rho_lr, rho_tb):
+    """rows x cols lattices (rows not a multiple of 32, row-mode widths with
+    rows != cols, tile-mode widths) with unequal LR / TB densities: the
+    initial draw, then every cell and count after runs under several
+    tunings, against the oracle's asymmetric draw and run."""
+    rng = np.random.default_rng(rows * 7919 + cols + layout)
+    seed = int(rng.integers(0, 2**32))
+    g0 = oracle.init_cells_asym(rows, cols, seed, rho_lr, rho_tb)
+    for tuning in RECT_TUNINGS:
+        steps = int(rng.integers(1, 2 * tuning[1] + 3))
+        say(f"rect {rows}x{cols} lr={rho_lr} tb={rho_tb} layout={layout} tuning={tuning} "
+            f"steps={steps} seed={seed}")
+        want, wst = oracle.run(g0, steps, n_threads=HOST_THREADS)
+        with B.Lattice(rows, seed=seed, cols=cols, rho_lr=rho_lr, rho_tb=rho_tb, layout=layout,
+                       stats_cap=64) as lat:
+            assert np.array_equal(lat.cells(), g0)
+            assert lat.initial_counts() == (oracle.count(g0, 1), oracle.count(g0, 2))
+            lat.set_tuning(*tuning)
+            lat.step(steps)
+            got = lat.cells()
+            if not np.array_equal(got, want):
+                bad = np.argwhere(got != want)
+                pytest.fail(f"{len(bad)} cells differ, first at {bad[0]}")
+            assert np.array_equal(stats_array(lat.stats(0, steps)), wst)
+
+
+def test_rect_equal_halves_is_the_square_draw(B):
+    with B.Lattice(256, 0.37, 11) as a, \
+            B.Lattice(256, seed=11, cols=256, rho_lr=0.37 / 2, rho_tb=0.37 / 2) as b:
+        assert np.array_equal(a.cells(), b.cells())
+
+
+def test_rect_group_and_host_cells(B):
+    """Rectangular lattices in joint launches, one of them from host cells."""
+    import torch
+    rows, cols, steps = 300, 2048, 21
+    stream = torch.cuda.Stream()
+    g1 = oracle.init_cells_asym(rows, cols, 5, 0.2, 0.25)
+    hand = np.zeros((rows, cols), np.uint8)
+    hand[7, cols - 1] = 1
+    hand[rows - 1, 9] = 2
+    hand[100, 1000:1010] = 1
+    lats = [B.Lattice(rows, seed=5, cols=cols, rho_lr=0.2, rho_tb=0.25, stream=stream),
+            B.Lattice(rows, cols=cols, cells=hand, layout=U8, stream=stream)]
+    try:
+        B.step_group(lats, steps)
+        for lat, g in zip(lats, (g1, hand)):
+            want, wst = oracle.run(g, steps, n_threads=HOST_THREADS)
+            assert np.array_equal(lat.cells(), want)
+            assert np.array_equal(stats_array(lat.stats(0, steps)), wst)
+    finally:
+        for lat in lats:
+            lat.close()
+
+
 # --- the 4096 x 4096 workload, whole lattice --------------------------------
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -446,3 +512,16 @@ def test_large_sampled_windows(B, layout):
         ref, _ = oracle.run(pad, steps)
         assert np.array_equal(window(got, i0, j0, W), ref[steps:steps + W, steps:steps + W]), \
             (i0, j0)
+
+
+def test_copy_reference_kernel(B):
+    """The bandwidth reference copy moves every byte, including a tail that
+    is not a multiple of the grid's stride."""
+    import torch
+    for nbytes in (16, 4096 + 48, (1 << 24) + 16 * 12345):
+        src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+        B.bml_copy(dst, src, nbytes, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        assert torch.equal(dst[:nbytes], src)
+        assert int(dst[nbytes:].sum()) == 0
