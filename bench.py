@@ -62,6 +62,11 @@ def alu_roofline(layout: int, k: int, gcups: float) -> dict:
             "lane_ops_per_cell_step": round(per_cell_step, 4)}
 
 
+def size_key(lt):
+    """Tuning-cache size key of a workload lattice: N, or ROWSxCOLS."""
+    return lt.n if lt.cols is None else f"{lt.n}x{lt.cols}"
+
+
 def load_tuning(layout: int, n, group: str | None = None):
     """Autotuned (tile_rows, t_phases, waves_per_block): the entry for the
     group of lattices run together (e.g. the four concurrent 4096 lattices),
@@ -81,10 +86,11 @@ def load_tuning(layout: int, n, group: str | None = None):
     return None
 
 
-def traffic_from_profile(name: str, launches_bytes: float):
+def traffic_from_profile(name: str, tuning, launches_bytes: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
-    path = os.path.join(PROFILES, f"{name}.traffic.json")
+    it was taken on the current kernel source with the same tuning; else
+    None."""
+    path = os.path.join(PROFILES, f"{name}_t{tuning[1]}.traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -93,6 +99,9 @@ def traffic_from_profile(name: str, launches_bytes: float):
     except (OSError, ValueError):
         return None
     if d.get("kernel_hash") != kernel_hash():
+        return None
+    p = d.get("probe", {})
+    if (p.get("tile_rows"), p.get("t_phases"), p.get("waves_per_block")) != tuple(tuning):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -156,17 +165,51 @@ def pmc_summary(probe_log: str, fetch_dir: str, write_dir: str) -> int:
            "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": alg,
            "ratio_to_algorithmic": hbm / alg,
            "dispatches": res["FETCH_SIZE"]["dispatches"]}
-    path = os.path.join(PROFILES, f"pass_{probe['layout']}_{probe['n']}.traffic.json")
+    path = os.path.join(PROFILES,
+                        f"pass_{probe['layout']}_{probe['n']}_t{probe['t_phases']}.traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
     return 0
 
 
-def cpu_baseline(n: int, rho: float, seed: int, target_s: float = 15.0):
+def copy_ceiling(B, dev, nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """GB/s (bytes read + bytes written) of a 1 GiB device copy, by torch and
+    by the library's streaming copy kernel, on this device."""
+    import torch
+    a = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn in (("torch_copy", lambda: b.copy_(a)),
+                     ("bml_copy", lambda: B.bml_copy(b, a, nbytes,
+                                                      torch.cuda.current_stream(dev)))):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(lt, target_s: float = 15.0):
+    """The oracle on (a bounded number of rows of) the workload's first
+    lattice, timed on the host cores."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
-    g = oracle.init_cells(n, seed, rho)
+    rows, cols = min(lt.n, 4096), min(lt.cols or lt.n, 4096 if lt.cols is None else lt.cols)
+    if lt.cols is None and lt.rho_lr is None:
+        g = oracle.init_cells(rows, lt.seed, lt.rho, cols=cols)
+    else:
+        g = oracle.init_cells_asym(min(lt.n, 1024), cols, lt.seed, lt.rho_lr, lt.rho_tb)
+        rows = g.shape[0]
+    rho, seed, n = lt.rho, lt.seed, rows
     t0 = time.perf_counter()
     g, _ = oracle.run(g, 2, n_threads=threads)
     cal = (time.perf_counter() - t0) / 2
@@ -174,10 +217,13 @@ def cpu_baseline(n: int, rho: float, seed: int, target_s: float = 15.0):
     t0 = time.perf_counter()
     oracle.run(g, steps, n_threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": n * n * steps / dt / 1e9, "unit": "GCUPS", "cores": threads,
+    return {"value": rows * cols * steps / dt / 1e9, "unit": "GCUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"{n}x{n} rho={rho} seed={seed}, {steps} steps, {threads} threads, "
-                      f"{dt:.1f} s (plain C oracle, -O3, OpenMP row split)"}
+            "sample": f"{rows}x{cols} (of the workload's first lattice) "
+                      + (f"rho={rho}" if lt.rho_lr is None
+                         else f"rho_lr={lt.rho_lr} rho_tb={lt.rho_tb}") + f" seed={seed}, "
+                      f"{steps} steps, {threads} threads, {dt:.1f} s (plain C oracle, -O3, "
+                      "OpenMP row split)"}
 
 
 def bench_sweep(args, B, workloads, dev) -> int:
@@ -261,7 +307,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["medium", "large", "sweep", "early-exit"],
+    ap.add_argument("--workload", choices=["medium", "large", "rect", "sweep", "early-exit"],
                     default="medium")
     ap.add_argument("--plain-sample", type=int, default=None,
                     help="sweep/early-exit: time plain per-lattice runs on this many "
@@ -273,6 +319,8 @@ def main() -> int:
     ap.add_argument("--probe", action="store_true",
                     help="for counter runs: a 1 GiB device copy (the calibration kernel "
                          "of known traffic), then --steps BML steps of the first lattice")
+    ap.add_argument("--tuning", type=int, nargs=3, metavar=("TILE_ROWS", "T_PHASES", "WPB"),
+                    help="medium/large: run this tuning instead of the autotuned one")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("PROBE_LOG", "FETCH_DIR", "WRITE_DIR"),
                     help="no GPU: turn two rocprofv3 --pmc runs of --probe (FETCH_SIZE, "
                          "WRITE_SIZE) into profiles/pass_<layout>_<n>.traffic.json")
@@ -298,9 +346,15 @@ def main() -> int:
         return bench_sweep(args, B, workloads, dev)
     if args.workload == "early-exit":
         return bench_early_exit(args)
-    wl = workloads.MEDIUM if args.workload == "medium" else workloads.LARGE
+    wl = {"medium": workloads.MEDIUM, "large": workloads.LARGE,
+          "rect": workloads.RECT}[args.workload]
     # the lattices of a multi-lattice workload run in joint launches, tuned as a group
     group = workloads.MEDIUM_GROUP if len(wl.lattices) > 1 else None
+    if args.tuning:
+        forced = tuple(args.tuning)
+        load = lambda lay, n, grp=None: forced   # noqa: E731
+    else:
+        load = load_tuning
     layout = 0 if args.layout == "u8" else 1
 
     if args.probe:
@@ -313,8 +367,8 @@ def main() -> int:
         # in joint launches, with the same tuning
         stream = torch.cuda.Stream(dev)
         lats = [B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=max(args.steps, 1),
-                          device=dev, stream=stream) for lt in wl.lattices]
-        tun = load_tuning(layout, wl.lattices[0].n, group)
+                          device=dev, stream=stream, **lt.kwargs()) for lt in wl.lattices]
+        tun = load(layout, size_key(wl.lattices[0]), group)
         for lat in lats:
             if tun:
                 lat.set_tuning(*tun)
@@ -322,8 +376,10 @@ def main() -> int:
         torch.cuda.synchronize()
         tr, tp, wpb = lats[0].tuning()
         print(json.dumps({"probe": wl.name, "layout": args.layout, "steps": args.steps,
-                          "n": wl.lattices[0].n, "lattices_per_launch": len(lats),
-                          "cells_per_launch": sum(lt.n * lt.n for lt in wl.lattices),
+                          "n": (wl.lattices[0].n if wl.lattices[0].cols is None
+                                else f"{wl.lattices[0].n}x{wl.lattices[0].cols}"),
+                          "lattices_per_launch": len(lats),
+                          "cells_per_launch": sum(lt.cells for lt in wl.lattices),
                           "t_phases": tp, "tile_rows": tr, "waves_per_block": wpb,
                           "kernel_hash": kernel_hash()}), flush=True)
         for lat in lats:
@@ -341,8 +397,8 @@ def main() -> int:
                       torch.cuda.Stream(dev) if mode == "streams" else
                       torch.cuda.current_stream(dev))
             lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps, device=dev,
-                            stream=stream)
-            tun = load_tuning(lay, lt.n, group if mode == "joint" else None)
+                            stream=stream, **lt.kwargs())
+            tun = load(lay, size_key(lt), group if mode == "joint" else None)
             if tun:
                 lat.set_tuning(*tun)
             lats.append(lat)
@@ -382,7 +438,7 @@ def main() -> int:
         k = tp // 2
         passes = -(-wl.steps // k) * steps
         launches = passes if mode == "joint" else passes * len(lats)
-        cells = sum(lt.n * lt.n for lt in wl.lattices)
+        cells = sum(lt.cells for lt in wl.lattices)
         for lat in lats:
             lat.close()
         return {"gpu_s": gpu_s, "wall_s": wall, "k": k, "tile_rows": tr, "wpb": wpb,
@@ -402,8 +458,11 @@ def main() -> int:
     launch_cells = res["cells"] / len(wl.lattices) * res["lattices_per_launch"]
     alg_bytes = bytes_per_cell_step(layout, k) * launch_cells * k
     achieved = alg_bytes / per_launch_s / 1e9
-    kname = f"pass_{args.layout}_{wl.lattices[0].n}"
-    traffic = traffic_from_profile(kname, alg_bytes)
+    lt0 = wl.lattices[0]
+    kname = (f"pass_{args.layout}_{lt0.n}" if lt0.cols is None
+             else f"pass_{args.layout}_{lt0.n}x{lt0.cols}")
+    traffic = traffic_from_profile(kname, (res["tile_rows"], 2 * k, res["wpb"]), alg_bytes)
+    copy_gbs = copy_ceiling(B, dev)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
@@ -413,6 +472,12 @@ def main() -> int:
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "avg_launch_us": round(per_launch_s * 1e6, 2),
                 "effective_gbs": round(value * 1e9 * bytes_per_cell_step(layout, 1) / 1e9, 1),
+                # what a plain read-once/write-once kernel reaches here, and the
+                # HBM bytes the counters saw per launch as a fraction of it
+                "copy_ceiling_gbs": copy_gbs,
+                "traffic_frac_of_copy": (round(traffic / per_launch_s / 1e9
+                                               / max(copy_gbs.values()), 4)
+                                         if traffic else None),
                 # the same launches against the plain-ALU ceiling
                 "alu": alu_roofline(layout, k, value)}
 
@@ -430,7 +495,10 @@ def main() -> int:
         "dtype": args.layout,
         "data": "synthetic (SplitMix64 iid lattices, seeded)",
         "config": {"workload": wl.name, "layout": args.layout,
-                   "lattices": [[lt.n, lt.rho, lt.seed] for lt in wl.lattices],
+                   "lattices": [[lt.n, lt.cols or lt.n, lt.rho_lr if lt.rho_lr is not None
+                                 else lt.rho / 2, lt.rho_tb if lt.rho_tb is not None
+                                 else lt.rho / 2, lt.seed] for lt in wl.lattices],
+                   "lattice_fields": ["rows", "cols", "rho_lr", "rho_tb", "seed"],
                    "steps_per_lattice": wl.steps,
                    "tuning": {"tile_rows": res["tile_rows"], "t_phases": 2 * k,
                               "waves_per_block": res["wpb"]},
@@ -455,7 +523,7 @@ def main() -> int:
                 for i, lt in enumerate(wl.lattices):
                     with B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps,
                                    device=dev) as lat:
-                        tun = load_tuning(lay, lt.n)
+                        tun = load(lay, size_key(lt))
                         if tun:
                             lat.set_tuning(*tun)
                         lat.step(wl.steps)
@@ -474,7 +542,7 @@ def main() -> int:
 
     if not args.no_cpu_baseline:
         lt = wl.lattices[0]
-        out["cpu_baseline"] = cpu_baseline(min(lt.n, 4096), lt.rho, lt.seed)
+        out["cpu_baseline"] = cpu_baseline(lt)
 
     print(json.dumps(out), flush=True)
     return 0

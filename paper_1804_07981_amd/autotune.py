@@ -65,16 +65,19 @@ def _stats_array(rec):
 
 def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
                  t_phases=(2, 4, 8, 12, 16), waves=(2, 4), steps: int | None = None,
-                 rho: float = 0.3, seed: int = 7, log=print) -> dict:
-    """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice."""
+                 rho: float = 0.3, seed: int = 7, log=print, shape: dict | None = None) -> dict:
+    """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice, or
+    n rows x shape["cols"] with the draw in `shape` (Lattice keywords)."""
+    shape = shape or {}
+    cells = n * shape.get("cols", n)
     if steps is None:
         # about 4e9 cell-steps per measurement, at least 48 steps
-        steps = int(max(48, min(2000, 4e9 / (n * n))))
+        steps = int(max(48, min(2000, 4e9 / cells)))
         steps -= steps % 48
     ref = None
     results = []
     for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
-        with Lattice(n, rho, seed, layout=layout, stats_cap=steps) as lat:
+        with Lattice(n, rho, seed, layout=layout, stats_cap=steps, **shape) as lat:
             lat.set_tuning(tr, tp, w)
             lat.step(steps)                      # warm-up (and the checked run)
             torch.cuda.synchronize()
@@ -91,10 +94,11 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
             exact = True
         else:
             exact = np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
-        gcups = n * n * steps / dt / 1e9
+        gcups = cells * steps / dt / 1e9
         results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
                         "gcups": gcups, "exact": exact})
-        log(f"  n={n} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS"
+        size = f"{n}x{shape['cols']}" if "cols" in shape else f"{n}"
+        log(f"  n={size} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS"
             + ("" if exact else "  DIFFERS FROM THE REFERENCE -- rejected"))
     ok = [r for r in results if r["exact"]]
     best = max(ok, key=lambda r: r["gcups"])
@@ -194,6 +198,8 @@ def main(argv=None) -> int:
     ap.add_argument("--sizes", type=int, nargs="*", default=[4096, 32768])
     ap.add_argument("--layouts", nargs="*", default=["u8", "bp"])
     ap.add_argument("--batch", action="store_true", help="also tune the 512-lattice sweep")
+    ap.add_argument("--rect", action="store_true",
+                    help="also tune the rectangular, asymmetric workload lattice")
     ap.add_argument("--medium", action="store_true",
                     help="also tune the four 4096x4096 lattices advanced by joint launches")
     ap.add_argument("--cache", default=CACHE)
@@ -212,6 +218,15 @@ def main(argv=None) -> int:
             if r["rejected"]:
                 print(f"bit-exactness gate rejected {len(r['rejected'])} candidates",
                       file=sys.stderr)
+    if args.rect:
+        import workloads
+        lt = workloads.RECT.lattices[0]
+        for lay in args.layouts:
+            layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
+            r = tune_lattice(lt.n, layout, rho=lt.rho, seed=lt.seed, shape=lt.kwargs(), **kw)
+            k = key(layout, f"{lt.n}x{lt.cols}")
+            cache[k] = dict(r["best"], steps=r["steps"], rejected=len(r["rejected"]))
+            print(json.dumps({"key": k, **r["best"]}), flush=True)
     if args.medium:
         import workloads
         specs = [(l.n, l.rho, l.seed) for l in workloads.MEDIUM.lattices]

@@ -45,9 +45,22 @@ def _unit(z: int) -> float:
 
 @dataclass(frozen=True)
 class Lattice:
-    n: int
+    n: int                       # rows (and columns unless `cols` is set)
     rho: float
     seed: int
+    cols: int | None = None      # rectangular lattices: columns
+    rho_lr: float | None = None  # asymmetric draw: LR / TB probabilities
+    rho_tb: float | None = None
+
+    @property
+    def cells(self) -> int:
+        return self.n * (self.cols or self.n)
+
+    def kwargs(self) -> dict:
+        """Keyword arguments of the library's Lattice for this shape and draw."""
+        if self.cols is None and self.rho_lr is None:
+            return {}
+        return {"cols": self.cols or self.n, "rho_lr": self.rho_lr, "rho_tb": self.rho_tb}
 
 
 @dataclass(frozen=True)
@@ -81,6 +94,15 @@ LARGE = Workload(
     "bml-32768x32768-rho0.30-seed7-1000steps",
     (Lattice(32768, 0.30, 7),), 1000,
     "single lattice far larger than any on-chip cache")
+
+
+# Rectangular lattice with unequal densities (Sec. 2's asymmetric
+# extension): 8192 rows x 32768 columns (256 MiB of uint8 cells), LR 0.20,
+# TB 0.10, seed 11, 1000 steps.
+RECT = Workload(
+    "bml-8192x32768-lr0.20-tb0.10-seed11-1000steps",
+    (Lattice(8192, 0.30, 11, cols=32768, rho_lr=0.20, rho_tb=0.10),), 1000,
+    "rectangular lattice, unequal LR / TB densities")
 
 
 SWEEP_STREAM_STATE = 0x5EEDBA7C
