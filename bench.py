@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import statistics
 import os
 import sys
 import time
@@ -305,7 +306,7 @@ def bench_early_exit(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["medium", "large", "rect", "sweep", "early-exit"],
                     default="medium")
@@ -419,15 +420,20 @@ def main() -> int:
         streams = list({id(lat.stream): lat.stream for lat in lats}.values())
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in streams]
+        # per-step events on the (first) stream give the spread of the steps
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
         for st, (e0, _) in zip(streams, evs):
             e0.record(st)
-        for _ in range(steps):
+        marks[0].record(streams[0])
+        for i in range(steps):
             run_job(lats, mode)
+            marks[i + 1].record(streams[0])
         for st, (_, e1) in zip(streams, evs):
             e1.record(st)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        step_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
         # Busy time of each stream (they overlap in "streams" mode).
         per_stream = [e0.elapsed_time(e1) / 1e3 for e0, e1 in evs]
         gpu_s = max(per_stream)
@@ -445,6 +451,7 @@ def main() -> int:
                 "launches": launches, "cells": cells, "mode": mode,
                 "lattices_per_launch": len(lats) if mode == "joint" else 1,
                 "avg_launch_s": sum(per_stream) / launches,
+                "step_ms": step_ms,
                 "gcups": cells * wl.steps * steps / gpu_s / 1e9}
 
     main_mode = "joint" if len(wl.lattices) > 1 else "single"
@@ -504,6 +511,11 @@ def main() -> int:
                               "waves_per_block": res["wpb"]},
                    "parallelism": "1 GPU"},
         "roofline": roofline,
+        # spread of the timed steps (HIP events between steps)
+        "step_ms_stats": {"median": round(statistics.median(res["step_ms"]), 3),
+                          "mean": round(statistics.fmean(res["step_ms"]), 3),
+                          "min": round(res["step_ms"][0], 3),
+                          "max": round(res["step_ms"][-1], 3)},
     }
 
     if not args.no_variants:
