@@ -70,6 +70,10 @@ def lib() -> ctypes.CDLL:
         L.bmlo_count.restype = i64
         L.bmlo_run.argtypes = [i64, i64, vp, vp, i64, vp, i32]
         L.bmlo_run.restype = None
+        L.bmlo_run_topo.argtypes = [i64, i64, vp, vp, i64, vp, i32, i32]
+        L.bmlo_run_topo.restype = None
+        L.bmlo_phase_v_topo.argtypes = [i64, i64, vp, vp, i32]
+        L.bmlo_phase_v_topo.restype = i64
         L.bmlo_run_many.argtypes = [i64, vp, vp, vp, vp, vp, i64, i32]
         L.bmlo_run_many.restype = i32
         L.bmlo_pack.argtypes = [i64, i64, vp, vp, vp]
@@ -146,16 +150,27 @@ def phase_v(cells: np.ndarray) -> tuple[np.ndarray, int]:
     return out, int(moved)
 
 
-def run(cells: np.ndarray, steps: int, n_threads: int = 1
+TORUS, KLEIN = 0, 1
+
+
+def run(cells: np.ndarray, steps: int, n_threads: int = 1, topology: int = TORUS
         ) -> tuple[np.ndarray, np.ndarray]:
     """`steps` steps (H then V each).  Returns (final lattice, stats) with
-    stats[s] = (n_lr, moved_lr, n_tb, moved_tb) of step s."""
+    stats[s] = (n_lr, moved_lr, n_tb, moved_tb) of step s.  topology KLEIN
+    glues the top and bottom edges with a reversal (Klein bottle)."""
     a = _u8(cells).copy()
     tmp = np.empty_like(a)
     stats = np.zeros((max(steps, 0), 4), dtype=np.uint32)
-    lib().bmlo_run(a.shape[0], a.shape[1], _ptr(a), _ptr(tmp), int(steps),
-                   _ptr(stats), int(n_threads))
+    lib().bmlo_run_topo(a.shape[0], a.shape[1], _ptr(a), _ptr(tmp), int(steps),
+                        _ptr(stats), int(n_threads), int(topology))
     return a, stats
+
+
+def phase_v_topo(cells: np.ndarray, topology: int) -> tuple[np.ndarray, int]:
+    a = _u8(cells)
+    out = np.empty_like(a)
+    moved = lib().bmlo_phase_v_topo(a.shape[0], a.shape[1], _ptr(a), _ptr(out), int(topology))
+    return out, int(moved)
 
 
 def run_many(lattices: list[np.ndarray], steps: int, n_threads: int = 1

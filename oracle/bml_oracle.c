@@ -132,16 +132,26 @@ static int64_t phase_h_rows(int64_t r0, int64_t r1, int64_t cols,
     return moved;
 }
 
+/* Column of the vertical neighbour.  On the torus (topology 0) it is j.  On
+ * the Klein bottle (topology 1; the lattice of Campora et al. cited in
+ * Sec. 2) the top and bottom edges are glued with a reversal, so a
+ * neighbour across that edge sits in column cols-1-j; the left and right
+ * edges stay periodic. */
+static int64_t v_col(int64_t j, int64_t cols, int crosses_edge, int topology)
+{
+    return (topology == 1 && crosses_edge) ? cols - 1 - j : j;
+}
+
 static int64_t phase_v_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
-                            const uint8_t *cur, uint8_t *next)
+                            const uint8_t *cur, uint8_t *next, int topology)
 {
     int64_t moved = 0;
     for (int64_t i = r0; i < r1; i++) {
         int64_t up = (i - 1 + rows) % rows, down = (i + 1) % rows;
         for (int64_t j = 0; j < cols; j++) {
-            uint8_t top = cur[up * cols + j];
+            uint8_t top = cur[up * cols + v_col(j, cols, i == 0, topology)];
             uint8_t center = cur[i * cols + j];
-            uint8_t bottom = cur[down * cols + j];
+            uint8_t bottom = cur[down * cols + v_col(j, cols, i == rows - 1, topology)];
             uint8_t out;
             if (top == TB && center == EMPTY) {
                 out = TB;
@@ -177,7 +187,14 @@ int64_t bmlo_phase_h(int64_t rows, int64_t cols, const uint8_t *cur,
 int64_t bmlo_phase_v(int64_t rows, int64_t cols, const uint8_t *cur,
                      uint8_t *next)
 {
-    return phase_v_rows(0, rows, rows, cols, cur, next);
+    return phase_v_rows(0, rows, rows, cols, cur, next, 0);
+}
+
+/* Vertical phase on the torus (topology 0) or the Klein bottle (1). */
+int64_t bmlo_phase_v_topo(int64_t rows, int64_t cols, const uint8_t *cur,
+                          uint8_t *next, int32_t topology)
+{
+    return phase_v_rows(0, rows, rows, cols, cur, next, topology);
 }
 
 int64_t bmlo_count(const uint8_t *cells, int64_t n, int32_t value)
@@ -197,8 +214,24 @@ int64_t bmlo_count(const uint8_t *cells, int64_t n, int32_t value)
 /* n_threads > 0 splits the row loop over that many OpenMP threads (Sec. 4);*/
 /* any thread count gives the same bytes and counts.                        */
 /* ------------------------------------------------------------------------ */
+static void run_topo(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
+                     int64_t steps, uint32_t *stats, int32_t n_threads, int topology);
+
 void bmlo_run(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
               int64_t steps, uint32_t *stats, int32_t n_threads)
+{
+    run_topo(rows, cols, cells, tmp, steps, stats, n_threads, 0);
+}
+
+/* As bmlo_run, on the torus (topology 0) or the Klein bottle (1). */
+void bmlo_run_topo(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
+                   int64_t steps, uint32_t *stats, int32_t n_threads, int32_t topology)
+{
+    run_topo(rows, cols, cells, tmp, steps, stats, n_threads, topology);
+}
+
+static void run_topo(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
+                     int64_t steps, uint32_t *stats, int32_t n_threads, int topology)
 {
     int nt = n_threads > 0 ? n_threads : 1;
     for (int64_t s = 0; s < steps; s++) {
@@ -214,7 +247,7 @@ void bmlo_run(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
 #pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : moved_tb, n_tb)
 #endif
         for (int64_t i = 0; i < rows; i++) {
-            moved_tb += phase_v_rows(i, i + 1, rows, cols, tmp, cells);
+            moved_tb += phase_v_rows(i, i + 1, rows, cols, tmp, cells, topology);
             n_tb += count_value(cells + i * cols, cols, TB);
         }
         if (stats) {

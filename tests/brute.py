@@ -9,14 +9,24 @@ that no two cars target the same cell, then applies every move at once
 EMPTY, LR, TB = 0, 1, 2
 
 
-def phase(grid, kind):
+def target(i, j, kind, rows, cols, klein=False):
+    """The cell a car at (i, j) drives into.  On the Klein bottle a TB car
+    leaving the bottom row re-enters the top row in the mirrored column."""
+    if kind == LR:
+        return i, (j + 1) % cols
+    if klein and i == rows - 1:
+        return 0, cols - 1 - j
+    return (i + 1) % rows, j
+
+
+def phase(grid, kind, klein=False):
     rows, cols = len(grid), len(grid[0])
     moves = []
     for i in range(rows):
         for j in range(cols):
             if grid[i][j] != kind:
                 continue
-            ti, tj = (i, (j + 1) % cols) if kind == LR else ((i + 1) % rows, j)
+            ti, tj = target(i, j, kind, rows, cols, klein)
             if grid[ti][tj] == EMPTY:
                 moves.append(((i, j), (ti, tj)))
     targets = [t for _, t in moves]
@@ -30,20 +40,20 @@ def phase(grid, kind):
     return new, len(moves)
 
 
-def step(grid):
+def step(grid, klein=False):
     """One step: every LR car, then every TB car.  Returns (grid, counts)
     with counts = (n_lr, moved_lr, n_tb, moved_tb)."""
     g1, mlr = phase(grid, LR)
     n_lr = sum(c == LR for r in g1 for c in r)
-    g2, mtb = phase(g1, TB)
+    g2, mtb = phase(g1, TB, klein)
     n_tb = sum(c == TB for r in g2 for c in r)
     return g2, (n_lr, mlr, n_tb, mtb)
 
 
-def run(grid, steps):
+def run(grid, steps, klein=False):
     grid = [list(r) for r in grid]
     stats = []
     for _ in range(steps):
-        grid, c = step(grid)
+        grid, c = step(grid, klein)
         stats.append(c)
     return grid, stats

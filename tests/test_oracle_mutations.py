@@ -19,10 +19,10 @@ MUTATIONS = [
     ("LR leaves into any non-LR cell", "} else if (center == LR && right == EMPTY) {",
      "} else if (center == LR && right != LR) {"),
     ("V phase reads the pre-H lattice",
-     "moved_tb += phase_v_rows(i, i + 1, rows, cols, tmp, cells);",
-     "moved_tb += phase_v_rows(i, i + 1, rows, cols, cells, tmp);"),
-    ("moved counts the arrivals twice", "                moved++;\n            } else {\n                out = center;\n            }\n            next[i * cols + j] = out;\n        }\n    }\n    return moved;\n}\n\nstatic int64_t phase_v_rows",
-     "                moved += 2;\n            } else {\n                out = center;\n            }\n            next[i * cols + j] = out;\n        }\n    }\n    return moved;\n}\n\nstatic int64_t phase_v_rows"),
+     "moved_tb += phase_v_rows(i, i + 1, rows, cols, tmp, cells, topology);",
+     "moved_tb += phase_v_rows(i, i + 1, rows, cols, cells, tmp, topology);"),
+    ("moved counts the arrivals twice", "                moved++;\n            } else {\n                out = center;\n            }\n            next[i * cols + j] = out;\n        }\n    }\n    return moved;\n}\n\n/* Column of the vertical neighbour",
+     "                moved += 2;\n            } else {\n                out = center;\n            }\n            next[i * cols + j] = out;\n        }\n    }\n    return moved;\n}\n\n/* Column of the vertical neighbour"),
     ("LR threshold off by a factor of two", "*thr_lr = (uint64_t)ldexp(rho * 0.5, 53);",
      "*thr_lr = (uint64_t)ldexp(rho * 0.5, 52);"),
     ("SplitMix64 shift constant", "z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
@@ -33,6 +33,12 @@ MUTATIONS = [
      "if (c == TB)\n                    b |= 1u << (31 - bit);"),
     ("stats fields swapped", "stats[4 * s + 1] = (uint32_t)moved_lr;",
      "stats[4 * s + 1] = (uint32_t)moved_tb;"),
+    ("Klein seam mirrors the top neighbour only on the torus side",
+     "uint8_t bottom = cur[down * cols + v_col(j, cols, i == rows - 1, topology)];",
+     "uint8_t bottom = cur[down * cols + j];"),
+    ("Klein seam mirrors at the wrong row",
+     "uint8_t top = cur[up * cols + v_col(j, cols, i == 0, topology)];",
+     "uint8_t top = cur[up * cols + v_col(j, cols, i == 1, topology)];"),
     ("asymmetric TB threshold without the LR share", "*thr_tb = (uint64_t)ldexp(rho_lr + rho_tb, 53);",
      "*thr_tb = (uint64_t)ldexp(rho_tb, 53);"),
 ]

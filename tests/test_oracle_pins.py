@@ -286,6 +286,53 @@ def test_init_fractions(rho):
         assert abs(frac - p) <= 5 * sigma + 1e-12
 
 
+# --- Klein bottle (top and bottom edges glued with a reversal) ------------
+
+KLEIN = oracle.KLEIN
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 5), (2, 3), (3, 2), (4, 7), (5, 5), (6, 4), (8, 8),
+                                       (7, 1)])
+def test_klein_matches_brute_force(rows, cols):
+    rng = np.random.default_rng(rows * 131 + cols)
+    for _ in range(25):
+        p = rng.random()
+        q = rng.random() * (1 - p)
+        g = workloads.random_lattice(rng, rows, cols, p, q)
+        og, ost = oracle.run(g, 6, topology=KLEIN)
+        bg, bst = brute.run(g.tolist(), 6, klein=True)
+        assert np.array_equal(og, np.array(bg, dtype=np.uint8))
+        assert [tuple(int(x) for x in s) for s in ost] == bst
+
+
+@pytest.mark.parametrize("rows,cols,i,j", [(8, 8, 3, 1), (5, 12, 0, 11), (16, 9, 15, 4)])
+def test_klein_lone_tb_car_comes_back_mirrored_then_home(rows, cols, i, j):
+    g = np.zeros((rows, cols), np.uint8)
+    g[i, j] = TB
+    once, st = oracle.run(g, rows, topology=KLEIN)
+    want = np.zeros_like(g)
+    want[i, cols - 1 - j] = TB
+    assert np.array_equal(once, want)
+    assert (st[:, 3] == 1).all() and (st[:, 1] == 0).all()
+    twice, _ = oracle.run(once, rows, topology=KLEIN)
+    assert np.array_equal(twice, g)
+
+
+def test_klein_conservation_per_row_and_column_pair():
+    rng = np.random.default_rng(77)
+    g = workloads.random_lattice(rng, 24, 19, 0.3, 0.3)
+    out, _ = oracle.run(g, 40, topology=KLEIN)
+    assert np.array_equal((out == LR).sum(axis=1), (g == LR).sum(axis=1))
+    pair = lambda x: (x == TB).sum(axis=0) + (x == TB).sum(axis=0)[::-1]   # noqa: E731
+    assert np.array_equal(pair(out), pair(g))
+
+
+def test_klein_without_tb_cars_is_the_torus():
+    rng = np.random.default_rng(5)
+    g = workloads.random_lattice(rng, 12, 10, 0.5, 0.0)
+    assert np.array_equal(oracle.run(g, 9, topology=KLEIN)[0], oracle.run(g, 9)[0])
+
+
 # --- asymmetric placement (unequal LR and TB numbers, Sec. 2 extensions) ---
 
 def _floor_times_2_53(x: float) -> int:
