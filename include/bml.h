@@ -53,6 +53,13 @@ enum {
  *                        leftmost cell (two bits per cell suffice, Sec. 3). */
 enum { BML_LAYOUT_U8 = 0, BML_LAYOUT_BITPLANE = 1 };
 
+/* Lattice topologies.  TORUS: both directions periodic (the model of
+ * Sec. 2).  KLEIN: left and right edges periodic, top and bottom edges
+ * glued with a reversal (the Klein-bottle lattice Sec. 2 cites): a TB car
+ * leaving the bottom row in column j enters the top row in column
+ * cols-1-j.  LR cars never cross that edge. */
+enum { BML_TOPO_TORUS = 0, BML_TOPO_KLEIN = 1 };
+
 /* Counts of one step (the project's reading of per-phase car counts and
  * moved counts): n_lr = LR cars after the horizontal phase, moved_lr = LR
  * cars that moved in it, n_tb = TB cars after the vertical phase, moved_tb =
@@ -105,7 +112,7 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed,
  *                bml_init_rect(n, n, rho/2, rho/2).
  * Everything else (buffers, ring, stream, errors, later calls) is as for
  * bml_init; bml_get_cells returns rows*cols bytes; bml_step_group needs
- * equal rows and cols. */
+ * equal rows, cols and topology. */
 int bml_state_bytes_rect(int32_t rows, int32_t cols, int32_t layout, size_t *bytes);
 int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
                   uint64_t seed, double rho_lr, double rho_tb, const uint8_t *cells_host,
@@ -152,6 +159,12 @@ int bml_get_cells(bml_lattice *L, uint8_t *out_host);
 
 /* Initial car counts computed at bml_init. */
 int bml_initial_counts(const bml_lattice *L, uint64_t *n_lr, uint64_t *n_tb);
+
+/* Topology of the lattice for the steps that follow (BML_TOPO_TORUS after
+ * init).  The state layout does not change.  EINVAL on an unknown value,
+ * ESTATE on an invalid handle.  bml_get_topology returns it (or ESTATE). */
+int bml_set_topology(bml_lattice *L, int32_t topology);
+int bml_get_topology(const bml_lattice *L);
 
 /* Launch shape of the step kernels.  Each wavefront streams down a strip of
  * the lattice `tile_rows` output rows tall (plus t_phases/2 halo rows above

@@ -20,6 +20,8 @@ BML_ECORRUPT = -5
 BML_EBADARG = BML_EINVAL
 BML_LAYOUT_U8 = 0
 BML_LAYOUT_BITPLANE = 1
+BML_TOPO_TORUS = 0
+BML_TOPO_KLEIN = 1
 
 # bml_step_stats as a numpy record: n_lr, moved_lr, n_tb, moved_tb.
 STEP_STATS_DTYPE = np.dtype([("n_lr", "<u4"), ("moved_lr", "<u4"),
@@ -58,6 +60,8 @@ _SIGNATURES = {
     "bml_get_cells": ([_vp, _vp], ctypes.c_int),
     "bml_initial_counts": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
     "bml_set_tuning": ([_vp, _i32, _i32, _i32], ctypes.c_int),
+    "bml_set_topology": ([_vp, _i32], ctypes.c_int),
+    "bml_get_topology": ([_vp], ctypes.c_int),
     "bml_get_tuning": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                         ctypes.POINTER(_i32)], ctypes.c_int),
     "bml_step_count": ([_vp], _i64),
@@ -189,6 +193,14 @@ def bml_init_rect(rows: int, cols: int, layout: int, seed: int, rho_lr: float, r
                                float(rho_lr), float(rho_tb), _ptr(cells), _ptr(d_state_a),
                                _ptr(d_state_b), _ptr(d_stats), stats_cap, _stream_ptr(stream)))
     return int(h.value)
+
+
+def bml_set_topology(handle: int, topology: int) -> None:
+    _check(lib().bml_set_topology(handle, topology))
+
+
+def bml_get_topology(handle: int) -> int:
+    return _check(lib().bml_get_topology(handle))
 
 
 def bml_step(handle: int, n_steps: int) -> None:

@@ -11,10 +11,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbml.so")
-SOURCES = ["bml_lattice.hip", "bml_pass_u8_lo.hip", "bml_pass_u8_hi.hip",
-           "bml_pass_bp_lo.hip", "bml_pass_bp_hi.hip", "bml_pass_u8_row1.hip",
-           "bml_pass_u8_row2.hip", "bml_pass_bp_row1.hip", "bml_pass_bp_row2.hip",
-           "bml_batch.hip",
+# The step kernels: bml_pass_inst.hip compiled once per (layout, column
+# mode / range of K, topology); see bml_pass.hpp.
+PASS_RANGES = {"lo": (0, 1, 4), "hi": (0, 5, 4), "row1": (1, 1, 8), "row2": (2, 1, 8)}
+PASS_VARIANTS = [
+    (f"pass_table_{io}_{rng}_{topo}",
+     [f"-DBML_INST_IO={'IO_U8' if io == 'u8' else 'IO_BP'}", f"-DBML_INST_ROW={row}",
+      f"-DBML_INST_TOPO={'TOPO_TORUS' if topo == 'torus' else 'TOPO_KLEIN'}",
+      f"-DBML_INST_KLO={klo}", f"-DBML_INST_KN={kn}",
+      f"-DBML_INST_NAME=pass_table_{io}_{rng}_{topo}"])
+    for topo in ("torus", "klein") for io in ("u8", "bp")
+    for rng, (row, klo, kn) in PASS_RANGES.items()]
+SOURCES = ["bml_lattice.hip", "bml_batch.hip",
            "bml_batch_u8.hip", "bml_batch_bp.hip", "bml_mlp.hip"]
 
 HIPCC_FLAGS = [
@@ -39,9 +47,10 @@ def build(out: str | None = None, extra: list[str] | None = None,
     os.makedirs(objdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-    def compile_one(src: str) -> str:
-        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), *inc, "-c",
+    def compile_one(job) -> str:
+        src, name, defines = job
+        obj = os.path.join(objdir, name + ".o")
+        cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), *defines, *inc, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
@@ -51,7 +60,9 @@ def build(out: str | None = None, extra: list[str] | None = None,
         return obj
 
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        jobs = [("bml_pass_inst.hip", name, defs) for name, defs in PASS_VARIANTS]
+        jobs += [(src, os.path.splitext(src)[0], []) for src in SOURCES]
+        objs = list(ex.map(compile_one, jobs))
     tmp = out + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

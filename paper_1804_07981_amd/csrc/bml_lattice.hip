@@ -198,17 +198,25 @@ __global__ void zero_words_kernel(uint32_t *p, int64_t count)
 constexpr int PASS_MODES = 3;
 
 struct KernelTable {
-    PassFn fn[PASS_MODES][2][MAX_K + 1] = {};
+    PassFn fn[2][PASS_MODES][2][MAX_K + 1] = {};   // [topology][mode][io][k]
     KernelTable()
     {
-        pass_table_u8_lo(fn[0][IO_U8]);
-        pass_table_u8_hi(fn[0][IO_U8]);
-        pass_table_bp_lo(fn[0][IO_BP]);
-        pass_table_bp_hi(fn[0][IO_BP]);
-        pass_table_u8_row1(fn[1][IO_U8]);
-        pass_table_bp_row1(fn[1][IO_BP]);
-        pass_table_u8_row2(fn[2][IO_U8]);
-        pass_table_bp_row2(fn[2][IO_BP]);
+        pass_table_u8_lo_torus(fn[TOPO_TORUS][0][IO_U8]);
+        pass_table_u8_hi_torus(fn[TOPO_TORUS][0][IO_U8]);
+        pass_table_bp_lo_torus(fn[TOPO_TORUS][0][IO_BP]);
+        pass_table_bp_hi_torus(fn[TOPO_TORUS][0][IO_BP]);
+        pass_table_u8_row1_torus(fn[TOPO_TORUS][1][IO_U8]);
+        pass_table_bp_row1_torus(fn[TOPO_TORUS][1][IO_BP]);
+        pass_table_u8_row2_torus(fn[TOPO_TORUS][2][IO_U8]);
+        pass_table_bp_row2_torus(fn[TOPO_TORUS][2][IO_BP]);
+        pass_table_u8_lo_klein(fn[TOPO_KLEIN][0][IO_U8]);
+        pass_table_u8_hi_klein(fn[TOPO_KLEIN][0][IO_U8]);
+        pass_table_bp_lo_klein(fn[TOPO_KLEIN][0][IO_BP]);
+        pass_table_bp_hi_klein(fn[TOPO_KLEIN][0][IO_BP]);
+        pass_table_u8_row1_klein(fn[TOPO_KLEIN][1][IO_U8]);
+        pass_table_bp_row1_klein(fn[TOPO_KLEIN][1][IO_BP]);
+        pass_table_u8_row2_klein(fn[TOPO_KLEIN][2][IO_U8]);
+        pass_table_bp_row2_klein(fn[TOPO_KLEIN][2][IO_BP]);
     }
 };
 
@@ -226,22 +234,22 @@ static const KernelTable &kernels()
 }
 
 // Resident blocks per CU of a pass kernel at `threads` threads per block.
-static int resident_blocks(int mode, int io, int k, int threads, int *out)
+static int resident_blocks(int topo, int mode, int io, int k, int threads, int *out)
 {
     static std::mutex mu;
-    static int cache[8][PASS_MODES][2][MAX_K + 1][3];   // [dev][mode][io][k][log2 wpb]
+    static int cache[8][2][PASS_MODES][2][MAX_K + 1][3];   // [dev][topo][mode][io][k][wpb]
     int dev = 0;
     BML_HIP(hipGetDevice(&dev));
     int wl = threads == 64 ? 0 : threads == 128 ? 1 : 2;
     std::lock_guard<std::mutex> lock(mu);
-    int *c = dev < 8 ? &cache[dev][mode][io][k][wl] : nullptr;
+    int *c = dev < 8 ? &cache[dev][topo][mode][io][k][wl] : nullptr;
     if (c && *c > 0) {
         *out = *c;
         return BML_OK;
     }
     int nb = 0;
     BML_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(kernels().fn[mode][io][k]), threads, 0));
+        &nb, reinterpret_cast<const void *>(kernels().fn[topo][mode][io][k]), threads, 0));
     if (nb < 1)
         nb = 1;
     if (c)
@@ -352,6 +360,7 @@ using namespace bml;
 
 struct bml_lattice {
     int32_t rows = 0, cols = 0, layout = 0;
+    int32_t topology = 0;                     // BML_TOPO_TORUS / BML_TOPO_KLEIN
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
     uint32_t *stats = nullptr;
@@ -625,6 +634,25 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed, double
                          d_state_b, d_stats, stats_cap, hip_stream);
 }
 
+int bml_set_topology(bml_lattice *L, int32_t topology)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    if (topology != BML_TOPO_TORUS && topology != BML_TOPO_KLEIN)
+        return fail(BML_EINVAL, "unknown topology %d", topology);
+    L->topology = topology;
+    return BML_OK;
+}
+
+int bml_get_topology(const bml_lattice *L)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    return L->topology;
+}
+
 int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases, int32_t waves_per_block)
 {
     clear_error();
@@ -725,7 +753,7 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
     a.tiles_x = mode ? 1 : (a.words + TILE_WORDS - 1) / TILE_WORDS;
     const int threads = 64 * L->wpb;
     int per_cu = 1;
-    int rc = resident_blocks(mode, io, k, threads, &per_cu);
+    int rc = resident_blocks(L->topology, mode, io, k, threads, &per_cu);
     if (rc)
         return rc;
     const int64_t max_blocks = (int64_t)per_cu * L->dev.cu_count;
@@ -759,7 +787,7 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
             grid = max_blocks / 8 * 8;
     }
     a.xcd_split = (grid >= 8 && grid % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(kernels().fn[mode][io][k], dim3((unsigned)grid), dim3(threads), 0,
+    hipLaunchKernelGGL(kernels().fn[L->topology][mode][io][k], dim3((unsigned)grid), dim3(threads), 0,
                        L->stream, a);
     BML_HIP(hipGetLastError());
     for (int i = 0; i < count; ++i) {
@@ -822,8 +850,9 @@ int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps)
             if (handles[j] == handles[i])
                 return fail(BML_EINVAL, "handle %d appears twice", i);
         const bml_lattice *L0 = handles[0], *Li = handles[i];
-        if (Li->rows != L0->rows || Li->cols != L0->cols || Li->layout != L0->layout)
-            return fail(BML_EINVAL, "lattice %d differs in size or layout from lattice 0", i);
+        if (Li->rows != L0->rows || Li->cols != L0->cols || Li->layout != L0->layout ||
+            Li->topology != L0->topology)
+            return fail(BML_EINVAL, "lattice %d differs in size, layout or topology from lattice 0", i);
         if (Li->tile_rows != L0->tile_rows || Li->t_phases != L0->t_phases ||
             Li->wpb != L0->wpb)
             return fail(BML_EINVAL, "lattice %d has another tuning than lattice 0", i);

@@ -39,6 +39,7 @@
 namespace bml {
 
 enum { IO_U8 = 0, IO_BP = 1 };
+enum { TOPO_TORUS = 0, TOPO_KLEIN = 1 };
 constexpr int MAX_K = 8;        // steps per pass
 constexpr int TILE_WORDS = 62;  // output words per wavefront tile (lanes 1..62)
 
@@ -123,7 +124,15 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // halo lane on each side.  ROW = m > 0: row mode for rows of 2048 m cells;
 // the wavefront holds a whole row, m words per lane, and the lane moves wrap
 // around it (periodic in x without halo lanes, every lane exact).
-template <int IO, int K, int ROW>
+// TOPO = TOPO_TORUS: both directions periodic.  TOPO = TOPO_KLEIN: the top
+// and bottom edges are glued with a reversal (a Klein bottle).  A strip then
+// holds the halo rows that lie across that edge mirrored, in the strip's own
+// frame: a lane loads the mirror word (columns counted from the other side)
+// and reverses its bits, and the horizontal phase of those rows runs towards
+// lower bit indices.  In that frame the vertical neighbours of every row are
+// simply the rows before and after it.  Output rows never lie across the
+// edge, so stores and counts are unchanged.
+template <int IO, int K, int ROW, int TOPO>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
     static_assert(K >= 1 && K <= MAX_K, "bad steps per pass");
@@ -206,6 +215,20 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
             lane_ok = lane >= 1 && lane <= vwords;
         }
         const uint32_t voff = IO == IO_U8 ? word * 32u : word * 4u;
+        // Klein bottle: offset of the lane's words in a mirrored row (the
+        // WL words ending at column words-1-word, loaded in natural order).
+        const uint32_t word_m = (uint32_t)(a.words - WL) - word;
+        const uint32_t voff_m = IO == IO_U8 ? word_m * 32u : word_m * 4u;
+        // Input row s of the strip lies across the glued top/bottom edge.
+        const int lattice_rows = a.rows;
+        auto mirrored = [row_a, lattice_rows](int s) {
+            if constexpr (TOPO == TOPO_KLEIN) {
+                const int g = row_a - K + s;
+                return g < 0 || g >= lattice_rows;
+            } else {
+                return false;
+            }
+        };
 
         // Byte offset of input row t (lattice row row_a - K + t, periodic).
         // `ld_off` runs D rows ahead of the pipeline; `st_off` is the next
@@ -223,23 +246,27 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         uint32_t ring[D][NW];
         // Row layout in the ring: u8: 8 dwords (32 cells) per word; bp: the
         // WL LR words, then the WL TB words.
-        auto issue = [&](uint32_t (&dstw)[NW], uint32_t off_) {
+        // Captures by value: a select between captured references would be
+        // lowered to an indexed private (scratch) array.
+        auto issue = [src, voff, voff_m, plane_bytes](uint32_t (&dstw)[NW], uint32_t off_,
+                                                     bool mir) {
             const uint32_t off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off_);
+            const uint32_t vo = (TOPO == TOPO_KLEIN && mir) ? voff_m : voff;
             if constexpr (IO == IO_U8) {
 #pragma unroll
                 for (int j = 0; j < 2 * WL; ++j) {
-                    const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(src, voff + 16 * j,
+                    const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(src, vo + 16 * j,
                                                                           off, BML_LOAD_AUX);
                     dstw[4 * j + 0] = u.x; dstw[4 * j + 1] = u.y;
                     dstw[4 * j + 2] = u.z; dstw[4 * j + 3] = u.w;
                 }
             } else if constexpr (WL == 1) {
-                dstw[0] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off, BML_LOAD_AUX);
-                dstw[1] = __builtin_amdgcn_raw_buffer_load_b32(src, voff, off + plane_bytes,
+                dstw[0] = __builtin_amdgcn_raw_buffer_load_b32(src, vo, off, BML_LOAD_AUX);
+                dstw[1] = __builtin_amdgcn_raw_buffer_load_b32(src, vo, off + plane_bytes,
                                                                BML_LOAD_AUX);
             } else {
-                const u32x2 l = __builtin_amdgcn_raw_buffer_load_b64(src, voff, off, BML_LOAD_AUX);
-                const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(src, voff, off + plane_bytes,
+                const u32x2 l = __builtin_amdgcn_raw_buffer_load_b64(src, vo, off, BML_LOAD_AUX);
+                const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(src, vo, off + plane_bytes,
                                                                      BML_LOAD_AUX);
                 dstw[0] = l.x; dstw[1] = l.y; dstw[2] = t.x; dstw[3] = t.y;
             }
@@ -247,7 +274,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             if (d < total_in) {
-                issue(ring[d], ld_off);
+                issue(ring[d], ld_off, mirrored(d));
                 ld_off = advance(ld_off);
             }
         }
@@ -290,8 +317,25 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                             T0[i] = ring[d][WL + i];
                         }
                     }
+                    // A row across the Klein edge was loaded from the mirror
+                    // columns: reverse its words (and their order) into the
+                    // strip's frame.  Never in the FULL body, whose input
+                    // rows all lie inside the lattice's own rows.
+                    if (TOPO == TOPO_KLEIN && !FULL && mirrored(t)) {
+                        uint32_t l[WL], tt[WL];
+#pragma unroll
+                        for (int i = 0; i < WL; ++i) {
+                            l[i] = __builtin_bitreverse32(L0[WL - 1 - i]);
+                            tt[i] = __builtin_bitreverse32(T0[WL - 1 - i]);
+                        }
+#pragma unroll
+                        for (int i = 0; i < WL; ++i) {
+                            L0[i] = l[i];
+                            T0[i] = tt[i];
+                        }
+                    }
                     if (FULL || t + D < total_in) {
-                        issue(ring[d], ld_off);
+                        issue(ring[d], ld_off, mirrored(t + D));
                         ld_off = advance(ld_off);
                     }
                 }
@@ -306,8 +350,11 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                     // level k + 1 is then idle too.
                     if (!FULL && (t < 3 * k || t > h + 2 * K - 1 + k))
                         continue;
-                    const LevelOut<WL> o =
-                        level_push<WL, WRAP>(lv[k], k ? bl[k - 1] : L0, k ? bt[k - 1] : T0);
+                    // The row this level takes in is input row t - 2k; in the
+                    // FULL body it never lies across the Klein edge.
+                    const bool mir = !FULL && mirrored(t - 2 * k);
+                    const LevelOut<WL> o = level_push<WL, WRAP>(lv[k], k ? bl[k - 1] : L0,
+                                                                k ? bt[k - 1] : T0, mir);
                     const int rh = t - 2 * k - K;   // H row relative to row_a
 #pragma unroll
                     for (int i = 0; i < WL; ++i) {
@@ -437,22 +484,23 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         __hip_atomic_store(&ticket_owner->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Fills tab[k] (k = KLO..KHI) with pass_kernel<IO, k, ROW>.
-template <int IO, int ROW, int KLO, int... Ks>
+// Fills tab[k] (k = KLO..KHI) with pass_kernel<IO, k, ROW, TOPO>.
+template <int IO, int ROW, int TOPO, int KLO, int... Ks>
 inline void fill_pass_table(PassFn *tab, std::integer_sequence<int, Ks...>)
 {
-    ((tab[KLO + Ks] = pass_kernel<IO, KLO + Ks, ROW>), ...);
+    ((tab[KLO + Ks] = pass_kernel<IO, KLO + Ks, ROW, TOPO>), ...);
 }
 
-// Defined in one translation unit per (layout, mode, range of K); tab has
-// MAX_K + 1 entries.
-void pass_table_u8_lo(PassFn *tab);    // tile mode, K = 1..4
-void pass_table_u8_hi(PassFn *tab);    // tile mode, K = 5..8
-void pass_table_bp_lo(PassFn *tab);
-void pass_table_bp_hi(PassFn *tab);
-void pass_table_u8_row1(PassFn *tab);  // row mode, N = 2048, K = 1..8
-void pass_table_u8_row2(PassFn *tab);  // row mode, N = 4096
-void pass_table_bp_row1(PassFn *tab);
-void pass_table_bp_row2(PassFn *tab);
+// Each table function fills tab[k] for its range of K; tab has MAX_K + 1
+// entries.  One translation unit per (layout, column mode / K range,
+// topology): bml_pass_inst.hip compiled once per variant, so the variants
+// build in parallel.  Ranges: lo = tile mode K 1..4, hi = tile mode K 5..8,
+// row1 / row2 = row mode with one / two words per lane, K 1..8.
+#define BML_PASS_TABLE_DECL(io, range, topo) void pass_table_##io##_##range##_##topo(PassFn *tab);
+#define BML_PASS_TABLES(X, topo)                                                        \
+    X(u8, lo, topo) X(u8, hi, topo) X(u8, row1, topo) X(u8, row2, topo) X(bp, lo, topo) \
+    X(bp, hi, topo) X(bp, row1, topo) X(bp, row2, topo)
+BML_PASS_TABLES(BML_PASS_TABLE_DECL, torus)
+BML_PASS_TABLES(BML_PASS_TABLE_DECL, klein)
 
 } // namespace bml

@@ -97,6 +97,33 @@ __device__ __forceinline__ void h_row(uint32_t (&L)[WL], const uint32_t (&T)[WL]
     }
 }
 
+// The horizontal phase of a row held mirrored (cell order reversed), as the
+// Klein-bottle kernels hold the rows that lie across the glued top/bottom
+// edge: LR cars then move towards lower bit indices.  A car moves when the
+// cell on its lower side is EMPTY (word i-1, or the previous lane's last
+// word, supplies bit 31 of that neighbour), and lands one cell lower.
+template <int WL, bool WRAP>
+__device__ __forceinline__ void h_row_mirrored(uint32_t (&L)[WL], const uint32_t (&T)[WL],
+                                               uint32_t (&mv)[WL])
+{
+    uint32_t E[WL];
+#pragma unroll
+    for (int i = 0; i < WL; ++i)
+        E[i] = ~(L[i] | T[i]);
+    const uint32_t e_prev = from_prev_lane<WRAP>(E[WL - 1]);
+#pragma unroll
+    for (int i = 0; i < WL; ++i)
+        mv[i] = L[i] & __builtin_amdgcn_alignbit(E[i], i ? E[i - 1] : e_prev, 31);
+    const uint32_t mv_next = from_next_lane<WRAP>(mv[0]);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+        const uint32_t arrive = __builtin_amdgcn_alignbit(i + 1 < WL ? mv[i + 1] : mv_next,
+                                                          mv[i], 1);
+        L[i] = (L[i] & ~mv[i]) | arrive;
+        asm("" : "+v"(L[i]));
+    }
+}
+
 // ---- streaming pipeline level ----------------------------------------------
 //
 // A wavefront sweeping down a strip keeps one Level per step of the pass.
@@ -119,16 +146,22 @@ struct LevelOut {
     uint32_t mv_v[WL];           // TB movers of row r-1 (V phase)
 };
 
+// `mirrored` (wave-uniform; only Klein-bottle kernels pass true) says the
+// incoming row is held with its cell order reversed.
 template <int WL, bool WRAP>
 __device__ __forceinline__ LevelOut<WL> level_push(Level<WL> &lv, const uint32_t (&L_in)[WL],
-                                                   const uint32_t (&T_in)[WL])
+                                                   const uint32_t (&T_in)[WL],
+                                                   bool mirrored = false)
 {
     LevelOut<WL> o;
     uint32_t L[WL];
 #pragma unroll
     for (int i = 0; i < WL; ++i)
         L[i] = L_in[i];
-    h_row<WL, WRAP>(L, T_in, o.mv_h);
+    if (mirrored)
+        h_row_mirrored<WL, WRAP>(L, T_in, o.mv_h);
+    else
+        h_row<WL, WRAP>(L, T_in, o.mv_h);
 #pragma unroll
     for (int i = 0; i < WL; ++i) {
         o.l_h[i] = L[i];

@@ -70,6 +70,14 @@ class Lattice:
                    waves_per_block: int = 0) -> None:
         B.bml_set_tuning(self.handle, tile_rows, t_phases, waves_per_block)
 
+    def set_topology(self, topology: int) -> None:
+        """BML_TOPO_TORUS (default) or BML_TOPO_KLEIN for the steps that follow."""
+        B.bml_set_topology(self.handle, topology)
+
+    @property
+    def topology(self) -> int:
+        return B.bml_get_topology(self.handle)
+
     def tuning(self) -> tuple[int, int, int]:
         return B.bml_get_tuning(self.handle)
 

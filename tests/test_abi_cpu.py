@@ -140,3 +140,9 @@ def test_init_rect_rejects_bad_densities_without_gpu(B):
         rc = lib.bml_init_rect(ctypes.byref(h), 64, 64, 0, 1, lr, tb, None, 256, 512 * 1024,
                                1024 * 1024, 8, None)
         assert rc == B.BML_EINVAL, (lr, tb)
+
+
+def test_topology_calls_reject_null_handle(B):
+    lib = B.lib()
+    assert lib.bml_set_topology(None, 1) == B.BML_ESTATE
+    assert lib.bml_get_topology(None) == B.BML_ESTATE

@@ -460,6 +460,84 @@ def test_rect_group_and_host_cells(B):
             lat.close()
 
 
+# --- Klein bottle (top and bottom edges glued with a reversal) ------------
+
+KLEIN_CASES = [(32, 64), (96, 160), (200, 2048), (33, 4096), (1000, 96), (64, 3008), (40, 32)]
+KLEIN_TUNINGS = [(0, 16, 4), (8, 6, 2), (3, 12, 1), (24, 2, 1), (1, 16, 4)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("rows,cols", KLEIN_CASES, ids=[f"{r}x{c}" for r, c in KLEIN_CASES])
+def test_klein_matches_oracle(B, layout, rows, cols):
+    """Klein-bottle lattices (strips whose halo crosses the glued edge at the
+    top, the bottom or both; tile and row widths): every cell and count
+    against the oracle's Klein run, under several tunings."""
+    rng = np.random.default_rng(rows * 104729 + cols + 17 * layout)
+    for tuning in KLEIN_TUNINGS:
+        seed = int(rng.integers(0, 2**32))
+        rho_lr, rho_tb = float(rng.uniform(0.05, 0.4)), float(rng.uniform(0.05, 0.4))
+        steps = int(rng.integers(1, 2 * tuning[1] + 5))
+        say(f"klein {rows}x{cols} layout={layout} tuning={tuning} steps={steps} seed={seed} "
+            f"lr={rho_lr:.3f} tb={rho_tb:.3f}")
+        g0 = oracle.init_cells_asym(rows, cols, seed, rho_lr, rho_tb)
+        want, wst = oracle.run(g0, steps, n_threads=HOST_THREADS, topology=oracle.KLEIN)
+        with B.Lattice(rows, seed=seed, cols=cols, rho_lr=rho_lr, rho_tb=rho_tb, layout=layout,
+                       stats_cap=64) as lat:
+            lat.set_topology(B.BML_TOPO_KLEIN)
+            lat.set_tuning(*tuning)
+            lat.step(steps)
+            got = lat.cells()
+            if not np.array_equal(got, want):
+                bad = np.argwhere(got != want)
+                pytest.fail(f"{len(bad)} cells differ, first at {bad[0]}")
+            assert np.array_equal(stats_array(lat.stats(0, steps)), wst)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_klein_lone_tb_car_mirrored_then_home(B, layout):
+    rows, cols = 64, 2048
+    g = np.zeros((rows, cols), np.uint8)
+    g[5, 3] = 2
+    g[9, 40] = 1
+    with B.Lattice(rows, cols=cols, cells=g, layout=layout, stats_cap=8) as lat:
+        lat.set_topology(B.BML_TOPO_KLEIN)
+        assert lat.topology == B.BML_TOPO_KLEIN
+        lat.step(rows)
+        want, _ = oracle.run(g, rows, topology=oracle.KLEIN)
+        assert want[5, cols - 1 - 3] == 2
+        assert np.array_equal(lat.cells(), want)
+        lat.step(rows)
+        want2, _ = oracle.run(want, rows, topology=oracle.KLEIN)
+        assert np.array_equal(lat.cells(), want2)
+
+
+def test_klein_errors_and_torus_switch(B):
+    import torch
+    stream = torch.cuda.Stream()
+    a = B.Lattice(64, 0.3, 1, stream=stream)
+    b = B.Lattice(64, 0.3, 2, stream=stream)
+    try:
+        with pytest.raises(B.BmlError) as e:
+            a.set_topology(2)
+        assert e.value.code == B.BML_EINVAL
+        a.set_topology(B.BML_TOPO_KLEIN)
+        with pytest.raises(B.BmlError) as e:
+            B.step_group([a, b], 1)
+        assert e.value.code == B.BML_EINVAL
+        b.set_topology(B.BML_TOPO_KLEIN)
+        g0a, g0b = a.cells(), b.cells()
+        B.step_group([a, b], 5)
+        a.set_topology(B.BML_TOPO_TORUS)
+        a.step(3)
+        wa, _ = oracle.run(g0a, 5, topology=oracle.KLEIN)
+        wa, _ = oracle.run(wa, 3)
+        wb, _ = oracle.run(g0b, 5, topology=oracle.KLEIN)
+        assert np.array_equal(a.cells(), wa) and np.array_equal(b.cells(), wb)
+    finally:
+        a.close()
+        b.close()
+
+
 # --- the 4096 x 4096 workload, whole lattice --------------------------------
 
 @pytest.mark.parametrize("layout", LAYOUTS)
