@@ -320,6 +320,9 @@ def main() -> int:
     ap.add_argument("--probe", action="store_true",
                     help="for counter runs: a 1 GiB device copy (the calibration kernel "
                          "of known traffic), then --steps BML steps of the first lattice")
+    ap.add_argument("--topology", choices=["torus", "klein"], default="torus",
+                    help="medium/large/rect: periodic in both directions, or the Klein "
+                         "bottle (top and bottom edges glued with a reversal)")
     ap.add_argument("--tuning", type=int, nargs=3, metavar=("TILE_ROWS", "T_PHASES", "WPB"),
                     help="medium/large: run this tuning instead of the autotuned one")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("PROBE_LOG", "FETCH_DIR", "WRITE_DIR"),
@@ -357,6 +360,7 @@ def main() -> int:
     else:
         load = load_tuning
     layout = 0 if args.layout == "u8" else 1
+    topology = B.BML_TOPO_KLEIN if args.topology == "klein" else B.BML_TOPO_TORUS
 
     if args.probe:
         a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
@@ -373,6 +377,7 @@ def main() -> int:
         for lat in lats:
             if tun:
                 lat.set_tuning(*tun)
+            lat.set_topology(topology)
         B.step_group(lats, args.steps)
         torch.cuda.synchronize()
         tr, tp, wpb = lats[0].tuning()
@@ -402,6 +407,7 @@ def main() -> int:
             tun = load(lay, size_key(lt), group if mode == "joint" else None)
             if tun:
                 lat.set_tuning(*tun)
+            lat.set_topology(topology)
             lats.append(lat)
         return lats
 
@@ -501,7 +507,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": args.layout,
         "data": "synthetic (SplitMix64 iid lattices, seeded)",
-        "config": {"workload": wl.name, "layout": args.layout,
+        "config": {"workload": wl.name + ("-klein" if args.topology == "klein" else ""),
+                   "layout": args.layout, "topology": args.topology,
                    "lattices": [[lt.n, lt.cols or lt.n, lt.rho_lr if lt.rho_lr is not None
                                  else lt.rho / 2, lt.rho_tb if lt.rho_tb is not None
                                  else lt.rho / 2, lt.seed] for lt in wl.lattices],
@@ -534,10 +541,11 @@ def main() -> int:
             for lay in (0, 1):
                 for i, lt in enumerate(wl.lattices):
                     with B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps,
-                                   device=dev) as lat:
+                                   device=dev, **lt.kwargs()) as lat:
                         tun = load(lay, size_key(lt))
                         if tun:
                             lat.set_tuning(*tun)
+                        lat.set_topology(topology)
                         lat.step(wl.steps)
                         torch.cuda.synchronize()
                         e0 = torch.cuda.Event(enable_timing=True)

@@ -221,6 +221,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         const uint32_t voff_m = IO == IO_U8 ? word_m * 32u : word_m * 4u;
         // Input row s of the strip lies across the glued top/bottom edge.
         const int lattice_rows = a.rows;
+        const bool edge_strip = row_a < K || row_a + h + K > lattice_rows;
         auto mirrored = [row_a, lattice_rows](int s) {
             if constexpr (TOPO == TOPO_KLEIN) {
                 const int g = row_a - K + s;
@@ -295,8 +296,12 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
             acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0;
         }
 
-        auto body = [&](int t0, auto full_tag) {
+        // EDGE: this strip's halo may cross the Klein edge (only the first
+        // and last strips of a Klein lattice); every other strip runs the
+        // torus code (one-word rows; see below).
+        auto body = [&](int t0, auto full_tag, auto edge_tag) {
             constexpr bool FULL = decltype(full_tag)::value;
+            constexpr bool EDGE = TOPO == TOPO_KLEIN && decltype(edge_tag)::value;
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 const int t = t0 + d;
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                     // columns: reverse its words (and their order) into the
                     // strip's frame.  Never in the FULL body, whose input
                     // rows all lie inside the lattice's own rows.
-                    if (TOPO == TOPO_KLEIN && !FULL && mirrored(t)) {
+                    if (EDGE && !FULL && mirrored(t)) {
                         uint32_t l[WL], tt[WL];
 #pragma unroll
                         for (int i = 0; i < WL; ++i) {
@@ -335,7 +340,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                         }
                     }
                     if (FULL || t + D < total_in) {
-                        issue(ring[d], ld_off, mirrored(t + D));
+                        issue(ring[d], ld_off, EDGE && (FULL || edge_strip) && mirrored(t + D));
                         ld_off = advance(ld_off);
                     }
                 }
@@ -352,7 +357,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                         continue;
                     // The row this level takes in is input row t - 2k; in the
                     // FULL body it never lies across the Klein edge.
-                    const bool mir = !FULL && mirrored(t - 2 * k);
+                    const bool mir = EDGE && !FULL && mirrored(t - 2 * k);
                     const LevelOut<WL> o = level_push<WL, WRAP>(lv[k], k ? bl[k - 1] : L0,
                                                                 k ? bt[k - 1] : T0, mir);
                     const int rh = t - 2 * k - K;   // H row relative to row_a
@@ -424,10 +429,17 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
             // prefetch stays inside the strip for all D iterations.
 #ifndef BML_NO_FULL_BODY
             if (t0 >= 3 * K - 1 && t0 + D <= h + K && t0 + 2 * D <= total_in)
-                body(t0, std::true_type{});
+                // (its only edge work is choosing the mirror offset of a
+                // prefetched bottom halo row: one select per load)
+                body(t0, std::true_type{}, std::bool_constant<TOPO == TOPO_KLEIN>{});
             else
 #endif
-                body(t0, std::false_type{});
+            // (two-word rows keep one body: a second copy would push them
+            // past 256 VGPRs)
+            if (TOPO == TOPO_KLEIN && (WL > 1 || edge_strip))
+                body(t0, std::false_type{}, std::true_type{});
+            else
+                body(t0, std::false_type{}, std::false_type{});
         }
 
         // Fold this item's counts into the wave totals (halo and duplicate
