@@ -72,6 +72,8 @@ def lib() -> ctypes.CDLL:
         L.bmlo_run.restype = None
         L.bmlo_run_topo.argtypes = [i64, i64, vp, vp, i64, vp, i32, i32]
         L.bmlo_run_topo.restype = None
+        L.bmlo_run_model2.argtypes = [i64, i64, vp, vp, i64, i64, u64, vp, i32]
+        L.bmlo_run_model2.restype = None
         L.bmlo_phase_v_topo.argtypes = [i64, i64, vp, vp, i32]
         L.bmlo_phase_v_topo.restype = i64
         L.bmlo_run_many.argtypes = [i64, vp, vp, vp, vp, vp, i64, i32]
@@ -163,6 +165,21 @@ def run(cells: np.ndarray, steps: int, n_threads: int = 1, topology: int = TORUS
     stats = np.zeros((max(steps, 0), 4), dtype=np.uint32)
     lib().bmlo_run_topo(a.shape[0], a.shape[1], _ptr(a), _ptr(tmp), int(steps),
                         _ptr(stats), int(n_threads), int(topology))
+    return a, stats
+
+
+def run_model2(cells: np.ndarray, steps: int, coin_seed: int, step0: int = 0,
+               n_threads: int = 1) -> tuple[np.ndarray, np.ndarray]:
+    """Model II (Sec. 2): both car types move in one phase per step; a
+    contested empty cell goes to the LR car when the step's counter-based
+    coin for that cell is 1 (bit j%32 of SplitMix64 output
+    step*rows*W + i*W + j//32 of stream coin_seed, W = ceil(cols/32)).
+    step0 is the global index of the first step (it selects the coins)."""
+    a = _u8(cells).copy()
+    tmp = np.empty_like(a)
+    stats = np.zeros((max(steps, 0), 4), dtype=np.uint32)
+    lib().bmlo_run_model2(a.shape[0], a.shape[1], _ptr(a), _ptr(tmp), int(steps), int(step0),
+                          coin_seed & (2**64 - 1), _ptr(stats), int(n_threads))
     return a, stats
 
 

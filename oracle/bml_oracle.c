@@ -260,6 +260,92 @@ static void run_topo(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
     (void)nt; /* unused when built without OpenMP */
 }
 
+/* ------------------------------------------------------------------------ */
+/* Model II (Sec. 2): every car advances in one phase per step.  A car moves */
+/* when its target cell (right for LR, below for TB) is EMPTY before the    */
+/* step; if an EMPTY cell is the target of both an LR car (its left         */
+/* neighbour) and a TB car (its top neighbour), one of them is chosen at    */
+/* random to move and the other stays.  The paper gives no distribution;    */
+/* here it is a fair coin from a counter-based generator: at global step s, */
+/* the coin of cell (i, j) is bit (j mod 32) of the low 32 bits of the      */
+/* SplitMix64 output number s*(rows*W) + i*W + j/32 of stream `coin_seed`,  */
+/* W = ceil(cols/32); 1 means the LR car moves.  Torus only.                */
+/* stats per step: n_lr, moved_lr, n_tb, moved_tb after that one phase.     */
+/* ------------------------------------------------------------------------ */
+static int model2_coin(uint64_t coin_seed, int64_t step, int64_t rows, int64_t cols,
+                       int64_t i, int64_t j)
+{
+    int64_t words = (cols + 31) / 32;
+    uint64_t k = (uint64_t)step * (uint64_t)(rows * words) + (uint64_t)(i * words + j / 32);
+    uint32_t z = (uint32_t)bmlo_splitmix64(coin_seed, k);
+    return (int)((z >> (j % 32)) & 1u);
+}
+
+static void model2_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
+                        const uint8_t *cur, uint8_t *next, uint64_t coin_seed, int64_t step,
+                        int64_t *moved_lr, int64_t *moved_tb)
+{
+    for (int64_t i = r0; i < r1; i++) {
+        int64_t up = (i - 1 + rows) % rows, down = (i + 1) % rows;
+        for (int64_t j = 0; j < cols; j++) {
+            int64_t left = (j - 1 + cols) % cols, right = (j + 1) % cols;
+            uint8_t c = cur[i * cols + j], out = c;
+            if (c == EMPTY) {
+                int from_left = cur[i * cols + left] == LR;
+                int from_top = cur[up * cols + j] == TB;
+                if (from_left && from_top)
+                    out = model2_coin(coin_seed, step, rows, cols, i, j) ? LR : TB;
+                else if (from_left)
+                    out = LR;
+                else if (from_top)
+                    out = TB;
+            } else if (c == LR && cur[i * cols + right] == EMPTY) {
+                /* a TB car above the target competes for it */
+                int contested = cur[up * cols + right] == TB;
+                if (!contested || model2_coin(coin_seed, step, rows, cols, i, right)) {
+                    out = EMPTY;
+                    (*moved_lr)++;
+                }
+            } else if (c == TB && cur[down * cols + j] == EMPTY) {
+                /* an LR car left of the target competes for it */
+                int contested = cur[down * cols + left] == LR;
+                if (!contested || !model2_coin(coin_seed, step, rows, cols, down, j)) {
+                    out = EMPTY;
+                    (*moved_tb)++;
+                }
+            }
+            next[i * cols + j] = out;
+        }
+    }
+}
+
+/* `steps` Model II steps starting at global step `step0` (the coin index). */
+void bmlo_run_model2(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp, int64_t steps,
+                     int64_t step0, uint64_t coin_seed, uint32_t *stats, int32_t n_threads)
+{
+    int nt = n_threads > 0 ? n_threads : 1;
+    for (int64_t s = 0; s < steps; s++) {
+        int64_t moved_lr = 0, moved_tb = 0;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : moved_lr, moved_tb)
+#endif
+        for (int64_t i = 0; i < rows; i++) {
+            int64_t ml = 0, mt = 0;
+            model2_rows(i, i + 1, rows, cols, cells, tmp, coin_seed, step0 + s, &ml, &mt);
+            moved_lr += ml;
+            moved_tb += mt;
+        }
+        memcpy(cells, tmp, (size_t)(rows * cols));
+        if (stats) {
+            stats[4 * s + 0] = (uint32_t)count_value(cells, rows * cols, LR);
+            stats[4 * s + 1] = (uint32_t)moved_lr;
+            stats[4 * s + 2] = (uint32_t)count_value(cells, rows * cols, TB);
+            stats[4 * s + 3] = (uint32_t)moved_tb;
+        }
+    }
+    (void)nt;
+}
+
 /* Many independent square lattices, one lattice per thread at a time
  * (dynamic schedule): lattice b has sizes[b] x sizes[b] cells starting at
  * cells + offsets[b]; its per-step counts (4 per step, as in bmlo_run) go to

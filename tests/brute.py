@@ -57,3 +57,64 @@ def run(grid, steps, klein=False):
         grid, c = step(grid, klein)
         stats.append(c)
     return grid, stats
+
+
+# --- Model II (Sec. 2): both types in one phase, random winner on conflict ---
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(state, k):
+    """k-th output of the SplitMix64 stream started at `state` (Steele, Lea
+    and Flood's generator, written out here independently of the oracle)."""
+    z = (state + (k + 1) * 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def model2_coin(seed, step, rows, cols, i, j):
+    words = (cols + 31) // 32
+    z = splitmix64(seed, step * rows * words + i * words + j // 32) & 0xFFFFFFFF
+    return (z >> (j % 32)) & 1          # 1: the LR car takes the contested cell
+
+
+def model2_step(grid, seed, step):
+    """Cars list their targets on the pre-step lattice; a target claimed by
+    an LR and a TB car goes to one of them by the coin; every winner moves at
+    once.  Returns (grid, (n_lr, moved_lr, n_tb, moved_tb))."""
+    rows, cols = len(grid), len(grid[0])
+    claims = {}
+    for i in range(rows):
+        for j in range(cols):
+            kind = grid[i][j]
+            if kind == EMPTY:
+                continue
+            t = target(i, j, kind, rows, cols)
+            if grid[t[0]][t[1]] == EMPTY:
+                claims.setdefault(t, []).append(((i, j), kind))
+    moves = []
+    for (ti, tj), cars in claims.items():
+        assert len(cars) <= 2
+        if len(cars) == 2:
+            want = LR if model2_coin(seed, step, rows, cols, ti, tj) else TB
+            cars = [c for c in cars if c[1] == want]
+        moves.append((cars[0][0], (ti, tj), cars[0][1]))
+    new = [list(r) for r in grid]
+    for (si, sj), _, _ in moves:
+        new[si][sj] = EMPTY
+    for _, (ti, tj), kind in moves:
+        new[ti][tj] = kind
+    n_lr = sum(c == LR for r in new for c in r)
+    n_tb = sum(c == TB for r in new for c in r)
+    mlr = sum(1 for m in moves if m[2] == LR)
+    return new, (n_lr, mlr, n_tb, len(moves) - mlr)
+
+
+def run_model2(grid, steps, seed, step0=0):
+    grid = [list(r) for r in grid]
+    stats = []
+    for s in range(steps):
+        grid, c = model2_step(grid, seed, step0 + s)
+        stats.append(c)
+    return grid, stats

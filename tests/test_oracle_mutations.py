@@ -39,6 +39,12 @@ MUTATIONS = [
     ("Klein seam mirrors at the wrong row",
      "uint8_t top = cur[up * cols + v_col(j, cols, i == 0, topology)];",
      "uint8_t top = cur[up * cols + v_col(j, cols, i == 1, topology)];"),
+    ("Model II: the TB car obeys the coin the wrong way round",
+     "if (!contested || !model2_coin(coin_seed, step, rows, cols, down, j)) {",
+     "if (!contested || model2_coin(coin_seed, step, rows, cols, down, j)) {"),
+    ("Model II: the LR car reads the coin of its own cell",
+     "if (!contested || model2_coin(coin_seed, step, rows, cols, i, right)) {",
+     "if (!contested || model2_coin(coin_seed, step, rows, cols, i, j)) {"),
     ("asymmetric TB threshold without the LR share", "*thr_tb = (uint64_t)ldexp(rho_lr + rho_tb, 53);",
      "*thr_tb = (uint64_t)ldexp(rho_tb, 53);"),
 ]

@@ -333,6 +333,75 @@ def test_klein_without_tb_cars_is_the_torus():
     assert np.array_equal(oracle.run(g, 9, topology=KLEIN)[0], oracle.run(g, 9)[0])
 
 
+# --- Model II (Sec. 2): one phase per step, random winner on conflicts ----
+
+@pytest.mark.parametrize("rows,cols", [(1, 4), (2, 2), (3, 5), (4, 4), (5, 3), (6, 7), (8, 8),
+                                       (3, 40)])
+def test_model2_matches_brute_force(rows, cols):
+    rng = np.random.default_rng(rows * 977 + cols)
+    for trial in range(20):
+        p = rng.random()
+        q = rng.random() * (1 - p)
+        g = workloads.random_lattice(rng, rows, cols, p, q)
+        seed, step0 = int(rng.integers(0, 2**63)), int(rng.integers(0, 1000))
+        og, ost = oracle.run_model2(g, 5, seed, step0)
+        bg, bst = brute.run_model2(g.tolist(), 5, seed, step0)
+        assert np.array_equal(og, np.array(bg, dtype=np.uint8))
+        assert [tuple(int(x) for x in s) for s in ost] == bst
+
+
+def test_model2_without_conflicts_is_one_phase_of_model1():
+    """With only one car type nothing is ever contested: a Model II step is
+    a horizontal (LR only) or vertical (TB only) phase of Model I."""
+    rng = np.random.default_rng(9)
+    for kind in (LR, TB):
+        g = workloads.random_lattice(rng, 12, 20, 0.45 if kind == LR else 0.0,
+                                     0.45 if kind == TB else 0.0)
+        got, st = oracle.run_model2(g, 1, 5)
+        want, moved = (oracle.phase_h if kind == LR else oracle.phase_v)(g)
+        assert np.array_equal(got, want)
+        assert int(st[0, 1] + st[0, 3]) == moved
+
+
+def test_model2_contested_cells_get_exactly_one_car_and_a_fair_coin():
+    """LR cars at (2a+1, 2b) and TB cars at (2a, 2b+1) make every cell
+    (2a+1, 2b+1) an empty cell claimed by both: each step exactly one of the
+    two enters, and the LR share over many steps is 1/2 within 5 sigma."""
+    rows, cols = 64, 64
+    lr_wins = trials = 0
+    for step0 in range(0, 40, 4):
+        g = np.zeros((rows, cols), np.uint8)
+        g[1::2, 0::2] = LR        # left of each target
+        g[0::2, 1::2] = TB        # above each target
+        out, st = oracle.run_model2(g, 1, 0xC0FFEE, step0)
+        targets = out[1::2, 1::2]
+        assert ((targets == LR) | (targets == TB)).all()
+        lr_wins += int((targets == LR).sum())
+        trials += targets.size
+        assert int(st[0, 1] + st[0, 3]) == targets.size
+    p = lr_wins / trials
+    assert abs(p - 0.5) <= 5 * np.sqrt(0.25 / trials)
+
+
+def test_model2_conserves_cars_per_row_and_column():
+    rng = np.random.default_rng(21)
+    g = workloads.random_lattice(rng, 30, 26, 0.3, 0.3)
+    out, st = oracle.run_model2(g, 50, 77)
+    assert np.array_equal((out == LR).sum(axis=1), (g == LR).sum(axis=1))
+    assert np.array_equal((out == TB).sum(axis=0), (g == TB).sum(axis=0))
+    assert (st[:, 0] == (g == LR).sum()).all() and (st[:, 2] == (g == TB).sum()).all()
+
+
+def test_model2_step_index_selects_the_coins():
+    """Running 3 + 4 steps with the global step carried over equals 7 steps."""
+    rng = np.random.default_rng(4)
+    g = workloads.random_lattice(rng, 16, 40, 0.35, 0.35)
+    a, sa = oracle.run_model2(g, 7, 11)
+    b1, s1 = oracle.run_model2(g, 3, 11)
+    b2, s2 = oracle.run_model2(b1, 4, 11, step0=3)
+    assert np.array_equal(a, b2) and np.array_equal(sa, np.concatenate([s1, s2]))
+
+
 # --- asymmetric placement (unequal LR and TB numbers, Sec. 2 extensions) ---
 
 def _floor_times_2_53(x: float) -> int:
