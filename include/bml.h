@@ -112,7 +112,7 @@ int bml_init(bml_lattice **out, int32_t n, int32_t layout, uint64_t seed,
  *                bml_init_rect(n, n, rho/2, rho/2).
  * Everything else (buffers, ring, stream, errors, later calls) is as for
  * bml_init; bml_get_cells returns rows*cols bytes; bml_step_group needs
- * equal rows, cols and topology. */
+ * equal rows, cols, topology and model. */
 int bml_state_bytes_rect(int32_t rows, int32_t cols, int32_t layout, size_t *bytes);
 int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
                   uint64_t seed, double rho_lr, double rho_tb, const uint8_t *cells_host,
@@ -165,6 +165,21 @@ int bml_initial_counts(const bml_lattice *L, uint64_t *n_lr, uint64_t *n_tb);
  * ESTATE on an invalid handle.  bml_get_topology returns it (or ESTATE). */
 int bml_set_topology(bml_lattice *L, int32_t topology);
 int bml_get_topology(const bml_lattice *L);
+
+/* Update rule for the steps that follow.  model 1 (after init): the model
+ * of Sec. 2, a horizontal then a vertical phase per step.  model 2: Model II
+ * (Sec. 2): every car advances in one phase per step when its target cell
+ * (right for LR, below for TB) is EMPTY before the step; an EMPTY cell that
+ * is the target of both an LR car and a TB car goes to one of them by a fair
+ * coin.  The paper gives no distribution; here, at global step s (the
+ * handle's step count), the coin of cell (i, j) is bit (j mod 32) of the low
+ * 32 bits of the SplitMix64 output number s*rows*W + i*W + j/32 of the stream
+ * started at `coin_seed` (W = cols/32), 1 meaning the LR car moves.  The
+ * counts of a Model II step are taken after its one phase, and a kernel
+ * pass still advances t_phases/2 steps (bml_set_tuning).  Torus only:
+ * EINVAL with the Klein topology, or for another model value; ESTATE on an
+ * invalid handle. */
+int bml_set_model(bml_lattice *L, int32_t model, uint64_t coin_seed);
 
 /* Launch shape of the step kernels.  Each wavefront streams down a strip of
  * the lattice `tile_rows` output rows tall (plus t_phases/2 halo rows above

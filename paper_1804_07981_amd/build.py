@@ -14,13 +14,15 @@ LIB = os.path.join(HERE, "libbml.so")
 # The step kernels: bml_pass_inst.hip compiled once per (layout, column
 # mode / range of K, topology); see bml_pass.hpp.
 PASS_RANGES = {"lo": (0, 1, 4), "hi": (0, 5, 4), "row1": (1, 1, 8), "row2": (2, 1, 8)}
+# variant name -> (topology, model)
+PASS_KINDS = {"torus": ("TOPO_TORUS", 1), "klein": ("TOPO_KLEIN", 1), "model2": ("TOPO_TORUS", 2)}
 PASS_VARIANTS = [
-    (f"pass_table_{io}_{rng}_{topo}",
+    (f"pass_table_{io}_{rng}_{kind}",
      [f"-DBML_INST_IO={'IO_U8' if io == 'u8' else 'IO_BP'}", f"-DBML_INST_ROW={row}",
-      f"-DBML_INST_TOPO={'TOPO_TORUS' if topo == 'torus' else 'TOPO_KLEIN'}",
+      f"-DBML_INST_TOPO={topo}", f"-DBML_INST_MODEL={model}",
       f"-DBML_INST_KLO={klo}", f"-DBML_INST_KN={kn}",
-      f"-DBML_INST_NAME=pass_table_{io}_{rng}_{topo}"])
-    for topo in ("torus", "klein") for io in ("u8", "bp")
+      f"-DBML_INST_NAME=pass_table_{io}_{rng}_{kind}"])
+    for kind, (topo, model) in PASS_KINDS.items() for io in ("u8", "bp")
     for rng, (row, klo, kn) in PASS_RANGES.items()]
 SOURCES = ["bml_lattice.hip", "bml_batch.hip",
            "bml_batch_u8.hip", "bml_batch_bp.hip", "bml_mlp.hip"]

@@ -197,28 +197,33 @@ __global__ void zero_words_kernel(uint32_t *p, int64_t count)
 // for N = 2048 m (the wavefront holds a whole row, m words per lane).
 constexpr int PASS_MODES = 3;
 
+// Kernel kinds: the model of Sec. 2 on the torus or the Klein bottle, and
+// Model II on the torus.
+enum { KIND_TORUS = 0, KIND_KLEIN = 1, KIND_MODEL2 = 2, PASS_KINDS = 3 };
+
 struct KernelTable {
-    PassFn fn[2][PASS_MODES][2][MAX_K + 1] = {};   // [topology][mode][io][k]
+    PassFn fn[PASS_KINDS][PASS_MODES][2][MAX_K + 1] = {};   // [kind][mode][io][k]
     KernelTable()
     {
-        pass_table_u8_lo_torus(fn[TOPO_TORUS][0][IO_U8]);
-        pass_table_u8_hi_torus(fn[TOPO_TORUS][0][IO_U8]);
-        pass_table_bp_lo_torus(fn[TOPO_TORUS][0][IO_BP]);
-        pass_table_bp_hi_torus(fn[TOPO_TORUS][0][IO_BP]);
-        pass_table_u8_row1_torus(fn[TOPO_TORUS][1][IO_U8]);
-        pass_table_bp_row1_torus(fn[TOPO_TORUS][1][IO_BP]);
-        pass_table_u8_row2_torus(fn[TOPO_TORUS][2][IO_U8]);
-        pass_table_bp_row2_torus(fn[TOPO_TORUS][2][IO_BP]);
-        pass_table_u8_lo_klein(fn[TOPO_KLEIN][0][IO_U8]);
-        pass_table_u8_hi_klein(fn[TOPO_KLEIN][0][IO_U8]);
-        pass_table_bp_lo_klein(fn[TOPO_KLEIN][0][IO_BP]);
-        pass_table_bp_hi_klein(fn[TOPO_KLEIN][0][IO_BP]);
-        pass_table_u8_row1_klein(fn[TOPO_KLEIN][1][IO_U8]);
-        pass_table_bp_row1_klein(fn[TOPO_KLEIN][1][IO_BP]);
-        pass_table_u8_row2_klein(fn[TOPO_KLEIN][2][IO_U8]);
-        pass_table_bp_row2_klein(fn[TOPO_KLEIN][2][IO_BP]);
+#define BML_FILL(io, range, kind, KIND, MODE, IO) pass_table_##io##_##range##_##kind(fn[KIND][MODE][IO]);
+#define BML_FILL_KIND(kind, KIND)                                                          \
+    BML_FILL(u8, lo, kind, KIND, 0, IO_U8) BML_FILL(u8, hi, kind, KIND, 0, IO_U8)             \
+    BML_FILL(bp, lo, kind, KIND, 0, IO_BP) BML_FILL(bp, hi, kind, KIND, 0, IO_BP)             \
+    BML_FILL(u8, row1, kind, KIND, 1, IO_U8) BML_FILL(bp, row1, kind, KIND, 1, IO_BP)         \
+    BML_FILL(u8, row2, kind, KIND, 2, IO_U8) BML_FILL(bp, row2, kind, KIND, 2, IO_BP)
+        BML_FILL_KIND(torus, KIND_TORUS)
+        BML_FILL_KIND(klein, KIND_KLEIN)
+        BML_FILL_KIND(model2, KIND_MODEL2)
+#undef BML_FILL_KIND
+#undef BML_FILL
     }
 };
+
+static const KernelTable &kernels()
+{
+    static KernelTable t;
+    return t;
+}
 
 // Row mode when a row is exactly 64 or 128 words (one wavefront).
 static int pass_mode(int cols)
@@ -227,29 +232,23 @@ static int pass_mode(int cols)
     return words == 64 ? 1 : words == 128 ? 2 : 0;
 }
 
-static const KernelTable &kernels()
-{
-    static KernelTable t;
-    return t;
-}
-
 // Resident blocks per CU of a pass kernel at `threads` threads per block.
-static int resident_blocks(int topo, int mode, int io, int k, int threads, int *out)
+static int resident_blocks(int kind, int mode, int io, int k, int threads, int *out)
 {
     static std::mutex mu;
-    static int cache[8][2][PASS_MODES][2][MAX_K + 1][3];   // [dev][topo][mode][io][k][wpb]
+    static int cache[8][PASS_KINDS][PASS_MODES][2][MAX_K + 1][3];   // [dev][kind][mode][io][k][wpb]
     int dev = 0;
     BML_HIP(hipGetDevice(&dev));
     int wl = threads == 64 ? 0 : threads == 128 ? 1 : 2;
     std::lock_guard<std::mutex> lock(mu);
-    int *c = dev < 8 ? &cache[dev][topo][mode][io][k][wl] : nullptr;
+    int *c = dev < 8 ? &cache[dev][kind][mode][io][k][wl] : nullptr;
     if (c && *c > 0) {
         *out = *c;
         return BML_OK;
     }
     int nb = 0;
     BML_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(kernels().fn[topo][mode][io][k]), threads, 0));
+        &nb, reinterpret_cast<const void *>(kernels().fn[kind][mode][io][k]), threads, 0));
     if (nb < 1)
         nb = 1;
     if (c)
@@ -361,6 +360,8 @@ using namespace bml;
 struct bml_lattice {
     int32_t rows = 0, cols = 0, layout = 0;
     int32_t topology = 0;                     // BML_TOPO_TORUS / BML_TOPO_KLEIN
+    int32_t model = 1;                        // 1: Sec. 2's model; 2: Model II
+    uint64_t coin_seed = 0;                   // Model II conflict coins
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
     uint32_t *stats = nullptr;
@@ -641,7 +642,23 @@ int bml_set_topology(bml_lattice *L, int32_t topology)
         return fail(BML_ESTATE, "invalid handle");
     if (topology != BML_TOPO_TORUS && topology != BML_TOPO_KLEIN)
         return fail(BML_EINVAL, "unknown topology %d", topology);
+    if (topology == BML_TOPO_KLEIN && L->model == 2)
+        return fail(BML_EINVAL, "Model II runs on the torus only");
     L->topology = topology;
+    return BML_OK;
+}
+
+int bml_set_model(bml_lattice *L, int32_t model, uint64_t coin_seed)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    if (model != 1 && model != 2)
+        return fail(BML_EINVAL, "model=%d must be 1 or 2", model);
+    if (model == 2 && L->topology != BML_TOPO_TORUS)
+        return fail(BML_EINVAL, "Model II runs on the torus only");
+    L->model = model;
+    L->coin_seed = coin_seed;
     return BML_OK;
 }
 
@@ -746,6 +763,8 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
                 pl.slot[j] = (int32_t)((step0[i] + j) % G[i]->cap);
             }
         a.any_rec |= pl.rec_mask;
+        pl.step0 = (uint64_t)step0[i];
+        pl.coin_seed = G[i]->coin_seed;
     }
     a.rows = L->rows;
     a.words = L->cols / 32;
@@ -753,7 +772,9 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
     a.tiles_x = mode ? 1 : (a.words + TILE_WORDS - 1) / TILE_WORDS;
     const int threads = 64 * L->wpb;
     int per_cu = 1;
-    int rc = resident_blocks(L->topology, mode, io, k, threads, &per_cu);
+    const int kind = L->model == 2 ? KIND_MODEL2 : L->topology == BML_TOPO_KLEIN ? KIND_KLEIN
+                                                                                : KIND_TORUS;
+    int rc = resident_blocks(kind, mode, io, k, threads, &per_cu);
     if (rc)
         return rc;
     const int64_t max_blocks = (int64_t)per_cu * L->dev.cu_count;
@@ -787,7 +808,7 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
             grid = max_blocks / 8 * 8;
     }
     a.xcd_split = (grid >= 8 && grid % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(kernels().fn[L->topology][mode][io][k], dim3((unsigned)grid), dim3(threads), 0,
+    hipLaunchKernelGGL(kernels().fn[kind][mode][io][k], dim3((unsigned)grid), dim3(threads), 0,
                        L->stream, a);
     BML_HIP(hipGetLastError());
     for (int i = 0; i < count; ++i) {
@@ -851,8 +872,9 @@ int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps)
                 return fail(BML_EINVAL, "handle %d appears twice", i);
         const bml_lattice *L0 = handles[0], *Li = handles[i];
         if (Li->rows != L0->rows || Li->cols != L0->cols || Li->layout != L0->layout ||
-            Li->topology != L0->topology)
-            return fail(BML_EINVAL, "lattice %d differs in size, layout or topology from lattice 0", i);
+            Li->topology != L0->topology || Li->model != L0->model)
+            return fail(BML_EINVAL, "lattice %d differs in size, layout, topology or model from "
+                                    "lattice 0", i);
         if (Li->tile_rows != L0->tile_rows || Li->t_phases != L0->t_phases ||
             Li->wpb != L0->wpb)
             return fail(BML_EINVAL, "lattice %d has another tuning than lattice 0", i);

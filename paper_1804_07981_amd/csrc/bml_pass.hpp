@@ -62,6 +62,8 @@ struct PassLattice {
     uint32_t rec_mask;       // bit k set: record the counts of step k of this pass
     int32_t slot[MAX_K];     // ring slot of step k
     int32_t pad;
+    uint64_t step0;          // Model II: global index of the pass's first step
+    uint64_t coin_seed;      // Model II: stream of the conflict coins
 };
 
 // A launch advances n_lat lattices of the same size and layout by K steps;
@@ -132,10 +134,14 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // lower bit indices.  In that frame the vertical neighbours of every row are
 // simply the rows before and after it.  Output rows never lie across the
 // edge, so stores and counts are unchanged.
-template <int IO, int K, int ROW, int TOPO>
+// MODEL = 1: the model of Sec. 2 (horizontal then vertical phase).
+// MODEL = 2: Model II (both car types in one phase, a coin on conflicts;
+// level_push_model2), torus only.
+template <int IO, int K, int ROW, int TOPO, int MODEL>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
     static_assert(K >= 1 && K <= MAX_K, "bad steps per pass");
+    static_assert(MODEL == 1 || (MODEL == 2 && TOPO == TOPO_TORUS), "Model II on the torus");
     static_assert(ROW >= 0 && ROW <= 2, "row mode holds at most 2 words per lane");
     constexpr int WL = ROW ? ROW : 1;        // words per lane
     constexpr bool WRAP = ROW > 0;
@@ -357,9 +363,25 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                         continue;
                     // The row this level takes in is input row t - 2k; in the
                     // FULL body it never lies across the Klein edge.
-                    const bool mir = EDGE && !FULL && mirrored(t - 2 * k);
-                    const LevelOut<WL> o = level_push<WL, WRAP>(lv[k], k ? bl[k - 1] : L0,
-                                                                k ? bt[k - 1] : T0, mir);
+                    LevelOut<WL> o;
+                    if constexpr (MODEL == 2) {
+                        // coins of input row t - 2k at global step step0 + k
+                        const int g0 = row_a - K + (t - 2 * k);
+                        const int g = g0 < 0 ? g0 + a.rows : g0 >= a.rows ? g0 - a.rows : g0;
+                        const uint64_t base =
+                            (a.lat[li].step0 + (uint64_t)k) * (uint64_t)a.rows * (uint64_t)a.words +
+                            (uint64_t)g * (uint64_t)a.words;
+                        uint32_t coin[WL];
+#pragma unroll
+                        for (int i = 0; i < WL; ++i)
+                            coin[i] = model2_coin_word(a.lat[li].coin_seed, base + word + i);
+                        o = level_push_model2<WL, WRAP>(lv[k], k ? bl[k - 1] : L0,
+                                                         k ? bt[k - 1] : T0, coin);
+                    } else {
+                        const bool mir = EDGE && !FULL && mirrored(t - 2 * k);
+                        o = level_push<WL, WRAP>(lv[k], k ? bl[k - 1] : L0, k ? bt[k - 1] : T0,
+                                                 mir);
+                    }
                     const int rh = t - 2 * k - K;   // H row relative to row_a
 #pragma unroll
                     for (int i = 0; i < WL; ++i) {
@@ -496,11 +518,11 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         __hip_atomic_store(&ticket_owner->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Fills tab[k] (k = KLO..KHI) with pass_kernel<IO, k, ROW, TOPO>.
-template <int IO, int ROW, int TOPO, int KLO, int... Ks>
+// Fills tab[k] (k = KLO..KHI) with pass_kernel<IO, k, ROW, TOPO, MODEL>.
+template <int IO, int ROW, int TOPO, int MODEL, int KLO, int... Ks>
 inline void fill_pass_table(PassFn *tab, std::integer_sequence<int, Ks...>)
 {
-    ((tab[KLO + Ks] = pass_kernel<IO, KLO + Ks, ROW, TOPO>), ...);
+    ((tab[KLO + Ks] = pass_kernel<IO, KLO + Ks, ROW, TOPO, MODEL>), ...);
 }
 
 // Each table function fills tab[k] for its range of K; tab has MAX_K + 1
@@ -514,5 +536,6 @@ inline void fill_pass_table(PassFn *tab, std::integer_sequence<int, Ks...>)
     X(bp, hi, topo) X(bp, row1, topo) X(bp, row2, topo)
 BML_PASS_TABLES(BML_PASS_TABLE_DECL, torus)
 BML_PASS_TABLES(BML_PASS_TABLE_DECL, klein)
+BML_PASS_TABLES(BML_PASS_TABLE_DECL, model2)   // Model II, torus
 
 } // namespace bml

@@ -178,6 +178,83 @@ __device__ __forceinline__ LevelOut<WL> level_push(Level<WL> &lv, const uint32_t
     return o;
 }
 
+// ---- Model II level ----------------------------------------------------------
+//
+// Model II (Sec. 2): every car advances in one phase per step; an EMPTY
+// cell claimed by both an LR car (on its left) and a TB car (above it)
+// goes to one of them by a coin (coin bit 1: the LR car moves).  With the
+// same skew as level_push: on receiving row r (before this step) the level
+// finishes row r itself for the LR cars (their claims need row r-1's TB
+// cars, already held) and finishes row r-1 for the TB cars (their targets
+// and claims are in row r).  In the bit words, cell j+1 of a word is bit
+// j+1, continued into the next word / lane.
+template <int WL, bool WRAP>
+__device__ __forceinline__ LevelOut<WL> level_push_model2(Level<WL> &lv,
+                                                          const uint32_t (&L_in)[WL],
+                                                          const uint32_t (&T_in)[WL],
+                                                          const uint32_t (&coin)[WL])
+{
+    LevelOut<WL> o;
+    uint32_t E[WL], from_left[WL], claimed[WL], lr_loses[WL], mv[WL];
+#pragma unroll
+    for (int i = 0; i < WL; ++i)
+        E[i] = ~(L_in[i] | T_in[i]);
+    // LR car on the left of each cell (bit j <- bit j-1, previous lane's
+    // last word supplies bit 0).
+    const uint32_t l_prev = from_prev_lane<WRAP>(L_in[WL - 1]);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+        from_left[i] = __builtin_amdgcn_alignbit(L_in[i], i ? L_in[i - 1] : l_prev, 31);
+        claimed[i] = E[i] & from_left[i] & lv.T[i];   // TB car above, too
+        lr_loses[i] = claimed[i] & ~coin[i];
+    }
+    // An LR car moves when the cell on its right is EMPTY and not lost to
+    // the TB car above that cell (bit j <- bit j+1 of E and of lr_loses).
+    const uint32_t e_next = from_next_lane<WRAP>(E[0]);
+    const uint32_t loss_next = from_next_lane<WRAP>(lr_loses[0]);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+        const uint32_t e_right =
+            __builtin_amdgcn_alignbit(i + 1 < WL ? E[i + 1] : e_next, E[i], 1);
+        const uint32_t loss_right = __builtin_amdgcn_alignbit(
+            i + 1 < WL ? lr_loses[i + 1] : loss_next, lr_loses[i], 1);
+        mv[i] = L_in[i] & e_right & ~loss_right;
+    }
+    const uint32_t mv_prev = from_prev_lane<WRAP>(mv[WL - 1]);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+        const uint32_t arrive = __builtin_amdgcn_alignbit(mv[i], i ? mv[i - 1] : mv_prev, 31);
+        uint32_t l_new = (L_in[i] & ~mv[i]) | arrive;
+        asm("" : "+v"(l_new));
+        o.mv_h[i] = mv[i];
+        o.l_h[i] = l_new;
+        // TB cars of row r-1 move into EMPTY cells of row r unless the LR
+        // car won the cell.
+        const uint32_t mvt = lv.T[i] & E[i] & ~(claimed[i] & coin[i]);
+        uint32_t t_new = (lv.T[i] & ~mvt) | lv.mvp[i];
+        asm("" : "+v"(t_new));
+        o.L[i] = lv.L[i];
+        o.T[i] = t_new;
+        o.mv_v[i] = mvt;
+        lv.L[i] = l_new;
+        lv.T[i] = T_in[i];
+        lv.mvp[i] = mvt;
+    }
+    return o;
+}
+
+// Model II coin word: the low 32 bits of SplitMix64 output number k of the
+// stream started at `seed` (Steele, Lea and Flood; Vigna's constants);
+// k = step * rows * words + row * words + word, bit b = the coin of cell
+// 32 word + b.
+__device__ __forceinline__ uint32_t model2_coin_word(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (uint32_t)(z ^ (z >> 31));
+}
+
 // ---- byte cells <-> bitplane words -----------------------------------------
 //
 // Byte j of a 32-byte chunk (cells 32w .. 32w+31) holds 0, 1 or 2; bit 0 of

@@ -74,6 +74,11 @@ class Lattice:
         """BML_TOPO_TORUS (default) or BML_TOPO_KLEIN for the steps that follow."""
         B.bml_set_topology(self.handle, topology)
 
+    def set_model(self, model: int, coin_seed: int = 0) -> None:
+        """1: the model of Sec. 2 (default); 2: Model II with conflict coins
+        from stream `coin_seed`."""
+        B.bml_set_model(self.handle, model, coin_seed)
+
     @property
     def topology(self) -> int:
         return B.bml_get_topology(self.handle)

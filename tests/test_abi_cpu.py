@@ -146,3 +146,9 @@ def test_topology_calls_reject_null_handle(B):
     lib = B.lib()
     assert lib.bml_set_topology(None, 1) == B.BML_ESTATE
     assert lib.bml_get_topology(None) == B.BML_ESTATE
+
+
+def test_set_model_rejects_null_handle(B):
+    lib = B.lib()
+    assert lib.bml_set_model(None, 2, 7) == B.BML_ESTATE
+    assert lib.bml_set_model(None, 1, 0) == B.BML_ESTATE
