@@ -50,12 +50,15 @@ def bytes_per_cell_step(layout: int, k: int) -> float:
 ALU_PEAK_LANE_OPS = 256 * 4 * 64 / 4 * 2.4e9   # CUs x SIMDs x lanes / clocks per op x clock
 
 
-def alu_roofline(layout: int, k: int, gcups: float) -> dict:
+def alu_roofline(layout: int, k: int, gcups: float, model: int = 1) -> dict:
     """Algorithmic lane-ops of the bitwise rule: 9 logic ops per 32-cell
     word and step plus 4 popcount-adds for the per-step counts; the byte
     layout adds its in-register conversion, about 80 lane-ops per word per
-    pass of k steps."""
-    per_cell_step = (13 + (80.0 / k if layout == 0 else 0.0)) / 32
+    pass of k steps.  Model II: 27 logic ops (the contested-cell masks and
+    both moves in one phase), 4 popcount-adds and about 29 lane-ops for the
+    word's coin hash (a 64-bit SplitMix64 output in 32-bit lane ops)."""
+    per_word = 13 if model == 1 else 27 + 4 + 29
+    per_cell_step = (per_word + (80.0 / k if layout == 0 else 0.0)) / 32
     achieved = gcups * 1e9 * per_cell_step
     return {"bound": "alu", "achieved": round(achieved / 1e12, 2),
             "peak": round(ALU_PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",
@@ -68,17 +71,21 @@ def size_key(lt):
     return lt.n if lt.cols is None else f"{lt.n}x{lt.cols}"
 
 
-def load_tuning(layout: int, n, group: str | None = None):
+def load_tuning(layout: int, n, group: str | None = None, model: int = 1):
     """Autotuned (tile_rows, t_phases, waves_per_block): the entry for the
     group of lattices run together (e.g. the four concurrent 4096 lattices),
-    else the one for a lone lattice of side n, else None."""
+    else the one for a lone lattice of side n, else None.  Model II uses its
+    own entries (a /model2 suffix) when they exist."""
     path = os.path.join(ROOT, "paper_1804_07981_amd", "tune_cache.json")
     if os.path.exists(path):
         try:
             with open(path) as f:
                 cache = json.load(f)
             lay = "u8" if layout == 0 else "bp"
-            for key in ([f"gfx950/{lay}/{group}"] if group else []) + [f"gfx950/{lay}/{n}"]:
+            keys = ([f"gfx950/{lay}/{group}"] if group else []) + [f"gfx950/{lay}/{n}"]
+            if model == 2:
+                keys = [k + "/model2" for k in keys] + keys
+            for key in keys:
                 if key in cache:
                     t = cache[key]
                     return int(t["tile_rows"]), int(t["t_phases"]), int(t["waves_per_block"])
@@ -199,10 +206,15 @@ def copy_ceiling(B, dev, nbytes: int = 1 << 30, reps: int = 5) -> dict:
     return out
 
 
-def cpu_baseline(lt, target_s: float = 15.0):
+def cpu_baseline(lt, target_s: float = 15.0, model: int = 1, coin_seed: int = 0):
     """The oracle on (a bounded number of rows of) the workload's first
     lattice, timed on the host cores."""
     import oracle
+
+    def run(g, steps):
+        if model == 2:
+            return oracle.run_model2(g, steps, coin_seed, n_threads=threads)
+        return oracle.run(g, steps, n_threads=threads)
     threads = min(os.cpu_count() or 1, 16)
     rows, cols = min(lt.n, 4096), min(lt.cols or lt.n, 4096 if lt.cols is None else lt.cols)
     if lt.cols is None and lt.rho_lr is None:
@@ -212,11 +224,11 @@ def cpu_baseline(lt, target_s: float = 15.0):
         rows = g.shape[0]
     rho, seed, n = lt.rho, lt.seed, rows
     t0 = time.perf_counter()
-    g, _ = oracle.run(g, 2, n_threads=threads)
+    g, _ = run(g, 2)
     cal = (time.perf_counter() - t0) / 2
     steps = max(2, min(int(target_s / max(cal, 1e-6)), 2000))
     t0 = time.perf_counter()
-    oracle.run(g, steps, n_threads=threads)
+    run(g, steps)
     dt = time.perf_counter() - t0
     return {"value": rows * cols * steps / dt / 1e9, "unit": "GCUPS", "cores": threads,
             "kind": "oracle",
@@ -224,7 +236,7 @@ def cpu_baseline(lt, target_s: float = 15.0):
                       + (f"rho={rho}" if lt.rho_lr is None
                          else f"rho_lr={lt.rho_lr} rho_tb={lt.rho_tb}") + f" seed={seed}, "
                       f"{steps} steps, {threads} threads, {dt:.1f} s (plain C oracle, -O3, "
-                      "OpenMP row split)"}
+                      "OpenMP row split" + (", Model II" if model == 2 else "") + ")"}
 
 
 def bench_sweep(args, B, workloads, dev) -> int:
@@ -323,6 +335,11 @@ def main() -> int:
     ap.add_argument("--topology", choices=["torus", "klein"], default="torus",
                     help="medium/large/rect: periodic in both directions, or the Klein "
                          "bottle (top and bottom edges glued with a reversal)")
+    ap.add_argument("--model", type=int, choices=[1, 2], default=1,
+                    help="medium/large/rect: the model of Sec. 2 (1) or Model II (2: one "
+                         "phase per step, a coin on contested cells)")
+    ap.add_argument("--coin-seed", type=int, default=0x5EED,
+                    help="Model II: the coin stream's seed")
     ap.add_argument("--tuning", type=int, nargs=3, metavar=("TILE_ROWS", "T_PHASES", "WPB"),
                     help="medium/large: run this tuning instead of the autotuned one")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("PROBE_LOG", "FETCH_DIR", "WRITE_DIR"),
@@ -358,9 +375,17 @@ def main() -> int:
         forced = tuple(args.tuning)
         load = lambda lay, n, grp=None: forced   # noqa: E731
     else:
-        load = load_tuning
+        load = lambda lay, n, grp=None: load_tuning(lay, n, grp, args.model)   # noqa: E731
     layout = 0 if args.layout == "u8" else 1
     topology = B.BML_TOPO_KLEIN if args.topology == "klein" else B.BML_TOPO_TORUS
+    if args.model == 2 and args.topology != "torus":
+        print("Model II runs on the torus only", file=sys.stderr)
+        return 2
+
+    def configure(lat):
+        lat.set_topology(topology)
+        if args.model == 2:
+            lat.set_model(2, args.coin_seed)
 
     if args.probe:
         a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
@@ -377,7 +402,7 @@ def main() -> int:
         for lat in lats:
             if tun:
                 lat.set_tuning(*tun)
-            lat.set_topology(topology)
+            configure(lat)
         B.step_group(lats, args.steps)
         torch.cuda.synchronize()
         tr, tp, wpb = lats[0].tuning()
@@ -407,7 +432,7 @@ def main() -> int:
             tun = load(lay, size_key(lt), group if mode == "joint" else None)
             if tun:
                 lat.set_tuning(*tun)
-            lat.set_topology(topology)
+            configure(lat)
             lats.append(lat)
         return lats
 
@@ -474,6 +499,7 @@ def main() -> int:
     lt0 = wl.lattices[0]
     kname = (f"pass_{args.layout}_{lt0.n}" if lt0.cols is None
              else f"pass_{args.layout}_{lt0.n}x{lt0.cols}")
+    kname += ("_klein" if args.topology == "klein" else "") + ("_model2" if args.model == 2 else "")
     traffic = traffic_from_profile(kname, (res["tile_rows"], 2 * k, res["wpb"]), alg_bytes)
     copy_gbs = copy_ceiling(B, dev)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -492,7 +518,7 @@ def main() -> int:
                                                / max(copy_gbs.values()), 4)
                                          if traffic else None),
                 # the same launches against the plain-ALU ceiling
-                "alu": alu_roofline(layout, k, value)}
+                "alu": alu_roofline(layout, k, value, args.model)}
 
     out = {
         "metric": "GCUPS (cell updates/s) + % HBM roofline",
@@ -507,8 +533,11 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": args.layout,
         "data": "synthetic (SplitMix64 iid lattices, seeded)",
-        "config": {"workload": wl.name + ("-klein" if args.topology == "klein" else ""),
+        "config": {"workload": wl.name + ("-klein" if args.topology == "klein" else "")
+                   + ("-modelII" if args.model == 2 else ""),
                    "layout": args.layout, "topology": args.topology,
+                   "update_rule": ("Model II (one phase, coin seed %d)" % args.coin_seed
+                                   if args.model == 2 else "LR phase then TB phase"),
                    "lattices": [[lt.n, lt.cols or lt.n, lt.rho_lr if lt.rho_lr is not None
                                  else lt.rho / 2, lt.rho_tb if lt.rho_tb is not None
                                  else lt.rho / 2, lt.seed] for lt in wl.lattices],
@@ -545,7 +574,7 @@ def main() -> int:
                         tun = load(lay, size_key(lt))
                         if tun:
                             lat.set_tuning(*tun)
-                        lat.set_topology(topology)
+                        configure(lat)
                         lat.step(wl.steps)
                         torch.cuda.synchronize()
                         e0 = torch.cuda.Event(enable_timing=True)
@@ -562,7 +591,7 @@ def main() -> int:
 
     if not args.no_cpu_baseline:
         lt = wl.lattices[0]
-        out["cpu_baseline"] = cpu_baseline(lt)
+        out["cpu_baseline"] = cpu_baseline(lt, model=args.model, coin_seed=args.coin_seed)
 
     print(json.dumps(out), flush=True)
     return 0

@@ -27,14 +27,17 @@ from .batch import Batch
 from .lattice import Lattice, step_group
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+MODEL2_COIN_SEED = 0x5EED       # coin stream of the Model II candidates
 
 
 def arch() -> str:
     return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
 
 
-def key(layout: int, n) -> str:
-    return f"{arch()}/{'u8' if layout == L.BML_LAYOUT_U8 else 'bp'}/{n}"
+def key(layout: int, n, model: int = 1) -> str:
+    """Cache key: arch/layout/size, with a /model2 suffix for Model II."""
+    return (f"{arch()}/{'u8' if layout == L.BML_LAYOUT_U8 else 'bp'}/{n}"
+            + ("/model2" if model == 2 else ""))
 
 
 def load(path: str = CACHE) -> dict:
@@ -65,9 +68,11 @@ def _stats_array(rec):
 
 def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
                  t_phases=(2, 4, 8, 12, 16), waves=(2, 4), steps: int | None = None,
-                 rho: float = 0.3, seed: int = 7, log=print, shape: dict | None = None) -> dict:
+                 rho: float = 0.3, seed: int = 7, log=print, shape: dict | None = None,
+                 model: int = 1) -> dict:
     """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice, or
-    n rows x shape["cols"] with the draw in `shape` (Lattice keywords)."""
+    n rows x shape["cols"] with the draw in `shape` (Lattice keywords), under
+    update rule `model` (1, or 2 for Model II)."""
     shape = shape or {}
     cells = n * shape.get("cols", n)
     if steps is None:
@@ -78,6 +83,8 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
     results = []
     for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
         with Lattice(n, rho, seed, layout=layout, stats_cap=steps, **shape) as lat:
+            if model == 2:
+                lat.set_model(2, MODEL2_COIN_SEED)
             lat.set_tuning(tr, tp, w)
             lat.step(steps)                      # warm-up (and the checked run)
             torch.cuda.synchronize()
@@ -107,7 +114,8 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
 
 
 def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 32, 48),
-               t_phases=(8, 10, 12, 14, 16), waves=(2, 4), steps: int = 480, log=print) -> dict:
+               t_phases=(8, 10, 12, 14, 16), waves=(2, 4), steps: int = 480, log=print,
+               model: int = 1) -> dict:
     """Fastest common tuning for lattices (n, rho, seed) of one size that are
     advanced together by joint launches (bml_step_group): a launch spreads
     the strips of all of them over the device, so the best strip height
@@ -122,6 +130,8 @@ def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 3
                 for n, rho, seed in specs]
         try:
             for lat in lats:
+                if model == 2:
+                    lat.set_model(2, MODEL2_COIN_SEED)
                 lat.set_tuning(tr, tp, w)
             step_group(lats, steps)                  # warm-up (and the checked run)
             torch.cuda.synchronize()
@@ -204,17 +214,20 @@ def main(argv=None) -> int:
                     help="also tune the four 4096x4096 lattices advanced by joint launches")
     ap.add_argument("--cache", default=CACHE)
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
+    ap.add_argument("--model", type=int, choices=[1, 2], default=1,
+                    help="update rule of the tuned runs: 1, or 2 for Model II")
     args = ap.parse_args(argv)
+    m = args.model
     torch.cuda.set_device(0)
     cache = load(args.cache)
     kw = dict(strip_rows=(0, 64, 256), t_phases=(4, 8, 16), waves=(4,)) if args.quick else {}
     for n in args.sizes:
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
-            r = tune_lattice(n, layout, **kw)
-            cache[key(layout, n)] = dict(r["best"], steps=r["steps"],
-                                         rejected=len(r["rejected"]))
-            print(json.dumps({"key": key(layout, n), **r["best"]}), flush=True)
+            r = tune_lattice(n, layout, model=m, **kw)
+            cache[key(layout, n, m)] = dict(r["best"], steps=r["steps"],
+                                            rejected=len(r["rejected"]))
+            print(json.dumps({"key": key(layout, n, m), **r["best"]}), flush=True)
             if r["rejected"]:
                 print(f"bit-exactness gate rejected {len(r['rejected'])} candidates",
                       file=sys.stderr)
@@ -223,8 +236,9 @@ def main(argv=None) -> int:
         lt = workloads.RECT.lattices[0]
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
-            r = tune_lattice(lt.n, layout, rho=lt.rho, seed=lt.seed, shape=lt.kwargs(), **kw)
-            k = key(layout, f"{lt.n}x{lt.cols}")
+            r = tune_lattice(lt.n, layout, rho=lt.rho, seed=lt.seed, shape=lt.kwargs(),
+                             model=m, **kw)
+            k = key(layout, f"{lt.n}x{lt.cols}", m)
             cache[k] = dict(r["best"], steps=r["steps"], rejected=len(r["rejected"]))
             print(json.dumps({"key": k, **r["best"]}), flush=True)
     if args.medium:
@@ -232,8 +246,8 @@ def main(argv=None) -> int:
         specs = [(l.n, l.rho, l.seed) for l in workloads.MEDIUM.lattices]
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
-            r = tune_group(specs, layout, workloads.MEDIUM_GROUP)
-            k = key(layout, workloads.MEDIUM_GROUP)
+            r = tune_group(specs, layout, workloads.MEDIUM_GROUP, model=m)
+            k = key(layout, workloads.MEDIUM_GROUP, m)
             cache[k] = dict(r["best"], steps=r["steps"], rejected=len(r["rejected"]))
             print(json.dumps({"key": k, **r["best"]}), flush=True)
     if args.batch:

@@ -221,6 +221,11 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
             lane_ok = lane >= 1 && lane <= vwords;
         }
         const uint32_t voff = IO == IO_U8 ? word * 32u : word * 4u;
+        // Model II: the lane's share of each coin counter (word * gamma).
+        uint64_t coin_lane[WL];
+#pragma unroll
+        for (int i = 0; i < WL; ++i)
+            coin_lane[i] = MODEL == 2 ? (uint64_t)(word + i) * SPLITMIX64_GAMMA : 0;
         // Klein bottle: offset of the lane's words in a mirrored row (the
         // WL words ending at column words-1-word, loaded in natural order).
         const uint32_t word_m = (uint32_t)(a.words - WL) - word;
@@ -371,10 +376,12 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                         const uint64_t base =
                             (a.lat[li].step0 + (uint64_t)k) * (uint64_t)a.rows * (uint64_t)a.words +
                             (uint64_t)g * (uint64_t)a.words;
+                        const uint64_t row_z =
+                            a.lat[li].coin_seed + (base + 1ull) * SPLITMIX64_GAMMA;
                         uint32_t coin[WL];
 #pragma unroll
                         for (int i = 0; i < WL; ++i)
-                            coin[i] = model2_coin_word(a.lat[li].coin_seed, base + word + i);
+                            coin[i] = splitmix64_mix_lo(row_z + coin_lane[i]);
                         o = level_push_model2<WL, WRAP>(lv[k], k ? bl[k - 1] : L0,
                                                          k ? bt[k - 1] : T0, coin);
                     } else {

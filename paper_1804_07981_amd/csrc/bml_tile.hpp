@@ -246,13 +246,21 @@ __device__ __forceinline__ LevelOut<WL> level_push_model2(Level<WL> &lv,
 // Model II coin word: the low 32 bits of SplitMix64 output number k of the
 // stream started at `seed` (Steele, Lea and Flood; Vigna's constants);
 // k = step * rows * words + row * words + word, bit b = the coin of cell
-// 32 word + b.
-__device__ __forceinline__ uint32_t model2_coin_word(uint64_t seed, uint64_t k)
+// 32 word + b.  Output k mixes seed + (k + 1) * gamma; the kernels split the
+// product as seed + (row_base + 1) * gamma (uniform per row) plus
+// word * gamma (fixed per lane), so a word costs one 64-bit add and the mix.
+constexpr uint64_t SPLITMIX64_GAMMA = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint32_t splitmix64_mix_lo(uint64_t z)
 {
-    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return (uint32_t)(z ^ (z >> 31));
+}
+
+__device__ __forceinline__ uint32_t model2_coin_word(uint64_t seed, uint64_t k)
+{
+    return splitmix64_mix_lo(seed + (k + 1ull) * SPLITMIX64_GAMMA);
 }
 
 // ---- byte cells <-> bitplane words -----------------------------------------
