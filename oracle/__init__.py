@@ -74,6 +74,8 @@ def lib() -> ctypes.CDLL:
         L.bmlo_run_topo.restype = None
         L.bmlo_run_model2.argtypes = [i64, i64, vp, vp, i64, i64, u64, vp, i32]
         L.bmlo_run_model2.restype = None
+        L.bmlo_run_model3.argtypes = [i64, i64, vp, vp, i64, vp, i32]
+        L.bmlo_run_model3.restype = None
         L.bmlo_phase_v_topo.argtypes = [i64, i64, vp, vp, i32]
         L.bmlo_phase_v_topo.restype = i64
         L.bmlo_run_many.argtypes = [i64, vp, vp, vp, vp, vp, i64, i32]
@@ -90,10 +92,12 @@ def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
 
-def _u8(cells: np.ndarray) -> np.ndarray:
+def _u8(cells: np.ndarray, allow_both: bool = False) -> np.ndarray:
     a = np.ascontiguousarray(cells, dtype=np.uint8)
     if a.ndim != 2:
         raise ValueError("lattice must be 2-D")
+    if a.size and int(a.max()) > (3 if allow_both else 2):
+        raise ValueError("cell values must be 0..2 (0..3 under Model III)")
     return a
 
 
@@ -180,6 +184,19 @@ def run_model2(cells: np.ndarray, steps: int, coin_seed: int, step0: int = 0,
     stats = np.zeros((max(steps, 0), 4), dtype=np.uint32)
     lib().bmlo_run_model2(a.shape[0], a.shape[1], _ptr(a), _ptr(tmp), int(steps), int(step0),
                           coin_seed & (2**64 - 1), _ptr(stats), int(n_threads))
+    return a, stats
+
+
+def run_model3(cells: np.ndarray, steps: int, n_threads: int = 1
+               ) -> tuple[np.ndarray, np.ndarray]:
+    """Model III (Sec. 2), read as Model II's one-phase update in which an
+    EMPTY cell wanted by an LR and a TB car takes both (value 3 = LR | TB);
+    any car in a cell blocks cars of either type.  Cells hold 0..3."""
+    a = _u8(cells, allow_both=True).copy()
+    tmp = np.empty_like(a)
+    stats = np.zeros((max(steps, 0), 4), dtype=np.uint32)
+    lib().bmlo_run_model3(a.shape[0], a.shape[1], _ptr(a), _ptr(tmp), int(steps), _ptr(stats),
+                          int(n_threads))
     return a, stats
 
 

@@ -346,6 +346,86 @@ void bmlo_run_model2(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp, i
     (void)nt;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Model III (Sec. 2): a cell may hold an LR and a TB car at once (value 3 = */
+/* LR | TB).  The paper gives one sentence; the reading here keeps Model   */
+/* II's one-phase update and changes only the conflict: every car may       */
+/* advance in one phase per step, moving when its target cell (right for    */
+/* LR, below for TB) holds no car before the step, and an EMPTY cell wanted */
+/* by both an LR car (its left neighbour) and a TB car (its top neighbour)  */
+/* takes both.  A doubly occupied cell blocks cars of either type, like any */
+/* occupied cell, and each of its two cars leaves by its own rule.  Torus   */
+/* only.  stats per step: n_lr, moved_lr, n_tb, moved_tb after that phase,  */
+/* a doubly occupied cell counting once in n_lr and once in n_tb.           */
+/* ------------------------------------------------------------------------ */
+#define BOTH (LR | TB)
+
+static int64_t count_bit(const uint8_t *cells, int64_t n, uint8_t bit)
+{
+    int64_t c = 0;
+    for (int64_t k = 0; k < n; k++)
+        c += (cells[k] & bit) != 0;
+    return c;
+}
+
+static void model3_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
+                        const uint8_t *cur, uint8_t *next, int64_t *moved_lr,
+                        int64_t *moved_tb)
+{
+    for (int64_t i = r0; i < r1; i++) {
+        int64_t up = (i - 1 + rows) % rows, down = (i + 1) % rows;
+        for (int64_t j = 0; j < cols; j++) {
+            int64_t left = (j - 1 + cols) % cols, right = (j + 1) % cols;
+            uint8_t c = cur[i * cols + j], out = EMPTY;
+            if (c & LR) {
+                if (cur[i * cols + right] == EMPTY)
+                    (*moved_lr)++;            /* the LR car leaves */
+                else
+                    out |= LR;
+            }
+            if (c & TB) {
+                if (cur[down * cols + j] == EMPTY)
+                    (*moved_tb)++;            /* the TB car leaves */
+                else
+                    out |= TB;
+            }
+            if (c == EMPTY) {                 /* arrivals, possibly both */
+                if (cur[i * cols + left] & LR)
+                    out |= LR;
+                if (cur[up * cols + j] & TB)
+                    out |= TB;
+            }
+            next[i * cols + j] = out;
+        }
+    }
+}
+
+void bmlo_run_model3(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp, int64_t steps,
+                     uint32_t *stats, int32_t n_threads)
+{
+    int nt = n_threads > 0 ? n_threads : 1;
+    for (int64_t s = 0; s < steps; s++) {
+        int64_t moved_lr = 0, moved_tb = 0;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : moved_lr, moved_tb)
+#endif
+        for (int64_t i = 0; i < rows; i++) {
+            int64_t ml = 0, mt = 0;
+            model3_rows(i, i + 1, rows, cols, cells, tmp, &ml, &mt);
+            moved_lr += ml;
+            moved_tb += mt;
+        }
+        memcpy(cells, tmp, (size_t)(rows * cols));
+        if (stats) {
+            stats[4 * s + 0] = (uint32_t)count_bit(cells, rows * cols, LR);
+            stats[4 * s + 1] = (uint32_t)moved_lr;
+            stats[4 * s + 2] = (uint32_t)count_bit(cells, rows * cols, TB);
+            stats[4 * s + 3] = (uint32_t)moved_tb;
+        }
+    }
+    (void)nt;
+}
+
 /* Many independent square lattices, one lattice per thread at a time
  * (dynamic schedule): lattice b has sizes[b] x sizes[b] cells starting at
  * cells + offsets[b]; its per-step counts (4 per step, as in bmlo_run) go to

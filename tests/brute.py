@@ -118,3 +118,40 @@ def run_model2(grid, steps, seed, step0=0):
         grid, c = model2_step(grid, seed, step0 + s)
         stats.append(c)
     return grid, stats
+
+
+# --- Model III (Sec. 2): a cell may hold an LR and a TB car at once ----------
+
+def model3_step(grid):
+    """Cells hold a set of cars as bits (1 LR, 2 TB).  Every car lists its
+    target on the pre-step lattice and moves iff the target holds no car;
+    then all moves happen at once, so a target wanted by one car of each
+    type ends with both.  Returns (grid, (n_lr, moved_lr, n_tb, moved_tb))."""
+    rows, cols = len(grid), len(grid[0])
+    moves = []
+    for i in range(rows):
+        for j in range(cols):
+            for kind in (LR, TB):
+                if grid[i][j] & kind:
+                    ti, tj = target(i, j, kind, rows, cols)
+                    if grid[ti][tj] == EMPTY:
+                        moves.append(((i, j), (ti, tj), kind))
+    new = [list(r) for r in grid]
+    for (si, sj), _, kind in moves:
+        new[si][sj] &= ~kind
+    for _, (ti, tj), kind in moves:
+        assert not new[ti][tj] & kind, "two cars of one type share a target"
+        new[ti][tj] |= kind
+    n_lr = sum(1 for r in new for c in r if c & LR)
+    n_tb = sum(1 for r in new for c in r if c & TB)
+    mlr = sum(1 for m in moves if m[2] == LR)
+    return new, (n_lr, mlr, n_tb, len(moves) - mlr)
+
+
+def run_model3(grid, steps):
+    grid = [list(r) for r in grid]
+    stats = []
+    for _ in range(steps):
+        grid, c = model3_step(grid)
+        stats.append(c)
+    return grid, stats

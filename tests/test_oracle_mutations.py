@@ -45,6 +45,15 @@ MUTATIONS = [
     ("Model II: the LR car reads the coin of its own cell",
      "if (!contested || model2_coin(coin_seed, step, rows, cols, i, right)) {",
      "if (!contested || model2_coin(coin_seed, step, rows, cols, i, j)) {"),
+    ("Model III: an LR car enters a cell that holds only a TB car",
+     "if (cur[i * cols + right] == EMPTY)\n                    (*moved_lr)++;",
+     "if (!(cur[i * cols + right] & LR))\n                    (*moved_lr)++;"),
+    ("Model III: a contested cell keeps only the LR car",
+     "if (cur[up * cols + j] & TB)\n                    out |= TB;",
+     "if ((cur[up * cols + j] & TB) && !(out & LR))\n                    out |= TB;"),
+    ("Model III: cars arrive in a cell the other type holds",
+     "if (c == EMPTY) {                 /* arrivals, possibly both */",
+     "if (c != BOTH) {                  /* arrivals, possibly both */"),
     ("asymmetric TB threshold without the LR share", "*thr_tb = (uint64_t)ldexp(rho_lr + rho_tb, 53);",
      "*thr_tb = (uint64_t)ldexp(rho_tb, 53);"),
 ]

@@ -402,6 +402,105 @@ def test_model2_step_index_selects_the_coins():
     assert np.array_equal(a, b2) and np.array_equal(sa, np.concatenate([s1, s2]))
 
 
+# --- Model III (Sec. 2): a cell may hold an LR and a TB car at once --------
+
+BOTH = LR | TB
+
+
+def _with_both(rng, g, frac):
+    g = g.copy()
+    g[rng.random(g.shape) < frac] = BOTH
+    return g
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 4), (2, 2), (3, 5), (4, 4), (5, 3), (6, 7), (8, 8),
+                                       (3, 40)])
+def test_model3_matches_brute_force(rows, cols):
+    rng = np.random.default_rng(rows * 683 + cols)
+    for trial in range(20):
+        p = rng.random()
+        q = rng.random() * (1 - p)
+        g = _with_both(rng, workloads.random_lattice(rng, rows, cols, p, q), rng.random() * 0.3)
+        og, ost = oracle.run_model3(g, 6)
+        bg, bst = brute.run_model3(g.tolist(), 6)
+        assert np.array_equal(og, np.array(bg, dtype=np.uint8))
+        assert [tuple(int(x) for x in s) for s in ost] == bst
+
+
+def test_model3_one_type_is_rule_184():
+    """LR cars alone: every row is elementary CA rule 184 (Wolfram's
+    numbering, bit n of 184 = new centre for neighbourhood n = 4l + 2c + r);
+    TB cars alone: every column is."""
+    rng = np.random.default_rng(31)
+    rule = [(184 >> n) & 1 for n in range(8)]
+    for kind in (LR, TB):
+        g = workloads.random_lattice(rng, 14, 18, 0.5 if kind == LR else 0.0,
+                                     0.5 if kind == TB else 0.0)
+        got, _ = oracle.run_model3(g, 1)
+        lines = (g == kind).astype(int) if kind == LR else (g == kind).astype(int).T
+        want = np.zeros_like(lines)
+        for r, line in enumerate(lines):
+            n = len(line)
+            for c in range(n):
+                want[r, c] = rule[4 * line[c - 1] + 2 * line[c] + line[(c + 1) % n]]
+        out = (got == kind).astype(int) if kind == LR else (got == kind).astype(int).T
+        assert np.array_equal(out, want)
+
+
+def test_model3_without_contested_cells_is_model2():
+    """A step with no EMPTY cell wanted by both types is the same under
+    Models II and III (whatever the coins)."""
+    rng = np.random.default_rng(17)
+    for trial in range(30):
+        g = workloads.random_lattice(rng, 10, 12, 0.3, 0.3)
+        while True:          # drop the TB car above each contested cell
+            contested = (g == EMPTY) & (np.roll(g, 1, axis=1) == LR) & (np.roll(g, 1, axis=0) == TB)
+            if not contested.any():
+                break
+            g[np.roll(contested, -1, axis=0)] = EMPTY
+        a, sa = oracle.run_model3(g, 1)
+        b, sb = oracle.run_model2(g, 1, int(rng.integers(0, 2**63)))
+        assert np.array_equal(a, b) and np.array_equal(sa, sb)
+
+
+def test_model3_contested_cells_take_both_cars():
+    rows, cols = 32, 32
+    g = np.zeros((rows, cols), np.uint8)
+    g[1::2, 0::2] = LR
+    g[0::2, 1::2] = TB
+    out, st = oracle.run_model3(g, 1)
+    assert (out[1::2, 1::2] == BOTH).all()
+    assert (out[1::2, 0::2] == EMPTY).all() and (out[0::2, 1::2] == EMPTY).all()
+    assert tuple(int(x) for x in st[0]) == (rows * cols // 4, rows * cols // 4,
+                                            rows * cols // 4, rows * cols // 4)
+
+
+def test_model3_doubly_occupied_cell_blocks_both_types_and_empties_one_car_at_a_time():
+    g = np.zeros((5, 6), np.uint8)
+    g[2, 2] = BOTH
+    g[2, 1] = LR            # blocked by the double cell on its right
+    g[1, 2] = TB            # blocked by the double cell below
+    g[3, 2] = LR            # blocks the double cell's TB car
+    out, st = oracle.run_model3(g, 1)
+    want = np.zeros_like(g)
+    want[2, 1] = LR
+    want[1, 2] = TB
+    want[2, 2] = TB         # its LR car left, its TB car is blocked
+    want[2, 3] = LR
+    want[3, 3] = LR
+    assert np.array_equal(out, want)
+    assert tuple(int(x) for x in st[0]) == (3, 2, 2, 0)
+
+
+def test_model3_conserves_cars_per_row_and_column():
+    rng = np.random.default_rng(23)
+    g = _with_both(rng, workloads.random_lattice(rng, 30, 26, 0.3, 0.3), 0.05)
+    out, st = oracle.run_model3(g, 60)
+    assert np.array_equal((out & LR > 0).sum(axis=1), (g & LR > 0).sum(axis=1))
+    assert np.array_equal((out & TB > 0).sum(axis=0), (g & TB > 0).sum(axis=0))
+    assert (st[:, 0] == (g & LR > 0).sum()).all() and (st[:, 2] == (g & TB > 0).sum()).all()
+
+
 # --- asymmetric placement (unequal LR and TB numbers, Sec. 2 extensions) ---
 
 def _floor_times_2_53(x: float) -> int:
