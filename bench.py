@@ -56,8 +56,9 @@ def alu_roofline(layout: int, k: int, gcups: float, model: int = 1) -> dict:
     layout adds its in-register conversion, about 80 lane-ops per word per
     pass of k steps.  Model II: 27 logic ops (the contested-cell masks and
     both moves in one phase), 4 popcount-adds and about 29 lane-ops for the
-    word's coin hash (a 64-bit SplitMix64 output in 32-bit lane ops)."""
-    per_word = 13 if model == 1 else 27 + 4 + 29
+    word's coin hash (a 64-bit SplitMix64 output in 32-bit lane ops).  Model
+    III: the one phase without the coin, 9 logic ops + 4 popcount-adds."""
+    per_word = 27 + 4 + 29 if model == 2 else 13
     per_cell_step = (per_word + (80.0 / k if layout == 0 else 0.0)) / 32
     achieved = gcups * 1e9 * per_cell_step
     return {"bound": "alu", "achieved": round(achieved / 1e12, 2),
@@ -74,8 +75,8 @@ def size_key(lt):
 def load_tuning(layout: int, n, group: str | None = None, model: int = 1):
     """Autotuned (tile_rows, t_phases, waves_per_block): the entry for the
     group of lattices run together (e.g. the four concurrent 4096 lattices),
-    else the one for a lone lattice of side n, else None.  Model II uses its
-    own entries (a /model2 suffix) when they exist."""
+    else the one for a lone lattice of side n, else None.  Models II and III
+    use their own entries (a /model2 or /model3 suffix) when they exist."""
     path = os.path.join(ROOT, "paper_1804_07981_amd", "tune_cache.json")
     if os.path.exists(path):
         try:
@@ -83,8 +84,8 @@ def load_tuning(layout: int, n, group: str | None = None, model: int = 1):
                 cache = json.load(f)
             lay = "u8" if layout == 0 else "bp"
             keys = ([f"gfx950/{lay}/{group}"] if group else []) + [f"gfx950/{lay}/{n}"]
-            if model == 2:
-                keys = [k + "/model2" for k in keys] + keys
+            if model != 1:
+                keys = [k + f"/model{model}" for k in keys] + keys
             for key in keys:
                 if key in cache:
                     t = cache[key]
@@ -214,6 +215,8 @@ def cpu_baseline(lt, target_s: float = 15.0, model: int = 1, coin_seed: int = 0)
     def run(g, steps):
         if model == 2:
             return oracle.run_model2(g, steps, coin_seed, n_threads=threads)
+        if model == 3:
+            return oracle.run_model3(g, steps, n_threads=threads)
         return oracle.run(g, steps, n_threads=threads)
     threads = min(os.cpu_count() or 1, 16)
     rows, cols = min(lt.n, 4096), min(lt.cols or lt.n, 4096 if lt.cols is None else lt.cols)
@@ -236,7 +239,7 @@ def cpu_baseline(lt, target_s: float = 15.0, model: int = 1, coin_seed: int = 0)
                       + (f"rho={rho}" if lt.rho_lr is None
                          else f"rho_lr={lt.rho_lr} rho_tb={lt.rho_tb}") + f" seed={seed}, "
                       f"{steps} steps, {threads} threads, {dt:.1f} s (plain C oracle, -O3, "
-                      "OpenMP row split" + (", Model II" if model == 2 else "") + ")"}
+                      "OpenMP row split" + {1: "", 2: ", Model II", 3: ", Model III"}[model] + ")"}
 
 
 def bench_sweep(args, B, workloads, dev) -> int:
@@ -335,9 +338,10 @@ def main() -> int:
     ap.add_argument("--topology", choices=["torus", "klein"], default="torus",
                     help="medium/large/rect: periodic in both directions, or the Klein "
                          "bottle (top and bottom edges glued with a reversal)")
-    ap.add_argument("--model", type=int, choices=[1, 2], default=1,
-                    help="medium/large/rect: the model of Sec. 2 (1) or Model II (2: one "
-                         "phase per step, a coin on contested cells)")
+    ap.add_argument("--model", type=int, choices=[1, 2, 3], default=1,
+                    help="medium/large/rect: the model of Sec. 2 (1), Model II (2: one "
+                         "phase per step, a coin on contested cells) or Model III (3: one "
+                         "phase, a contested cell takes both cars)")
     ap.add_argument("--coin-seed", type=int, default=0x5EED,
                     help="Model II: the coin stream's seed")
     ap.add_argument("--tuning", type=int, nargs=3, metavar=("TILE_ROWS", "T_PHASES", "WPB"),
@@ -378,14 +382,14 @@ def main() -> int:
         load = lambda lay, n, grp=None: load_tuning(lay, n, grp, args.model)   # noqa: E731
     layout = 0 if args.layout == "u8" else 1
     topology = B.BML_TOPO_KLEIN if args.topology == "klein" else B.BML_TOPO_TORUS
-    if args.model == 2 and args.topology != "torus":
-        print("Model II runs on the torus only", file=sys.stderr)
+    if args.model != 1 and args.topology != "torus":
+        print("Models II and III run on the torus only", file=sys.stderr)
         return 2
 
     def configure(lat):
         lat.set_topology(topology)
-        if args.model == 2:
-            lat.set_model(2, args.coin_seed)
+        if args.model != 1:
+            lat.set_model(args.model, args.coin_seed)
 
     if args.probe:
         a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
@@ -499,7 +503,8 @@ def main() -> int:
     lt0 = wl.lattices[0]
     kname = (f"pass_{args.layout}_{lt0.n}" if lt0.cols is None
              else f"pass_{args.layout}_{lt0.n}x{lt0.cols}")
-    kname += ("_klein" if args.topology == "klein" else "") + ("_model2" if args.model == 2 else "")
+    kname += ("_klein" if args.topology == "klein" else "") + (
+        f"_model{args.model}" if args.model != 1 else "")
     traffic = traffic_from_profile(kname, (res["tile_rows"], 2 * k, res["wpb"]), alg_bytes)
     copy_gbs = copy_ceiling(B, dev)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -534,10 +539,12 @@ def main() -> int:
         "dtype": args.layout,
         "data": "synthetic (SplitMix64 iid lattices, seeded)",
         "config": {"workload": wl.name + ("-klein" if args.topology == "klein" else "")
-                   + ("-modelII" if args.model == 2 else ""),
+                   + {1: "", 2: "-modelII", 3: "-modelIII"}[args.model],
                    "layout": args.layout, "topology": args.topology,
-                   "update_rule": ("Model II (one phase, coin seed %d)" % args.coin_seed
-                                   if args.model == 2 else "LR phase then TB phase"),
+                   "update_rule": {1: "LR phase then TB phase",
+                                   2: "Model II (one phase, coin seed %d)" % args.coin_seed,
+                                   3: "Model III (one phase, a contested cell takes both "
+                                      "cars)"}[args.model],
                    "lattices": [[lt.n, lt.cols or lt.n, lt.rho_lr if lt.rho_lr is not None
                                  else lt.rho / 2, lt.rho_tb if lt.rho_tb is not None
                                  else lt.rho / 2, lt.seed] for lt in wl.lattices],

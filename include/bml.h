@@ -84,7 +84,9 @@ int bml_state_bytes(int32_t n, int32_t layout, size_t *bytes);
  *                (Sec. 2); this iid draw is the library's reading.  rho must
  *                be in [0, 1].
  *   cells_host   NULL, or N*N host bytes (row-major, values 0..2) to start
- *                from instead (also how a saved state is resumed).
+ *                from instead (also how a saved state is resumed); value 3
+ *                (an LR and a TB car in one cell) is accepted too, but such
+ *                a lattice steps only under Model III (bml_set_model).
  *   d_state_a/b  two caller-owned device buffers of bml_state_bytes() each,
  *                256-byte aligned, not overlapping; the library ping-pongs
  *                between them (synchronous update via two grids, Sec. 3).
@@ -152,8 +154,9 @@ int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps);
 int bml_stats(bml_lattice *L, int64_t first_step, int64_t count,
               bml_step_stats *out_host);
 
-/* Copy the current lattice to out_host as N*N (rows*cols) row-major bytes (values 0..2),
- * whatever the layout (a bitplane lattice is unpacked on the device first).
+/* Copy the current lattice to out_host as N*N (rows*cols) row-major bytes (values 0..2,
+ * and 3 for a cell holding both cars under Model III), whatever the layout (a
+ * bitplane lattice is unpacked on the device first).
  * Synchronises the stream. */
 int bml_get_cells(bml_lattice *L, uint8_t *out_host);
 
@@ -176,8 +179,19 @@ int bml_get_topology(const bml_lattice *L);
  * 32 bits of the SplitMix64 output number s*rows*W + i*W + j/32 of the stream
  * started at `coin_seed` (W = cols/32), 1 meaning the LR car moves.  The
  * counts of a Model II step are taken after its one phase, and a kernel
- * pass still advances t_phases/2 steps (bml_set_tuning).  Torus only:
- * EINVAL with the Klein topology, or for another model value; ESTATE on an
+ * pass still advances t_phases/2 steps (bml_set_tuning).  model 3: Model III
+ * (Sec. 2: a cell may hold an LR and a TB car).  The paper gives one
+ * sentence; here it is the one-phase step of Model II in which an EMPTY
+ * cell wanted by both an LR and a TB car takes both (cell value 3, LR and
+ * TB bits both set; coin_seed unused).  A car still moves only into a cell
+ * that held no car before the step, so a doubly occupied cell blocks both
+ * types, and each of its cars leaves by its own rule; counts are taken
+ * after the phase, a doubly occupied cell counting once in n_lr and once in
+ * n_tb.  A lattice that has run Model III steps, or was initialised with a
+ * value-3 cell, stays on Model III: selecting model 1 or 2 for it is EINVAL,
+ * and so is stepping it (bml_step, bml_step_group) under model 1 before
+ * Model III is selected.  Models II and III run on the torus only: EINVAL
+ * with the Klein topology, or for another model value; ESTATE on an
  * invalid handle. */
 int bml_set_model(bml_lattice *L, int32_t model, uint64_t coin_seed);
 

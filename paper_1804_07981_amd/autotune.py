@@ -35,9 +35,10 @@ def arch() -> str:
 
 
 def key(layout: int, n, model: int = 1) -> str:
-    """Cache key: arch/layout/size, with a /model2 suffix for Model II."""
+    """Cache key: arch/layout/size, with a /model2 or /model3 suffix for
+    Models II and III."""
     return (f"{arch()}/{'u8' if layout == L.BML_LAYOUT_U8 else 'bp'}/{n}"
-            + ("/model2" if model == 2 else ""))
+            + (f"/model{model}" if model != 1 else ""))
 
 
 def load(path: str = CACHE) -> dict:
@@ -72,7 +73,7 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
                  model: int = 1) -> dict:
     """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice, or
     n rows x shape["cols"] with the draw in `shape` (Lattice keywords), under
-    update rule `model` (1, or 2 for Model II)."""
+    update rule `model` (1, 2 for Model II, 3 for Model III)."""
     shape = shape or {}
     cells = n * shape.get("cols", n)
     if steps is None:
@@ -83,8 +84,8 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
     results = []
     for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
         with Lattice(n, rho, seed, layout=layout, stats_cap=steps, **shape) as lat:
-            if model == 2:
-                lat.set_model(2, MODEL2_COIN_SEED)
+            if model != 1:
+                lat.set_model(model, MODEL2_COIN_SEED)
             lat.set_tuning(tr, tp, w)
             lat.step(steps)                      # warm-up (and the checked run)
             torch.cuda.synchronize()
@@ -130,8 +131,8 @@ def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 3
                 for n, rho, seed in specs]
         try:
             for lat in lats:
-                if model == 2:
-                    lat.set_model(2, MODEL2_COIN_SEED)
+                if model != 1:
+                    lat.set_model(model, MODEL2_COIN_SEED)
                 lat.set_tuning(tr, tp, w)
             step_group(lats, steps)                  # warm-up (and the checked run)
             torch.cuda.synchronize()
@@ -214,8 +215,8 @@ def main(argv=None) -> int:
                     help="also tune the four 4096x4096 lattices advanced by joint launches")
     ap.add_argument("--cache", default=CACHE)
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
-    ap.add_argument("--model", type=int, choices=[1, 2], default=1,
-                    help="update rule of the tuned runs: 1, or 2 for Model II")
+    ap.add_argument("--model", type=int, choices=[1, 2, 3], default=1,
+                    help="update rule of the tuned runs: 1, 2 (Model II) or 3 (Model III)")
     args = ap.parse_args(argv)
     m = args.model
     torch.cuda.set_device(0)

@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "libbml.so")
 # mode / range of K, topology); see bml_pass.hpp.
 PASS_RANGES = {"lo": (0, 1, 4), "hi": (0, 5, 4), "row1": (1, 1, 8), "row2": (2, 1, 8)}
 # variant name -> (topology, model)
-PASS_KINDS = {"torus": ("TOPO_TORUS", 1), "klein": ("TOPO_KLEIN", 1), "model2": ("TOPO_TORUS", 2)}
+PASS_KINDS = {"torus": ("TOPO_TORUS", 1), "klein": ("TOPO_KLEIN", 1), "model2": ("TOPO_TORUS", 2),
+              "model3": ("TOPO_TORUS", 3)}
 PASS_VARIANTS = [
     (f"pass_table_{io}_{rng}_{kind}",
      [f"-DBML_INST_IO={'IO_U8' if io == 'u8' else 'IO_BP'}", f"-DBML_INST_ROW={row}",

@@ -199,7 +199,7 @@ constexpr int PASS_MODES = 3;
 
 // Kernel kinds: the model of Sec. 2 on the torus or the Klein bottle, and
 // Model II on the torus.
-enum { KIND_TORUS = 0, KIND_KLEIN = 1, KIND_MODEL2 = 2, PASS_KINDS = 3 };
+enum { KIND_TORUS = 0, KIND_KLEIN = 1, KIND_MODEL2 = 2, KIND_MODEL3 = 3, PASS_KINDS = 4 };
 
 struct KernelTable {
     PassFn fn[PASS_KINDS][PASS_MODES][2][MAX_K + 1] = {};   // [kind][mode][io][k]
@@ -214,6 +214,7 @@ struct KernelTable {
         BML_FILL_KIND(torus, KIND_TORUS)
         BML_FILL_KIND(klein, KIND_KLEIN)
         BML_FILL_KIND(model2, KIND_MODEL2)
+        BML_FILL_KIND(model3, KIND_MODEL3)
 #undef BML_FILL_KIND
 #undef BML_FILL
     }
@@ -360,7 +361,8 @@ using namespace bml;
 struct bml_lattice {
     int32_t rows = 0, cols = 0, layout = 0;
     int32_t topology = 0;                     // BML_TOPO_TORUS / BML_TOPO_KLEIN
-    int32_t model = 1;                        // 1: Sec. 2's model; 2: Model II
+    int32_t model = 1;                        // 1: Sec. 2's model; 2: Model II; 3: Model III
+    bool both_cells = false;                  // may hold LR+TB cells (Model III only)
     uint64_t coin_seed = 0;                   // Model II conflict coins
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
@@ -545,11 +547,14 @@ int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
     if (!cells_host && !(rho_lr >= 0.0 && rho_tb >= 0.0 && rho_lr + rho_tb <= 1.0))
         return fail(BML_EINVAL, "densities must be >= 0 with a sum in [0, 1]");
     const size_t n_cells = (size_t)rows * cols;
+    bool both_cells = false;   // an LR and a TB car in one cell (Model III)
     if (cells_host) {
-        for (size_t k = 0; k < n_cells; ++k)
-            if (cells_host[k] > 2)
-                return fail(BML_EINVAL, "cell %zu has value %d (must be 0, 1 or 2)", k,
+        for (size_t k = 0; k < n_cells; ++k) {
+            if (cells_host[k] > 3)
+                return fail(BML_EINVAL, "cell %zu has value %d (must be 0, 1, 2 or 3)", k,
                             (int)cells_host[k]);
+            both_cells |= cells_host[k] == 3;
+        }
     }
 
     bml_lattice *L = new (std::nothrow) bml_lattice();
@@ -558,6 +563,7 @@ int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
     L->rows = rows;
     L->cols = cols;
     L->layout = layout;
+    L->both_cells = both_cells;
     L->buf[0] = d_state_a;
     L->buf[1] = d_state_b;
     L->stats = (uint32_t *)d_stats;
@@ -642,8 +648,8 @@ int bml_set_topology(bml_lattice *L, int32_t topology)
         return fail(BML_ESTATE, "invalid handle");
     if (topology != BML_TOPO_TORUS && topology != BML_TOPO_KLEIN)
         return fail(BML_EINVAL, "unknown topology %d", topology);
-    if (topology == BML_TOPO_KLEIN && L->model == 2)
-        return fail(BML_EINVAL, "Model II runs on the torus only");
+    if (topology == BML_TOPO_KLEIN && L->model != 1)
+        return fail(BML_EINVAL, "Models II and III run on the torus only");
     L->topology = topology;
     return BML_OK;
 }
@@ -653,10 +659,13 @@ int bml_set_model(bml_lattice *L, int32_t model, uint64_t coin_seed)
     clear_error();
     if (!live(L))
         return fail(BML_ESTATE, "invalid handle");
-    if (model != 1 && model != 2)
-        return fail(BML_EINVAL, "model=%d must be 1 or 2", model);
-    if (model == 2 && L->topology != BML_TOPO_TORUS)
-        return fail(BML_EINVAL, "Model II runs on the torus only");
+    if (model < 1 || model > 3)
+        return fail(BML_EINVAL, "model=%d must be 1, 2 or 3", model);
+    if (model != 1 && L->topology != BML_TOPO_TORUS)
+        return fail(BML_EINVAL, "Models II and III run on the torus only");
+    if (model != 3 && L->both_cells)
+        return fail(BML_EINVAL, "the lattice may hold cells with both an LR and a TB car, "
+                                "which only Model III defines");
     L->model = model;
     L->coin_seed = coin_seed;
     return BML_OK;
@@ -772,8 +781,10 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
     a.tiles_x = mode ? 1 : (a.words + TILE_WORDS - 1) / TILE_WORDS;
     const int threads = 64 * L->wpb;
     int per_cu = 1;
-    const int kind = L->model == 2 ? KIND_MODEL2 : L->topology == BML_TOPO_KLEIN ? KIND_KLEIN
-                                                                                : KIND_TORUS;
+    const int kind = L->model == 2                    ? KIND_MODEL2
+                     : L->model == 3                  ? KIND_MODEL3
+                     : L->topology == BML_TOPO_KLEIN ? KIND_KLEIN
+                                                      : KIND_TORUS;
     int rc = resident_blocks(kind, mode, io, k, threads, &per_cu);
     if (rc)
         return rc;
@@ -839,6 +850,7 @@ static int step_group(bml_lattice *const *G, int count, int64_t n_steps)
         for (int i = 0; i < count; ++i) {
             s[i] += k;
             G[i]->steps_done = s[i];
+            G[i]->both_cells |= G[i]->model == 3;
         }
     }
     return BML_OK;
@@ -851,6 +863,9 @@ int bml_step(bml_lattice *L, int64_t n_steps)
         return fail(BML_ESTATE, "invalid handle");
     if (n_steps < 0)
         return fail(BML_EINVAL, "n_steps must be >= 0");
+    if (L->both_cells && L->model != 3)
+        return fail(BML_EINVAL, "the lattice holds cells with both an LR and a TB car; "
+                                "select Model III (bml_set_model) to step it");
     if (n_steps == 0)
         return BML_OK;
     bml_lattice *G[1] = {L};
@@ -880,6 +895,9 @@ int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps)
             return fail(BML_EINVAL, "lattice %d has another tuning than lattice 0", i);
         if (Li->stream != L0->stream || Li->dev.device != L0->dev.device)
             return fail(BML_EINVAL, "lattice %d is on another stream or device", i);
+        if (Li->both_cells && Li->model != 3)
+            return fail(BML_EINVAL, "lattice %d holds cells with both an LR and a TB car; "
+                                    "select Model III (bml_set_model) to step it", i);
     }
     if (n_steps == 0)
         return BML_OK;

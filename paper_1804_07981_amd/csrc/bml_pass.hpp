@@ -137,11 +137,14 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // MODEL = 1: the model of Sec. 2 (horizontal then vertical phase).
 // MODEL = 2: Model II (both car types in one phase, a coin on conflicts;
 // level_push_model2), torus only.
+// MODEL = 3: Model III (one phase; a contested cell takes both cars;
+// level_push_model3), torus only.
 template <int IO, int K, int ROW, int TOPO, int MODEL>
 __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 {
     static_assert(K >= 1 && K <= MAX_K, "bad steps per pass");
-    static_assert(MODEL == 1 || (MODEL == 2 && TOPO == TOPO_TORUS), "Model II on the torus");
+    static_assert(MODEL == 1 || ((MODEL == 2 || MODEL == 3) && TOPO == TOPO_TORUS),
+                  "Models II and III on the torus");
     static_assert(ROW >= 0 && ROW <= 2, "row mode holds at most 2 words per lane");
     constexpr int WL = ROW ? ROW : 1;        // words per lane
     constexpr bool WRAP = ROW > 0;
@@ -384,6 +387,9 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                             coin[i] = splitmix64_mix_lo(row_z + coin_lane[i]);
                         o = level_push_model2<WL, WRAP>(lv[k], k ? bl[k - 1] : L0,
                                                          k ? bt[k - 1] : T0, coin);
+                    } else if constexpr (MODEL == 3) {
+                        o = level_push_model3<WL, WRAP>(lv[k], k ? bl[k - 1] : L0,
+                                                         k ? bt[k - 1] : T0);
                     } else {
                         const bool mir = EDGE && !FULL && mirrored(t - 2 * k);
                         o = level_push<WL, WRAP>(lv[k], k ? bl[k - 1] : L0, k ? bt[k - 1] : T0,
@@ -544,5 +550,6 @@ inline void fill_pass_table(PassFn *tab, std::integer_sequence<int, Ks...>)
 BML_PASS_TABLES(BML_PASS_TABLE_DECL, torus)
 BML_PASS_TABLES(BML_PASS_TABLE_DECL, klein)
 BML_PASS_TABLES(BML_PASS_TABLE_DECL, model2)   // Model II, torus
+BML_PASS_TABLES(BML_PASS_TABLE_DECL, model3)   // Model III, torus
 
 } // namespace bml

@@ -243,6 +243,51 @@ __device__ __forceinline__ LevelOut<WL> level_push_model2(Level<WL> &lv,
     return o;
 }
 
+// Model III level (Sec. 2: a cell may hold an LR and a TB car): the phase of
+// level_push_model2 without the coin.  A car moves when its target held no
+// car before the step, and an EMPTY cell wanted by both an LR car (left) and
+// a TB car (above) takes both, so no move is ever lost; a cell with both
+// bits set blocks cars of either type, and each of its cars leaves by its
+// own rule.
+template <int WL, bool WRAP>
+__device__ __forceinline__ LevelOut<WL> level_push_model3(Level<WL> &lv,
+                                                          const uint32_t (&L_in)[WL],
+                                                          const uint32_t (&T_in)[WL])
+{
+    LevelOut<WL> o;
+    uint32_t E[WL], mv[WL];
+#pragma unroll
+    for (int i = 0; i < WL; ++i)
+        E[i] = ~(L_in[i] | T_in[i]);
+    const uint32_t e_next = from_next_lane<WRAP>(E[0]);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+        const uint32_t e_right =
+            __builtin_amdgcn_alignbit(i + 1 < WL ? E[i + 1] : e_next, E[i], 1);
+        mv[i] = L_in[i] & e_right;
+    }
+    const uint32_t mv_prev = from_prev_lane<WRAP>(mv[WL - 1]);
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+        const uint32_t arrive = __builtin_amdgcn_alignbit(mv[i], i ? mv[i - 1] : mv_prev, 31);
+        uint32_t l_new = (L_in[i] & ~mv[i]) | arrive;
+        asm("" : "+v"(l_new));
+        o.mv_h[i] = mv[i];
+        o.l_h[i] = l_new;
+        // TB cars of row r-1 move into the cells of row r that held no car.
+        const uint32_t mvt = lv.T[i] & E[i];
+        uint32_t t_new = (lv.T[i] & ~mvt) | lv.mvp[i];
+        asm("" : "+v"(t_new));
+        o.L[i] = lv.L[i];
+        o.T[i] = t_new;
+        o.mv_v[i] = mvt;
+        lv.L[i] = l_new;
+        lv.T[i] = T_in[i];
+        lv.mvp[i] = mvt;
+    }
+    return o;
+}
+
 // Model II coin word: the low 32 bits of SplitMix64 output number k of the
 // stream started at `seed` (Steele, Lea and Flood; Vigna's constants);
 // k = step * rows * words + row * words + word, bit b = the coin of cell

@@ -76,7 +76,8 @@ class Lattice:
 
     def set_model(self, model: int, coin_seed: int = 0) -> None:
         """1: the model of Sec. 2 (default); 2: Model II with conflict coins
-        from stream `coin_seed`."""
+        from stream `coin_seed`; 3: Model III (a contested cell takes both
+        cars, cell value 3)."""
         B.bml_set_model(self.handle, model, coin_seed)
 
     @property

@@ -93,10 +93,10 @@ def test_init_rejects_bad_cell_values_without_gpu(B):
     lib = B.lib()
     h = ctypes.c_void_p()
     cells = np.zeros(64 * 64, dtype=np.uint8)
-    cells[100] = 3
+    cells[100] = 4          # 0..2, and 3 (both cars, Model III) are the cell values
     rc = lib.bml_init(ctypes.byref(h), 64, 0, 0, 0.3, cells.ctypes.data, 1 << 20, 1 << 21,
                       1 << 22, 16, None)
-    assert rc == B.BML_EINVAL and "value 3" in B.bml_last_error()
+    assert rc == B.BML_EINVAL and "value 4" in B.bml_last_error()
 
 
 def test_step_group_rejects_bad_arguments_without_gpu(B):
@@ -152,3 +152,7 @@ def test_set_model_rejects_null_handle(B):
     lib = B.lib()
     assert lib.bml_set_model(None, 2, 7) == B.BML_ESTATE
     assert lib.bml_set_model(None, 1, 0) == B.BML_ESTATE
+
+
+def test_set_model_three_rejects_null_handle(B):
+    assert B.lib().bml_set_model(None, 3, 0) == B.BML_ESTATE

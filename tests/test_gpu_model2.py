@@ -164,7 +164,7 @@ def test_model2_errors(B):
     a = B.Lattice(64, 0.3, 1, stream=stream)
     b = B.Lattice(64, 0.3, 2, stream=stream)
     try:
-        for bad in (0, 3, -1):
+        for bad in (0, 4, -1):
             with pytest.raises(B.BmlError) as e:
                 a.set_model(bad)
             assert e.value.code == B.BML_EINVAL

@@ -1,0 +1,190 @@
+"""GPU parity of Model III (Sec. 2: a cell may hold an LR and a TB car; read
+as the one-phase step in which an EMPTY cell wanted by both types takes both)
+against the oracle's Model III run: every cell (0..3) and every per-step
+count, bit for bit, for tile and row widths, every pass length, passes that
+end mid-pass, continued step calls, joint launches, lattices that start with
+doubly occupied cells, and the 4096 x 4096 lattice.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+U8, BP = 0, 1
+LAYOUTS = [U8, BP]
+HOST_THREADS = min(16, os.cpu_count() or 1)
+BOTH = 3
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_07981_amd as pkg
+    pkg.lib()   # fail loudly if the library is missing
+    return pkg
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stats_array(rec):
+    return np.stack([rec["n_lr"], rec["moved_lr"], rec["n_tb"], rec["moved_tb"]], axis=1)
+
+
+def check_cells(got, want, what=""):
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        pytest.fail(f"{what}: {len(bad)} cells differ, first at {bad[0]}")
+
+
+M3_CASES = [(32, 64), (96, 96), (256, 256), (200, 2048), (33, 4096), (1000, 96),
+            (64, 3008), (40, 32), (130, 4096)]
+M3_TUNINGS = [(0, 16, 4), (8, 6, 2), (3, 12, 1), (24, 2, 1), (1, 16, 4), (0, 14, 2)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("rows,cols", M3_CASES, ids=[f"{r}x{c}" for r, c in M3_CASES])
+def test_model3_matches_oracle(B, layout, rows, cols):
+    rng = np.random.default_rng(rows * 6007 + cols + 29 * layout)
+    for n_t, tuning in enumerate(M3_TUNINGS):
+        seed = int(rng.integers(0, 2**32))
+        rho_lr, rho_tb = float(rng.uniform(0.05, 0.45)), float(rng.uniform(0.05, 0.45))
+        steps = int(rng.integers(1, 2 * tuning[1] + 5))
+        g0 = oracle.init_cells_asym(rows, cols, seed, rho_lr, rho_tb)
+        if n_t % 2:                      # every other case starts with doubly occupied cells
+            g0[rng.random(g0.shape) < 0.05] = BOTH
+        say(f"model3 {rows}x{cols} layout={layout} tuning={tuning} steps={steps} seed={seed} "
+            f"lr={rho_lr:.3f} tb={rho_tb:.3f} both0={int((g0 == BOTH).sum())}")
+        want, wst = oracle.run_model3(g0, steps, n_threads=HOST_THREADS)
+        with B.Lattice(rows, cols=cols, cells=g0, layout=layout, stats_cap=64) as lat:
+            lat.set_model(3)
+            lat.set_tuning(*tuning)
+            lat.step(steps)
+            check_cells(lat.cells(), want, f"tuning {tuning}")
+            assert np.array_equal(stats_array(lat.stats(0, steps)), wst)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_model3_calls_continue(B, layout):
+    rows, cols, seed = 160, 2048, 43
+    g0 = oracle.init_cells_asym(rows, cols, seed, 0.25, 0.25)
+    with B.Lattice(rows, seed=seed, cols=cols, rho_lr=0.25, rho_tb=0.25, layout=layout,
+                   stats_cap=128) as lat:
+        lat.set_model(3)
+        done = 0
+        want, wst_all = g0, []
+        for n, tuning in [(3, (0, 16, 4)), (11, (8, 10, 2)), (1, (0, 2, 4)), (7, (0, 8, 1))]:
+            lat.set_tuning(*tuning)
+            lat.step(n)
+            want, wst = oracle.run_model3(want, n, n_threads=HOST_THREADS)
+            wst_all.append(wst)
+            done += n
+            check_cells(lat.cells(), want, f"after {done} steps")
+        assert (want == BOTH).any()
+        assert np.array_equal(stats_array(lat.stats(0, done)), np.concatenate(wst_all))
+
+
+def test_model3_contested_cells_take_both(B):
+    rows, cols = 64, 2048
+    g = np.zeros((rows, cols), np.uint8)
+    g[1::2, 0::2] = 1
+    g[0::2, 1::2] = 2
+    want, wst = oracle.run_model3(g, 1)
+    with B.Lattice(rows, cols=cols, cells=g, stats_cap=4) as lat:
+        lat.set_model(3)
+        lat.step(1)
+        got = lat.cells()
+        check_cells(got, want)
+        assert (got[1::2, 1::2] == BOTH).all()
+        assert np.array_equal(stats_array(lat.stats(0, 1)), wst)
+
+
+M3_GROUP_CASES = [(4096, BP, (16, 16, 4), 4), (2048, U8, (0, 6, 4), 3), (224, BP, (24, 16, 1), 8),
+                  (96, U8, (3, 14, 4), 5)]
+
+
+@pytest.mark.parametrize("n,layout,tuning,count", M3_GROUP_CASES,
+                         ids=[f"n{n}_l{l}_vr{t[0]}_t{t[1]}_w{t[2]}_x{c}"
+                              for n, l, t, c in M3_GROUP_CASES])
+def test_model3_step_group(B, n, layout, tuning, count):
+    import torch
+    rng = np.random.default_rng(n * 11 + layout)
+    stream = torch.cuda.Stream()
+    rhos = [0.25, 0.35, 0.38, 0.45, 0.9, 0.1, 0.5, 0.3][:count]
+    seeds = [int(x) for x in rng.integers(0, 2**32, count)]
+    pre = [0, 3, 5, 0, 1, 2, 0, 7][:count]
+    steps = int(rng.integers(1, 3 * tuning[1]))
+    say(f"model3 group n={n} layout={layout} tuning={tuning} count={count} steps={steps}")
+    lats = [B.Lattice(n, r, sd, layout=layout, stats_cap=64, stream=stream)
+            for r, sd in zip(rhos, seeds)]
+    try:
+        for lat, p in zip(lats, pre):
+            lat.set_model(3)
+            lat.set_tuning(*tuning)
+            if p:
+                lat.step(p)
+        B.step_group(lats, steps)
+        for lat, r, sd, p in zip(lats, rhos, seeds, pre):
+            want, wst = oracle.run_model3(oracle.init_cells(n, sd, r), p + steps,
+                                          n_threads=HOST_THREADS)
+            check_cells(lat.cells(), want, f"rho={r}")
+            assert np.array_equal(stats_array(lat.stats(p, steps)), wst[p:])
+    finally:
+        for lat in lats:
+            lat.close()
+
+
+def test_model3_rules_for_doubly_occupied_lattices(B):
+    g = np.zeros((64, 64), np.uint8)
+    g[5, 7] = BOTH
+    g[9, 9] = 1
+    with B.Lattice(64, cells=g, stats_cap=8) as lat:
+        with pytest.raises(B.BmlError) as e:
+            lat.step(1)                       # Model I has no doubly occupied cells
+        assert e.value.code == B.BML_EINVAL
+        with pytest.raises(B.BmlError) as e:
+            lat.set_model(2, 1)
+        assert e.value.code == B.BML_EINVAL
+        lat.set_model(3)
+        lat.step(4)
+        want, _ = oracle.run_model3(g, 4)
+        check_cells(lat.cells(), want)
+        with pytest.raises(B.BmlError) as e:
+            lat.set_model(1)
+        assert e.value.code == B.BML_EINVAL
+    with B.Lattice(64, 0.3, 5, stats_cap=8) as lat:
+        lat.set_model(3)
+        with pytest.raises(B.BmlError) as e:
+            lat.set_topology(B.BML_TOPO_KLEIN)
+        assert e.value.code == B.BML_EINVAL
+        lat.set_model(1)                      # no Model III step yet: free to switch
+        lat.set_topology(B.BML_TOPO_KLEIN)
+        with pytest.raises(B.BmlError) as e:
+            lat.set_model(3)
+        assert e.value.code == B.BML_EINVAL
+        with pytest.raises(B.BmlError) as e:
+            lat.set_model(4)
+        assert e.value.code == B.BML_EINVAL
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_model3_medium_full_lattice(B, layout):
+    """4096 x 4096 at rho 0.38: every cell after 64 Model III steps in the
+    default launch shape, and all 64 count rows."""
+    import workloads
+    w = workloads.MEDIUM.lattices[2]
+    g0 = oracle.init_cells(w.n, w.seed, w.rho)
+    want, wst = oracle.run_model3(g0, 64, n_threads=HOST_THREADS)
+    with B.Lattice(w.n, w.rho, w.seed, layout=layout, stats_cap=64) as lat:
+        lat.set_model(3)
+        lat.step(64)
+        check_cells(lat.cells(), want)
+        assert np.array_equal(stats_array(lat.stats(0, 64)), wst)
