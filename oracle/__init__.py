@@ -72,7 +72,7 @@ def lib() -> ctypes.CDLL:
         L.bmlo_run.restype = None
         L.bmlo_run_topo.argtypes = [i64, i64, vp, vp, i64, vp, i32, i32]
         L.bmlo_run_topo.restype = None
-        L.bmlo_run_model2.argtypes = [i64, i64, vp, vp, i64, i64, u64, vp, i32]
+        L.bmlo_run_model2.argtypes = [i64, i64, vp, vp, i64, i64, u64, vp, i32, i64, i64, i64, i64]
         L.bmlo_run_model2.restype = None
         L.bmlo_run_model3.argtypes = [i64, i64, vp, vp, i64, vp, i32]
         L.bmlo_run_model3.restype = None
@@ -173,17 +173,26 @@ def run(cells: np.ndarray, steps: int, n_threads: int = 1, topology: int = TORUS
 
 
 def run_model2(cells: np.ndarray, steps: int, coin_seed: int, step0: int = 0,
-               n_threads: int = 1) -> tuple[np.ndarray, np.ndarray]:
+               n_threads: int = 1, frame: tuple[int, int, int, int] | None = None
+               ) -> tuple[np.ndarray, np.ndarray]:
     """Model II (Sec. 2): both car types move in one phase per step; a
     contested empty cell goes to the LR car when the step's counter-based
     coin for that cell is 1 (bit j%32 of SplitMix64 output
     step*rows*W + i*W + j//32 of stream coin_seed, W = ceil(cols/32)).
-    step0 is the global index of the first step (it selects the coins)."""
+    step0 is the global index of the first step (it selects the coins).
+    frame = (row0, col0, rows_g, cols_g) runs `cells` as the window at
+    (row0, col0) of a rows_g x cols_g lattice: every cell draws the coin of
+    its position there (the window itself stays periodic, so only cells
+    farther than `steps` from its edges match the large lattice's run)."""
     a = _u8(cells).copy()
     tmp = np.empty_like(a)
     stats = np.zeros((max(steps, 0), 4), dtype=np.uint32)
+    row0, col0, rows_g, cols_g = frame or (0, 0, a.shape[0], a.shape[1])
+    if not (0 <= row0 < rows_g and 0 <= col0 < cols_g):
+        raise ValueError("window origin outside the lattice")
     lib().bmlo_run_model2(a.shape[0], a.shape[1], _ptr(a), _ptr(tmp), int(steps), int(step0),
-                          coin_seed & (2**64 - 1), _ptr(stats), int(n_threads))
+                          coin_seed & (2**64 - 1), _ptr(stats), int(n_threads), int(row0),
+                          int(col0), int(rows_g), int(cols_g))
     return a, stats
 
 

@@ -271,19 +271,29 @@ static void run_topo(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
 /* SplitMix64 output number s*(rows*W) + i*W + j/32 of stream `coin_seed`,  */
 /* W = ceil(cols/32); 1 means the LR car moves.  Torus only.                */
 /* stats per step: n_lr, moved_lr, n_tb, moved_tb after that one phase.     */
+/* A window of a larger lattice (used to check a large run on small        */
+/* windows) keeps the coins of its cells' positions in that lattice: cell   */
+/* (i, j) of the window is cell ((row0 + i) mod rows_g, (col0 + j) mod      */
+/* cols_g) of a rows_g x cols_g lattice, and i, j, rows, cols above are     */
+/* those global ones.  A whole lattice is its own frame (0, 0, rows, cols). */
 /* ------------------------------------------------------------------------ */
-static int model2_coin(uint64_t coin_seed, int64_t step, int64_t rows, int64_t cols,
-                       int64_t i, int64_t j)
+typedef struct {
+    int64_t row0, col0, rows_g, cols_g;
+} coin_frame;
+
+static int model2_coin(uint64_t coin_seed, int64_t step, const coin_frame *f, int64_t i,
+                       int64_t j)
 {
-    int64_t words = (cols + 31) / 32;
-    uint64_t k = (uint64_t)step * (uint64_t)(rows * words) + (uint64_t)(i * words + j / 32);
+    int64_t gi = (f->row0 + i) % f->rows_g, gj = (f->col0 + j) % f->cols_g;
+    int64_t words = (f->cols_g + 31) / 32;
+    uint64_t k = (uint64_t)step * (uint64_t)(f->rows_g * words) + (uint64_t)(gi * words + gj / 32);
     uint32_t z = (uint32_t)bmlo_splitmix64(coin_seed, k);
-    return (int)((z >> (j % 32)) & 1u);
+    return (int)((z >> (gj % 32)) & 1u);
 }
 
 static void model2_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
                         const uint8_t *cur, uint8_t *next, uint64_t coin_seed, int64_t step,
-                        int64_t *moved_lr, int64_t *moved_tb)
+                        const coin_frame *f, int64_t *moved_lr, int64_t *moved_tb)
 {
     for (int64_t i = r0; i < r1; i++) {
         int64_t up = (i - 1 + rows) % rows, down = (i + 1) % rows;
@@ -294,7 +304,7 @@ static void model2_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
                 int from_left = cur[i * cols + left] == LR;
                 int from_top = cur[up * cols + j] == TB;
                 if (from_left && from_top)
-                    out = model2_coin(coin_seed, step, rows, cols, i, j) ? LR : TB;
+                    out = model2_coin(coin_seed, step, f, i, j) ? LR : TB;
                 else if (from_left)
                     out = LR;
                 else if (from_top)
@@ -302,14 +312,14 @@ static void model2_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
             } else if (c == LR && cur[i * cols + right] == EMPTY) {
                 /* a TB car above the target competes for it */
                 int contested = cur[up * cols + right] == TB;
-                if (!contested || model2_coin(coin_seed, step, rows, cols, i, right)) {
+                if (!contested || model2_coin(coin_seed, step, f, i, right)) {
                     out = EMPTY;
                     (*moved_lr)++;
                 }
             } else if (c == TB && cur[down * cols + j] == EMPTY) {
                 /* an LR car left of the target competes for it */
                 int contested = cur[down * cols + left] == LR;
-                if (!contested || !model2_coin(coin_seed, step, rows, cols, down, j)) {
+                if (!contested || !model2_coin(coin_seed, step, f, down, j)) {
                     out = EMPTY;
                     (*moved_tb)++;
                 }
@@ -319,11 +329,14 @@ static void model2_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
     }
 }
 
-/* `steps` Model II steps starting at global step `step0` (the coin index). */
+/* `steps` Model II steps starting at global step `step0` (the coin index),  */
+/* the lattice being the window (row0, col0) of a rows_g x cols_g one.       */
 void bmlo_run_model2(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp, int64_t steps,
-                     int64_t step0, uint64_t coin_seed, uint32_t *stats, int32_t n_threads)
+                     int64_t step0, uint64_t coin_seed, uint32_t *stats, int32_t n_threads,
+                     int64_t row0, int64_t col0, int64_t rows_g, int64_t cols_g)
 {
     int nt = n_threads > 0 ? n_threads : 1;
+    const coin_frame frame = {row0, col0, rows_g, cols_g};
     for (int64_t s = 0; s < steps; s++) {
         int64_t moved_lr = 0, moved_tb = 0;
 #ifdef _OPENMP
@@ -331,7 +344,7 @@ void bmlo_run_model2(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp, i
 #endif
         for (int64_t i = 0; i < rows; i++) {
             int64_t ml = 0, mt = 0;
-            model2_rows(i, i + 1, rows, cols, cells, tmp, coin_seed, step0 + s, &ml, &mt);
+            model2_rows(i, i + 1, rows, cols, cells, tmp, coin_seed, step0 + s, &frame, &ml, &mt);
             moved_lr += ml;
             moved_tb += mt;
         }

@@ -40,11 +40,11 @@ MUTATIONS = [
      "uint8_t top = cur[up * cols + v_col(j, cols, i == 0, topology)];",
      "uint8_t top = cur[up * cols + v_col(j, cols, i == 1, topology)];"),
     ("Model II: the TB car obeys the coin the wrong way round",
-     "if (!contested || !model2_coin(coin_seed, step, rows, cols, down, j)) {",
-     "if (!contested || model2_coin(coin_seed, step, rows, cols, down, j)) {"),
+     "if (!contested || !model2_coin(coin_seed, step, f, down, j)) {",
+     "if (!contested || model2_coin(coin_seed, step, f, down, j)) {"),
     ("Model II: the LR car reads the coin of its own cell",
-     "if (!contested || model2_coin(coin_seed, step, rows, cols, i, right)) {",
-     "if (!contested || model2_coin(coin_seed, step, rows, cols, i, j)) {"),
+     "if (!contested || model2_coin(coin_seed, step, f, i, right)) {",
+     "if (!contested || model2_coin(coin_seed, step, f, i, j)) {"),
     ("Model III: an LR car enters a cell that holds only a TB car",
      "if (cur[i * cols + right] == EMPTY)\n                    (*moved_lr)++;",
      "if (!(cur[i * cols + right] & LR))\n                    (*moved_lr)++;"),
@@ -54,6 +54,9 @@ MUTATIONS = [
     ("Model III: cars arrive in a cell the other type holds",
      "if (c == EMPTY) {                 /* arrivals, possibly both */",
      "if (c != BOTH) {                  /* arrivals, possibly both */"),
+    ("Model II window: the coin column ignores the window origin",
+     "int64_t gi = (f->row0 + i) % f->rows_g, gj = (f->col0 + j) % f->cols_g;",
+     "int64_t gi = (f->row0 + i) % f->rows_g, gj = j % f->cols_g;"),
     ("asymmetric TB threshold without the LR share", "*thr_tb = (uint64_t)ldexp(rho_lr + rho_tb, 53);",
      "*thr_tb = (uint64_t)ldexp(rho_tb, 53);"),
 ]

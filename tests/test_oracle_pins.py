@@ -402,6 +402,28 @@ def test_model2_step_index_selects_the_coins():
     assert np.array_equal(a, b2) and np.array_equal(sa, np.concatenate([s1, s2]))
 
 
+@pytest.mark.parametrize("i0,j0", [(0, 0), (37, 70), (90, 150), (5, 180)])
+def test_model2_window_with_global_coins_matches_the_whole_lattice(i0, j0):
+    """After s steps a cell depends only on cells within s rows and columns
+    of it, so a padded window run with the coins of its global positions
+    reproduces the whole lattice's run in its middle (windows that cross the
+    lattice's edges included)."""
+    rows, cols, steps, w = 96, 192, 6, 24
+    rng = np.random.default_rng(i0 * 31 + j0)
+    g = workloads.random_lattice(rng, rows, cols, 0.3, 0.3)
+    full, _ = oracle.run_model2(g, steps, 0xABCDEF, step0=11)
+    r = np.arange(i0 - steps, i0 + w + steps) % rows
+    c = np.arange(j0 - steps, j0 + w + steps) % cols
+    pad = g[np.ix_(r, c)]
+    frame = ((i0 - steps) % rows, (j0 - steps) % cols, rows, cols)
+    win, _ = oracle.run_model2(pad, steps, 0xABCDEF, step0=11, frame=frame)
+    want = full[np.ix_(r[steps:steps + w], c[steps:steps + w])]
+    assert np.array_equal(win[steps:steps + w, steps:steps + w], want)
+    # the window's own coins (no frame) generally differ
+    own, _ = oracle.run_model2(pad, steps, 0xABCDEF, step0=11)
+    assert (i0, j0) == (0, 0) or not np.array_equal(own, win)
+
+
 # --- Model III (Sec. 2): a cell may hold an LR and a TB car at once --------
 
 BOTH = LR | TB
