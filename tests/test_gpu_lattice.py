@@ -573,7 +573,8 @@ def test_large_sampled_windows(B, layout):
     n, rho, seed, steps, W = 32768, 0.30, 7, 48, 64
     say(f"large sampled n={n} layout={layout}")
     g0 = oracle.init_cells(n, seed, rho)
-    with make(B, n, rho, seed, layout, cap=steps) as lat:
+    import bench
+    with make(B, n, rho, seed, layout, cap=steps, tuning=bench.load_tuning(layout, n)) as lat:
         lat.step(2)
         got2 = stats_array(lat.stats(0, 2))
         lat.step(steps - 2)
@@ -585,6 +586,41 @@ def test_large_sampled_windows(B, layout):
     rng = np.random.default_rng(7)
     picks = [(0, 0), (0, n - W), (n - W, 0), (n - W, n - W), (n // 2, n // 2 - 32)]
     picks += [tuple(int(x) for x in rng.integers(0, n, size=2)) for _ in range(7)]
+    for i0, j0 in picks:
+        pad = window(g0, i0 - steps, j0 - steps, W + 2 * steps)
+        ref, _ = oracle.run(pad, steps)
+        assert np.array_equal(window(got, i0, j0, W), ref[steps:steps + W, steps:steps + W]), \
+            (i0, j0)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_klein_large(B, layout):
+    """32768 x 32768 Klein bottle in the benchmark's launch shape, 40 steps:
+    windows whose dependence cone stays clear of the glued edge match the
+    torus oracle on padded windows; over the whole lattice every row keeps
+    its LR cars and every column pair (j, N-1-j) its TB cars (a TB car
+    crossing the glued edge changes column j for N-1-j); the car counts of
+    every step are the initial ones."""
+    import bench
+    n, rho, seed, steps, W = 32768, 0.30, 7, 40, 64
+    say(f"klein large n={n} layout={layout}")
+    g0 = oracle.init_cells(n, seed, rho)
+    with make(B, n, rho, seed, layout, cap=steps) as lat:
+        lat.set_topology(B.BML_TOPO_KLEIN)
+        tun = bench.load_tuning(layout, n)
+        if tun:
+            lat.set_tuning(*tun)
+        lat.step(steps)
+        got = lat.cells()
+        st = stats_array(lat.stats(0, steps))
+    assert (st[:, 0] == oracle.count(g0, 1)).all() and (st[:, 2] == oracle.count(g0, 2)).all()
+    assert np.array_equal((got == 1).sum(axis=1), (g0 == 1).sum(axis=1))
+    tb_got, tb0 = (got == 2).sum(axis=0), (g0 == 2).sum(axis=0)
+    assert np.array_equal(tb_got + tb_got[::-1], tb0 + tb0[::-1])
+    assert not np.array_equal(tb_got, tb0)      # some TB cars crossed the glued edge
+    rng = np.random.default_rng(74)
+    picks = [(steps, 0), (n - W - steps, n - W), (n // 2, n // 2 - 32)]
+    picks += [(int(rng.integers(steps, n - W - steps)), int(rng.integers(0, n))) for _ in range(5)]
     for i0, j0 in picks:
         pad = window(g0, i0 - steps, j0 - steps, W + 2 * steps)
         ref, _ = oracle.run(pad, steps)

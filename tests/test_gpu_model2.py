@@ -205,3 +205,42 @@ def test_model2_medium_full_lattice(B, layout):
         lat.step(64)
         check_cells(lat.cells(), want)
         assert np.array_equal(stats_array(lat.stats(0, 64)), wst)
+
+
+# --- the 32768 x 32768 lattice, sampled windows ------------------------------
+
+def _window(g, i0, j0, size):
+    r = np.arange(i0, i0 + size) % g.shape[0]
+    c = np.arange(j0, j0 + size) % g.shape[1]
+    return g[np.ix_(r, c)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_model2_large_sampled_windows(B, layout):
+    """32768 x 32768, rho 0.30, seed 7, Model II in the launch shape the
+    benchmark times (the tuning cache's Model II entry): 24 steps, then 10
+    windows of 64 x 64 (corners, edges, interior) against the oracle run on
+    padded windows with the coins of their global positions; car counts
+    conserved at every step."""
+    import bench
+    n, rho, seed, steps, W, coin = 32768, 0.30, 7, 24, 64, 0x5EED
+    say(f"model2 large sampled n={n} layout={layout}")
+    g0 = oracle.init_cells(n, seed, rho)
+    with B.Lattice(n, rho, seed, layout=layout, stats_cap=steps) as lat:
+        lat.set_model(2, coin)
+        tun = bench.load_tuning(layout, n, None, 2)
+        if tun:
+            lat.set_tuning(*tun)
+        lat.step(steps)
+        got = lat.cells()
+        st = stats_array(lat.stats(0, steps))
+    assert (st[:, 0] == oracle.count(g0, 1)).all() and (st[:, 2] == oracle.count(g0, 2)).all()
+    rng = np.random.default_rng(72)
+    picks = [(0, 0), (0, n - W), (n - W, 0), (n - W, n - W), (n // 2, n // 2 - 32)]
+    picks += [tuple(int(x) for x in rng.integers(0, n, size=2)) for _ in range(5)]
+    for i0, j0 in picks:
+        pad = _window(g0, i0 - steps, j0 - steps, W + 2 * steps)
+        ref, _ = oracle.run_model2(pad, steps, coin,
+                                   frame=((i0 - steps) % n, (j0 - steps) % n, n, n))
+        assert np.array_equal(_window(got, i0, j0, W), ref[steps:steps + W, steps:steps + W]), \
+            (i0, j0)

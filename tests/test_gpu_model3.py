@@ -188,3 +188,43 @@ def test_model3_medium_full_lattice(B, layout):
         lat.step(64)
         check_cells(lat.cells(), want)
         assert np.array_equal(stats_array(lat.stats(0, 64)), wst)
+
+
+# --- the 32768 x 32768 lattice, sampled windows ------------------------------
+
+def _window(g, i0, j0, size):
+    r = np.arange(i0, i0 + size) % g.shape[0]
+    c = np.arange(j0, j0 + size) % g.shape[1]
+    return g[np.ix_(r, c)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_model3_large_sampled_windows(B, layout):
+    """32768 x 32768, rho 0.30, seed 7, Model III in the benchmark's launch
+    shape: 32 steps, then 10 windows of 64 x 64 against the oracle on padded
+    windows (a cell depends only on cells within s rows and columns after s
+    steps); per-row LR and per-column TB counts of the whole lattice
+    conserved."""
+    import bench
+    n, rho, seed, steps, W = 32768, 0.30, 7, 32, 64
+    say(f"model3 large sampled n={n} layout={layout}")
+    g0 = oracle.init_cells(n, seed, rho)
+    with B.Lattice(n, rho, seed, layout=layout, stats_cap=steps) as lat:
+        lat.set_model(3)
+        tun = bench.load_tuning(layout, n, None, 3)
+        if tun:
+            lat.set_tuning(*tun)
+        lat.step(steps)
+        got = lat.cells()
+        st = stats_array(lat.stats(0, steps))
+    assert (st[:, 0] == oracle.count(g0, 1)).all() and (st[:, 2] == oracle.count(g0, 2)).all()
+    assert np.array_equal(((got & 1) > 0).sum(axis=1), (g0 == 1).sum(axis=1))
+    assert np.array_equal(((got & 2) > 0).sum(axis=0), (g0 == 2).sum(axis=0))
+    rng = np.random.default_rng(73)
+    picks = [(0, 0), (0, n - W), (n - W, 0), (n - W, n - W), (n // 2, n // 2 - 32)]
+    picks += [tuple(int(x) for x in rng.integers(0, n, size=2)) for _ in range(5)]
+    for i0, j0 in picks:
+        pad = _window(g0, i0 - steps, j0 - steps, W + 2 * steps)
+        ref, _ = oracle.run_model3(pad, steps)
+        assert np.array_equal(_window(got, i0, j0, W), ref[steps:steps + W, steps:steps + W]), \
+            (i0, j0)
