@@ -628,6 +628,42 @@ def test_klein_large(B, layout):
             (i0, j0)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rect_large_sampled_windows(B, layout):
+    """The rectangular workload (8192 rows x 32768 columns, rho_LR 0.20,
+    rho_TB 0.10, seed 11) in the benchmark's tuned launch shape, 40 steps:
+    windows of 64 x 64 (corners, edges, interior) against the oracle on
+    padded windows; per-row LR and per-column TB counts conserved."""
+    import bench
+    lt = workloads.RECT.lattices[0]
+    rows, cols, steps, W = lt.n, lt.cols, 40, 64
+    say(f"rect large {rows}x{cols} layout={layout}")
+    g0 = oracle.init_cells_asym(rows, cols, lt.seed, lt.rho_lr, lt.rho_tb)
+    with B.Lattice(rows, seed=lt.seed, cols=cols, rho_lr=lt.rho_lr, rho_tb=lt.rho_tb,
+                   layout=layout, stats_cap=steps) as lat:
+        tun = bench.load_tuning(layout, f"{rows}x{cols}")
+        if tun:
+            lat.set_tuning(*tun)
+        lat.step(steps)
+        got = lat.cells()
+        st = stats_array(lat.stats(0, steps))
+    assert (st[:, 0] == oracle.count(g0, 1)).all() and (st[:, 2] == oracle.count(g0, 2)).all()
+    assert np.array_equal((got == 1).sum(axis=1), (g0 == 1).sum(axis=1))
+    assert np.array_equal((got == 2).sum(axis=0), (g0 == 2).sum(axis=0))
+
+    def win(g, i0, j0, h, w):
+        return g[np.ix_(np.arange(i0, i0 + h) % rows, np.arange(j0, j0 + w) % cols)]
+
+    rng = np.random.default_rng(75)
+    picks = [(0, 0), (0, cols - W), (rows - W, 0), (rows - W, cols - W)]
+    picks += [(int(rng.integers(0, rows)), int(rng.integers(0, cols))) for _ in range(6)]
+    for i0, j0 in picks:
+        pad = win(g0, i0 - steps, j0 - steps, W + 2 * steps, W + 2 * steps)
+        ref, _ = oracle.run(pad, steps)
+        assert np.array_equal(win(got, i0, j0, W, W), ref[steps:steps + W, steps:steps + W]), \
+            (i0, j0)
+
+
 def test_copy_reference_kernel(B):
     """The bandwidth reference copy moves every byte, including a tail that
     is not a multiple of the grid's stride."""
