@@ -181,14 +181,25 @@ constexpr int CHUNK = 32;    // samples staged in LDS at a time
 
 // Gradient of the mean BCE-with-logits loss over samples idx[0..n) (idx NULL
 // = 0..n-1) into grad[NP]; loss into *loss.  n <= MAX_BATCH.
-__device__ void mlp_grad_block(const float *params, const float *x, const float *y,
+__device__ __forceinline__ void mlp_grad_block(const float *params, const float *x, const float *y,
                                const int32_t *idx, int n, SampleScratch *scr, float *grad,
                                float *loss)
 {
     __shared__ float P[NP];
     __shared__ float red[MAX_BATCH];
-    __shared__ float cx[CHUNK][NI], ch1[CHUNK][NH], cd1[CHUNK][NH], ch2[CHUNK][NH],
-        cd2[CHUNK][NH], cdz[CHUNK];
+    // Per-sample hidden vector of layer 1, [unit][sample]: read back with a
+    // loop-variable index (LDS), so no register array is ever indexed by a
+    // loop variable (that would place it in scratch memory).  The staging
+    // arrays of the parameter-gradient sums below reuse the same LDS.
+    __shared__ float lds_h1[NH * MAX_BATCH];
+    static_assert(sizeof(float) * (CHUNK * (NI + 4 * NH + 1)) <= sizeof(float) * NH * MAX_BATCH,
+                  "gradient staging fits the activation buffer");
+    float(*cx)[NI] = reinterpret_cast<float(*)[NI]>(lds_h1);
+    float(*ch1)[NH] = reinterpret_cast<float(*)[NH]>(lds_h1 + CHUNK * NI);
+    float(*cd1)[NH] = ch1 + CHUNK;
+    float(*ch2)[NH] = cd1 + CHUNK;
+    float(*cd2)[NH] = ch2 + CHUNK;
+    float *cdz = &cd2[CHUNK][0];
     for (int p = threadIdx.x; p < NP; p += blockDim.x)
         P[p] = params[p];
     __syncthreads();
@@ -196,44 +207,64 @@ __device__ void mlp_grad_block(const float *params, const float *x, const float 
     float li = 0.0f;
     if (i < n) {
         const int64_t row = idx ? idx[i] : i;
-        const float *xi = x + row * NI;
+        const float *xg = x + row * NI;
         SampleScratch &s = scr[i];
-        float h[NH];
+        float xi[NI];
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+            xi[c] = xg[c];
+            s.x[c] = xi[c];
+        }
+        // layer 1: h1 = relu(W1 x + b1), each sum over c in ascending order
         for (int j = 0; j < NH; ++j) {
             float a = P[OFF_B1 + j];
+#pragma unroll
             for (int c = 0; c < NI; ++c)
                 a = fmaf(P[OFF_W1 + j * NI + c], xi[c], a);
-            h[j] = fmaxf(a, 0.0f);
-            s.h1[j] = h[j];
+            a = fmaxf(a, 0.0f);
+            lds_h1[j * MAX_BATCH + i] = a;
+            s.h1[j] = a;
         }
-        for (int c = 0; c < NI; ++c)
-            s.x[c] = xi[c];
-        float g[NH];
+        float h[NH];
+#pragma unroll
+        for (int c = 0; c < NH; ++c)
+            h[c] = lds_h1[c * MAX_BATCH + i];
+        // layer 2 and the output: h2 = relu(W2 h1 + b2), z = w3 . h2 + b3;
+        // which h2 units are active is kept as a bit mask for the backward
+        float z = P[OFF_B3];
+        uint64_t active = 0;
         for (int j = 0; j < NH; ++j) {
             float a = P[OFF_B2 + j];
+#pragma unroll
             for (int c = 0; c < NH; ++c)
                 a = fmaf(P[OFF_W2 + j * NH + c], h[c], a);
-            g[j] = fmaxf(a, 0.0f);
+            a = fmaxf(a, 0.0f);
+            s.h2[j] = a;
+            active |= (uint64_t)(a > 0.0f) << j;
+            z = fmaf(P[OFF_W3 + j], a, z);
         }
-        float z = P[OFF_B3];
-        for (int c = 0; c < NH; ++c)
-            z = fmaf(P[OFF_W3 + c], g[c], z);
         const float yi = y[row];
         li = bce_with_logits(z, yi);
         const float dz = (sigmoidf(z) - yi) / (float)n;
         s.dz = dz;
+        // backward: d2 = dz w3 on active units; d1 = (W2^T d2) on active
+        // layer-1 units, each sum over j in ascending order
+        float acc1[NH];
+#pragma unroll
+        for (int c = 0; c < NH; ++c)
+            acc1[c] = 0.0f;
         for (int j = 0; j < NH; ++j) {
-            s.h2[j] = g[j];
-            g[j] = g[j] > 0.0f ? dz * P[OFF_W3 + j] : 0.0f;   // now dL/d(pre-act 2)
-            s.d2[j] = g[j];
+            const float d2 = ((active >> j) & 1u) ? dz * P[OFF_W3 + j] : 0.0f;
+            s.d2[j] = d2;
+#pragma unroll
+            for (int c = 0; c < NH; ++c)
+                acc1[c] = fmaf(P[OFF_W2 + j * NH + c], d2, acc1[c]);
         }
-        for (int c = 0; c < NH; ++c) {
-            float a = 0.0f;
-            for (int j = 0; j < NH; ++j)
-                a = fmaf(P[OFF_W2 + j * NH + c], g[j], a);
-            s.d1[c] = h[c] > 0.0f ? a : 0.0f;
-        }
+#pragma unroll
+        for (int c = 0; c < NH; ++c)
+            s.d1[c] = h[c] > 0.0f ? acc1[c] : 0.0f;
     }
+    __syncthreads();   // lds_h1 becomes the gradient staging area below
     red[threadIdx.x] = li;
     __syncthreads();
     for (int o = MAX_BATCH / 2; o > 0; o >>= 1) {
@@ -248,6 +279,7 @@ __device__ void mlp_grad_block(const float *params, const float *x, const float 
     // staged in LDS; thread t owns parameters t, t + 256, ...
     constexpr int PER = (NP + MAX_BATCH - 1) / MAX_BATCH;
     float acc[PER];
+#pragma unroll
     for (int q = 0; q < PER; ++q)
         acc[q] = 0.0f;
     for (int k0 = 0; k0 < n; k0 += CHUNK) {
@@ -265,10 +297,11 @@ __device__ void mlp_grad_block(const float *params, const float *x, const float 
         for (int e = threadIdx.x; e < kn; e += blockDim.x)
             cdz[e] = scr[k0 + e].dz;
         __syncthreads();
+#pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int p = threadIdx.x + q * MAX_BATCH;
             if (p >= NP)
-                break;
+                continue;
             float g = acc[q];
             if (p < OFF_B1) {
                 const int j = p / NI, c = p - j * NI;
@@ -297,6 +330,7 @@ __device__ void mlp_grad_block(const float *params, const float *x, const float 
             acc[q] = g;
         }
     }
+#pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int p = threadIdx.x + q * MAX_BATCH;
         if (p < NP)
@@ -361,26 +395,33 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const float *params, con
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    // fixed trip counts, unrolled: the vectors stay in registers
     float xi[NI];
+#pragma unroll
     for (int c = 0; c < NI; ++c)
         xi[c] = BF16 ? to_bf16(x[i * NI + c]) : x[i * NI + c];
     float h1[NH];
+#pragma unroll
     for (int j = 0; j < NH; ++j) {
         float a = P[OFF_B1 + j];
+#pragma unroll
         for (int c = 0; c < NI; ++c)
             a = fmaf(P[OFF_W1 + j * NI + c], xi[c], a);
         a = fmaxf(a, 0.0f);
         h1[j] = BF16 ? to_bf16(a) : a;
     }
     float h2[NH];
+#pragma unroll
     for (int j = 0; j < NH; ++j) {
         float a = P[OFF_B2 + j];
+#pragma unroll
         for (int c = 0; c < NH; ++c)
             a = fmaf(P[OFF_W2 + j * NH + c], h1[c], a);
         a = fmaxf(a, 0.0f);
         h2[j] = BF16 ? to_bf16(a) : a;
     }
     float z = P[OFF_B3];
+#pragma unroll
     for (int c = 0; c < NH; ++c)
         z = fmaf(P[OFF_W3 + c], h2[c], z);
     logits[i] = z;
