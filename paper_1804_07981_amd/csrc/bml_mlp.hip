@@ -152,10 +152,11 @@ __global__ void standardize_kernel(float *x, int32_t n, const float *mean, const
 }
 
 // ---------------------------------------------------------------------------
-// Training: one block of MAX_BATCH threads per minibatch.  The parameters sit
-// in LDS (33.8 KB); thread i runs sample i forward and back to its hidden
-// gradients, parks its activations in global scratch, and after a barrier
-// every thread reduces the per-sample products of its share of parameters.
+// Training: one block of MAX_BATCH threads runs the minibatch forward and
+// back (thread i = sample i) and parks each sample's activations and
+// pre-activation gradients in global scratch; then one thread per parameter
+// (a grid over all NP parameters) sums its products over the samples and,
+// for a training step, applies Adam.
 // ---------------------------------------------------------------------------
 struct SampleScratch {       // per sample, in global memory
     float x[NI];
@@ -177,29 +178,20 @@ __device__ __forceinline__ float sigmoidf(float z)
     return z >= 0.0f ? 1.0f / (1.0f + expf(-z)) : expf(z) / (1.0f + expf(z));
 }
 
-constexpr int CHUNK = 32;    // samples staged in LDS at a time
 
-// Gradient of the mean BCE-with-logits loss over samples idx[0..n) (idx NULL
-// = 0..n-1) into grad[NP]; loss into *loss.  n <= MAX_BATCH.
-__device__ __forceinline__ void mlp_grad_block(const float *params, const float *x, const float *y,
-                               const int32_t *idx, int n, SampleScratch *scr, float *grad,
-                               float *loss)
+// Forward and backward of samples idx[0..n) (idx NULL = 0..n-1) of the mean
+// BCE-with-logits loss: per-sample activations and pre-activation gradients
+// into scr[0..n), the loss into *loss.  n <= MAX_BATCH.
+__device__ __forceinline__ void mlp_sample_block(const float *params, const float *x,
+                                                 const float *y, const int32_t *idx, int n,
+                                                 SampleScratch *scr, float *loss)
 {
     __shared__ float P[NP];
     __shared__ float red[MAX_BATCH];
     // Per-sample hidden vector of layer 1, [unit][sample]: read back with a
     // loop-variable index (LDS), so no register array is ever indexed by a
-    // loop variable (that would place it in scratch memory).  The staging
-    // arrays of the parameter-gradient sums below reuse the same LDS.
+    // loop variable (that would place it in scratch memory).
     __shared__ float lds_h1[NH * MAX_BATCH];
-    static_assert(sizeof(float) * (CHUNK * (NI + 4 * NH + 1)) <= sizeof(float) * NH * MAX_BATCH,
-                  "gradient staging fits the activation buffer");
-    float(*cx)[NI] = reinterpret_cast<float(*)[NI]>(lds_h1);
-    float(*ch1)[NH] = reinterpret_cast<float(*)[NH]>(lds_h1 + CHUNK * NI);
-    float(*cd1)[NH] = ch1 + CHUNK;
-    float(*ch2)[NH] = cd1 + CHUNK;
-    float(*cd2)[NH] = ch2 + CHUNK;
-    float *cdz = &cd2[CHUNK][0];
     for (int p = threadIdx.x; p < NP; p += blockDim.x)
         P[p] = params[p];
     __syncthreads();
@@ -264,7 +256,6 @@ __device__ __forceinline__ void mlp_grad_block(const float *params, const float 
         for (int c = 0; c < NH; ++c)
             s.d1[c] = h[c] > 0.0f ? acc1[c] : 0.0f;
     }
-    __syncthreads();   // lds_h1 becomes the gradient staging area below
     red[threadIdx.x] = li;
     __syncthreads();
     for (int o = MAX_BATCH / 2; o > 0; o >>= 1) {
@@ -274,92 +265,65 @@ __device__ __forceinline__ void mlp_grad_block(const float *params, const float 
     }
     if (threadIdx.x == 0 && loss)
         *loss = red[0] / (float)n;
-
-    // Parameter gradients: sums over the samples, CHUNK samples at a time
-    // staged in LDS; thread t owns parameters t, t + 256, ...
-    constexpr int PER = (NP + MAX_BATCH - 1) / MAX_BATCH;
-    float acc[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q)
-        acc[q] = 0.0f;
-    for (int k0 = 0; k0 < n; k0 += CHUNK) {
-        const int kn = min(CHUNK, n - k0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < kn * NI; e += blockDim.x)
-            cx[e / NI][e % NI] = scr[k0 + e / NI].x[e % NI];
-        for (int e = threadIdx.x; e < kn * NH; e += blockDim.x) {
-            const int k = e / NH, j = e % NH;
-            ch1[k][j] = scr[k0 + k].h1[j];
-            cd1[k][j] = scr[k0 + k].d1[j];
-            ch2[k][j] = scr[k0 + k].h2[j];
-            cd2[k][j] = scr[k0 + k].d2[j];
-        }
-        for (int e = threadIdx.x; e < kn; e += blockDim.x)
-            cdz[e] = scr[k0 + e].dz;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int p = threadIdx.x + q * MAX_BATCH;
-            if (p >= NP)
-                continue;
-            float g = acc[q];
-            if (p < OFF_B1) {
-                const int j = p / NI, c = p - j * NI;
-                for (int k = 0; k < kn; ++k)
-                    g = fmaf(cd1[k][j], cx[k][c], g);
-            } else if (p < OFF_W2) {
-                const int j = p - OFF_B1;
-                for (int k = 0; k < kn; ++k)
-                    g += cd1[k][j];
-            } else if (p < OFF_B2) {
-                const int j = (p - OFF_W2) / NH, c = (p - OFF_W2) - j * NH;
-                for (int k = 0; k < kn; ++k)
-                    g = fmaf(cd2[k][j], ch1[k][c], g);
-            } else if (p < OFF_W3) {
-                const int j = p - OFF_B2;
-                for (int k = 0; k < kn; ++k)
-                    g += cd2[k][j];
-            } else if (p < OFF_B3) {
-                const int c = p - OFF_W3;
-                for (int k = 0; k < kn; ++k)
-                    g = fmaf(cdz[k], ch2[k][c], g);
-            } else {
-                for (int k = 0; k < kn; ++k)
-                    g += cdz[k];
-            }
-            acc[q] = g;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int p = threadIdx.x + q * MAX_BATCH;
-        if (p < NP)
-            grad[p] = acc[q];
-    }
 }
 
-__global__ __launch_bounds__(MAX_BATCH) void mlp_grad_kernel(const float *params, const float *x,
-                                                             const float *y, int32_t n,
-                                                             SampleScratch *scr, float *grad,
-                                                             float *loss)
+__global__ __launch_bounds__(MAX_BATCH) void mlp_sample_kernel(const float *params,
+                                                               const float *x, const float *y,
+                                                               const int32_t *idx, int32_t n,
+                                                               SampleScratch *scr, float *loss)
 {
-    mlp_grad_block(params, x, y, nullptr, n, scr, grad, loss);
+    mlp_sample_block(params, x, y, idx, n, scr, loss);
 }
 
-// One Adam step (Kingma & Ba): gradient of the minibatch idx[0..n), then
+// Parameter gradients, one thread per parameter: the sum over samples
+// k = 0, 1, ..., n-1 (in that order) of its product of a pre-activation
+// gradient and an input (weights) or of the gradient alone (biases), into
+// grad[p].  With m != NULL also one Adam step (Kingma & Ba):
 // m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, and
 // theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
-__global__ __launch_bounds__(MAX_BATCH) void mlp_train_kernel(
-    float *params, float *m, float *v, float *grad, int64_t t, const float *x, const float *y,
-    const int32_t *idx, int32_t n, float lr, float beta1, float beta2, float eps,
-    SampleScratch *scr, float *loss)
+__global__ __launch_bounds__(256) void mlp_param_kernel(const SampleScratch *scr, int32_t n,
+                                                        float *grad, float *params, float *m,
+                                                        float *v, int64_t t, float lr,
+                                                        float beta1, float beta2, float eps)
 {
-    mlp_grad_block(params, x, y, idx, n, scr, grad, loss);
-    __syncthreads();
-    const float c1 = 1.0f - powf(beta1, (float)t);
-    const float c2 = 1.0f - powf(beta2, (float)t);
-    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
-        const float g = grad[p];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NP)
+        return;
+    float g = 0.0f;
+    if (p < OFF_B1) {
+        const int j = p / NI, c = p - j * NI;
+#pragma unroll 8
+        for (int k = 0; k < n; ++k)
+            g = fmaf(scr[k].d1[j], scr[k].x[c], g);
+    } else if (p < OFF_W2) {
+        const int j = p - OFF_B1;
+#pragma unroll 8
+        for (int k = 0; k < n; ++k)
+            g += scr[k].d1[j];
+    } else if (p < OFF_B2) {
+        const int j = (p - OFF_W2) / NH, c = (p - OFF_W2) - j * NH;
+#pragma unroll 8
+        for (int k = 0; k < n; ++k)
+            g = fmaf(scr[k].d2[j], scr[k].h1[c], g);
+    } else if (p < OFF_W3) {
+        const int j = p - OFF_B2;
+#pragma unroll 8
+        for (int k = 0; k < n; ++k)
+            g += scr[k].d2[j];
+    } else if (p < OFF_B3) {
+        const int c = p - OFF_W3;
+#pragma unroll 8
+        for (int k = 0; k < n; ++k)
+            g = fmaf(scr[k].dz, scr[k].h2[c], g);
+    } else {
+#pragma unroll 8
+        for (int k = 0; k < n; ++k)
+            g += scr[k].dz;
+    }
+    grad[p] = g;
+    if (m) {
+        const float c1 = 1.0f - powf(beta1, (float)t);
+        const float c2 = 1.0f - powf(beta2, (float)t);
         const float mp = beta1 * m[p] + (1.0f - beta1) * g;
         const float vp = beta2 * v[p] + (1.0f - beta2) * g * g;
         m[p] = mp;
@@ -525,8 +489,14 @@ int bml_mlp_grad(const float *d_params, const float *d_x, const float *d_y, int3
     clear_error();
     if (!d_params || !d_x || !d_y || !d_scratch || !d_grad || n < 1 || n > MAX_BATCH)
         return fail(BML_EINVAL, "bml_mlp_grad: bad arguments (1 <= n <= %d)", MAX_BATCH);
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(1), dim3(MAX_BATCH), 0, (hipStream_t)hip_stream,
-                       d_params, d_x, d_y, n, (SampleScratch *)d_scratch, d_grad, d_loss);
+    hipLaunchKernelGGL(mlp_sample_kernel, dim3(1), dim3(MAX_BATCH), 0, (hipStream_t)hip_stream,
+                       d_params, d_x, d_y, (const int32_t *)nullptr, n,
+                       (SampleScratch *)d_scratch, d_loss);
+    BML_HIP(hipGetLastError());
+    hipLaunchKernelGGL(mlp_param_kernel, dim3((NP + 255) / 256), dim3(256), 0,
+                       (hipStream_t)hip_stream, (const SampleScratch *)d_scratch, n, d_grad,
+                       (float *)nullptr, (float *)nullptr, (float *)nullptr, (int64_t)0, 0.0f,
+                       0.0f, 0.0f, 0.0f);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
@@ -541,9 +511,12 @@ int bml_mlp_train_step(float *d_params, float *d_m, float *d_v, float *d_grad, i
         n < 1 || n > MAX_BATCH || t < 1)
         return fail(BML_EINVAL, "bml_mlp_train_step: bad arguments (1 <= n <= %d, t >= 1)",
                     MAX_BATCH);
-    hipLaunchKernelGGL(mlp_train_kernel, dim3(1), dim3(MAX_BATCH), 0, (hipStream_t)hip_stream,
-                       d_params, d_m, d_v, d_grad, t, d_x, d_y, d_idx, n, lr, beta1, beta2, eps,
-                       (SampleScratch *)d_scratch, d_loss);
+    hipLaunchKernelGGL(mlp_sample_kernel, dim3(1), dim3(MAX_BATCH), 0, (hipStream_t)hip_stream,
+                       d_params, d_x, d_y, d_idx, n, (SampleScratch *)d_scratch, d_loss);
+    BML_HIP(hipGetLastError());
+    hipLaunchKernelGGL(mlp_param_kernel, dim3((NP + 255) / 256), dim3(256), 0,
+                       (hipStream_t)hip_stream, (const SampleScratch *)d_scratch, n, d_grad,
+                       d_params, d_m, d_v, t, lr, beta1, beta2, eps);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
