@@ -95,11 +95,11 @@ def load_tuning(layout: int, n, group: str | None = None, model: int = 1):
     return None
 
 
-def traffic_from_profile(name: str, tuning, launches_bytes: float):
+def traffic_from_profile(name: str, tuning, launches_bytes: float, profiles: str = PROFILES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source with the same tuning; else
     None."""
-    path = os.path.join(PROFILES, f"{name}_t{tuning[1]}.traffic.json")
+    path = os.path.join(profiles, f"{name}_t{tuning[1]}.traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -134,7 +134,7 @@ def _pmc_per_dispatch(csv_dir: str, counter: str) -> dict:
     return out
 
 
-def pmc_summary(probe_log: str, fetch_dir: str, write_dir: str) -> int:
+def pmc_summary(probe_log: str, fetch_dir: str, write_dir: str, profiles: str = PROFILES) -> int:
     """HBM bytes per launch of the step kernel from FETCH_SIZE / WRITE_SIZE
     (KiB per dispatch), each scaled so that the 1 GiB copy the probe runs
     first reads as 1 GiB fetched and 1 GiB written."""
@@ -174,7 +174,7 @@ def pmc_summary(probe_log: str, fetch_dir: str, write_dir: str) -> int:
            "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": alg,
            "ratio_to_algorithmic": hbm / alg,
            "dispatches": res["FETCH_SIZE"]["dispatches"]}
-    path = os.path.join(PROFILES,
+    path = os.path.join(profiles,
                         f"pass_{probe['layout']}_{probe['n']}_t{probe['t_phases']}.traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
