@@ -204,8 +204,8 @@ int64_t bmlo_count(const uint8_t *cells, int64_t n, int32_t value)
 
 /* ------------------------------------------------------------------------ */
 /* Step loop.  One step = horizontal phase (cells -> tmp) then vertical     */
-/* phase (tmp -> cells).  Per step it records four counts (the project's    */
-/* reading of "per-phase car counts and moved counts"):                     */
+/* phase (tmp -> cells).  Per step it records four counts, the cars of     */
+/* each type and how many of them moved in their phase:                     */
 /*   stats[4s+0] n_lr     = LR cars in the lattice after the H phase        */
 /*   stats[4s+1] moved_lr = LR cars that moved in the H phase               */
 /*   stats[4s+2] n_tb     = TB cars in the lattice after the V phase        */
