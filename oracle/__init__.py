@@ -183,7 +183,9 @@ def run_model2(cells: np.ndarray, steps: int, coin_seed: int, step0: int = 0,
     frame = (row0, col0, rows_g, cols_g) runs `cells` as the window at
     (row0, col0) of a rows_g x cols_g lattice: every cell draws the coin of
     its position there (the window itself stays periodic, so only cells
-    farther than `steps` from its edges match the large lattice's run)."""
+    farther than `steps` from its edges match the large lattice's run).
+    Parity unpinned against the paper, which gives no Model II values; the
+    coin is a reading and the tests pin it."""
     a = _u8(cells).copy()
     tmp = np.empty_like(a)
     stats = np.zeros((max(steps, 0), 4), dtype=np.uint32)
@@ -200,7 +202,9 @@ def run_model3(cells: np.ndarray, steps: int, n_threads: int = 1
                ) -> tuple[np.ndarray, np.ndarray]:
     """Model III (Sec. 2), read as Model II's one-phase update in which an
     EMPTY cell wanted by an LR and a TB car takes both (value 3 = LR | TB);
-    any car in a cell blocks cars of either type.  Cells hold 0..3."""
+    any car in a cell blocks cars of either type.  Cells hold 0..3.
+    Parity unpinned against the paper (one sentence on Model III): the tests
+    pin this reading, not the paper's numbers."""
     a = _u8(cells, allow_both=True).copy()
     tmp = np.empty_like(a)
     stats = np.zeros((max(steps, 0), 4), dtype=np.uint32)

@@ -276,6 +276,8 @@ static void run_topo(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
 /* (i, j) of the window is cell ((row0 + i) mod rows_g, (col0 + j) mod      */
 /* cols_g) of a rows_g x cols_g lattice, and i, j, rows, cols above are     */
 /* those global ones.  A whole lattice is its own frame (0, 0, rows, cols). */
+/* Parity unpinned against the paper: it gives no Model II values, and the  */
+/* coin is this library's reading; the tests pin the code to that reading.  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int64_t row0, col0, rows_g, cols_g;
@@ -370,6 +372,8 @@ void bmlo_run_model2(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp, i
 /* occupied cell, and each of its two cars leaves by its own rule.  Torus   */
 /* only.  stats per step: n_lr, moved_lr, n_tb, moved_tb after that phase,  */
 /* a doubly occupied cell counting once in n_lr and once in n_tb.           */
+/* Parity unpinned against the paper, which states Model III in one         */
+/* sentence; the tests pin the code to the reading above.                   */
 /* ------------------------------------------------------------------------ */
 #define BOTH (LR | TB)
 
