@@ -194,6 +194,8 @@ int bml_get_topology(const bml_lattice *L);
  * with the Klein topology, or for another model value; ESTATE on an
  * invalid handle. */
 int bml_set_model(bml_lattice *L, int32_t model, uint64_t coin_seed);
+/* The update rule in force (1, 2 or 3), or ESTATE on an invalid handle. */
+int bml_get_model(const bml_lattice *L);
 
 /* Launch shape of the step kernels.  Each wavefront streams down a strip of
  * the lattice `tile_rows` output rows tall (plus t_phases/2 halo rows above

@@ -63,6 +63,7 @@ _SIGNATURES = {
     "bml_set_topology": ([_vp, _i32], ctypes.c_int),
     "bml_set_model": ([_vp, _i32, _u64], ctypes.c_int),
     "bml_get_topology": ([_vp], ctypes.c_int),
+    "bml_get_model": ([_vp], ctypes.c_int),
     "bml_get_tuning": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                         ctypes.POINTER(_i32)], ctypes.c_int),
     "bml_step_count": ([_vp], _i64),
@@ -206,6 +207,10 @@ def bml_set_model(handle: int, model: int, coin_seed: int = 0) -> None:
 
 def bml_get_topology(handle: int) -> int:
     return _check(lib().bml_get_topology(handle))
+
+
+def bml_get_model(handle: int) -> int:
+    return _check(lib().bml_get_model(handle))
 
 
 def bml_step(handle: int, n_steps: int) -> None:

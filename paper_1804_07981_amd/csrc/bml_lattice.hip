@@ -679,6 +679,14 @@ int bml_get_topology(const bml_lattice *L)
     return L->topology;
 }
 
+int bml_get_model(const bml_lattice *L)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    return L->model;
+}
+
 int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases, int32_t waves_per_block)
 {
     clear_error();

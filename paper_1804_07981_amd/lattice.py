@@ -81,6 +81,10 @@ class Lattice:
         B.bml_set_model(self.handle, model, coin_seed)
 
     @property
+    def model(self) -> int:
+        return B.bml_get_model(self.handle)
+
+    @property
     def topology(self) -> int:
         return B.bml_get_topology(self.handle)
 

@@ -156,3 +156,4 @@ def test_set_model_rejects_null_handle(B):
 
 def test_set_model_three_rejects_null_handle(B):
     assert B.lib().bml_set_model(None, 3, 0) == B.BML_ESTATE
+    assert B.lib().bml_get_model(None) == B.BML_ESTATE

@@ -161,7 +161,9 @@ def test_model3_rules_for_doubly_occupied_lattices(B):
             lat.set_model(1)
         assert e.value.code == B.BML_EINVAL
     with B.Lattice(64, 0.3, 5, stats_cap=8) as lat:
+        assert lat.model == 1
         lat.set_model(3)
+        assert lat.model == 3
         with pytest.raises(B.BmlError) as e:
             lat.set_topology(B.BML_TOPO_KLEIN)
         assert e.value.code == B.BML_EINVAL
