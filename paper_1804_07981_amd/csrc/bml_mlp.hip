@@ -181,98 +181,145 @@ __device__ __forceinline__ float sigmoidf(float z)
 
 // Forward and backward of samples idx[0..n) (idx NULL = 0..n-1) of the mean
 // BCE-with-logits loss: per-sample activations and pre-activation gradients
-// into scr[0..n), the loss into *loss.  n <= MAX_BATCH.
-__device__ __forceinline__ void mlp_sample_block(const float *params, const float *x,
-                                                 const float *y, const int32_t *idx, int n,
-                                                 SampleScratch *scr, float *loss)
+// into scr[0..n); the loss summed over each block's samples into
+// part[block] (the parameter kernel adds the blocks in order).
+//
+// A block takes SPB = 64 samples with four threads each; thread (s, q) owns
+// hidden units 16q .. 16q+15 of sample s in both layers.  The inputs, the
+// layer-1 activations and the layer-2 gradients of the block's samples are
+// staged in LDS (rows padded to an odd stride), so every per-thread loop
+// over a vector reads LDS and the only register arrays are the thread's 16
+// accumulators, indexed by unrolled constants.  Each weighted sum runs over
+// its inputs in ascending order; the output logit adds the four threads'
+// partial sums in thread order.
+constexpr int SPB = 64;                  // samples per block (256 threads)
+constexpr int UPT = NH / 4;              // hidden units per thread
+constexpr int XS = NI;                   // staged input row stride (65)
+constexpr int HS = NH + 1;               // staged hidden row stride (65)
+static_assert(MAX_BATCH % SPB == 0 && (MAX_BATCH / SPB) * sizeof(float) <= 64,
+              "loss partials fit the scratch tail");
+
+__global__ __launch_bounds__(256) void mlp_sample_kernel(const float *params, const float *x,
+                                                         const float *y, const int32_t *idx,
+                                                         int32_t n, SampleScratch *scr,
+                                                         float *part)
 {
     __shared__ float P[NP];
-    __shared__ float red[MAX_BATCH];
-    // Per-sample hidden vector of layer 1, [unit][sample]: read back with a
-    // loop-variable index (LDS), so no register array is ever indexed by a
-    // loop variable (that would place it in scratch memory).
-    __shared__ float lds_h1[NH * MAX_BATCH];
+    __shared__ float xs[SPB * XS];
+    __shared__ float h1s[SPB * HS];
+    __shared__ float d2s[SPB * HS];
+    __shared__ float ls[SPB];
+    const int s = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int i = blockIdx.x * SPB + s;
+    const bool live = i < n;
     for (int p = threadIdx.x; p < NP; p += blockDim.x)
         P[p] = params[p];
-    __syncthreads();
-    const int i = threadIdx.x;
-    float li = 0.0f;
-    if (i < n) {
-        const int64_t row = idx ? idx[i] : i;
-        const float *xg = x + row * NI;
-        SampleScratch &s = scr[i];
-        float xi[NI];
-#pragma unroll
-        for (int c = 0; c < NI; ++c) {
-            xi[c] = xg[c];
-            s.x[c] = xi[c];
+    for (int e = threadIdx.x; e < SPB * NI; e += blockDim.x) {
+        const int ss = e / NI, c = e - ss * NI;
+        const int ii = blockIdx.x * SPB + ss;
+        float v = 0.0f;
+        if (ii < n) {
+            v = x[(int64_t)(idx ? idx[ii] : ii) * NI + c];
+            scr[ii].x[c] = v;
         }
-        // layer 1: h1 = relu(W1 x + b1), each sum over c in ascending order
-        for (int j = 0; j < NH; ++j) {
-            float a = P[OFF_B1 + j];
-#pragma unroll
-            for (int c = 0; c < NI; ++c)
-                a = fmaf(P[OFF_W1 + j * NI + c], xi[c], a);
-            a = fmaxf(a, 0.0f);
-            lds_h1[j * MAX_BATCH + i] = a;
-            s.h1[j] = a;
-        }
-        float h[NH];
-#pragma unroll
-        for (int c = 0; c < NH; ++c)
-            h[c] = lds_h1[c * MAX_BATCH + i];
-        // layer 2 and the output: h2 = relu(W2 h1 + b2), z = w3 . h2 + b3;
-        // which h2 units are active is kept as a bit mask for the backward
-        float z = P[OFF_B3];
-        uint64_t active = 0;
-        for (int j = 0; j < NH; ++j) {
-            float a = P[OFF_B2 + j];
-#pragma unroll
-            for (int c = 0; c < NH; ++c)
-                a = fmaf(P[OFF_W2 + j * NH + c], h[c], a);
-            a = fmaxf(a, 0.0f);
-            s.h2[j] = a;
-            active |= (uint64_t)(a > 0.0f) << j;
-            z = fmaf(P[OFF_W3 + j], a, z);
-        }
-        const float yi = y[row];
-        li = bce_with_logits(z, yi);
-        const float dz = (sigmoidf(z) - yi) / (float)n;
-        s.dz = dz;
-        // backward: d2 = dz w3 on active units; d1 = (W2^T d2) on active
-        // layer-1 units, each sum over j in ascending order
-        float acc1[NH];
-#pragma unroll
-        for (int c = 0; c < NH; ++c)
-            acc1[c] = 0.0f;
-        for (int j = 0; j < NH; ++j) {
-            const float d2 = ((active >> j) & 1u) ? dz * P[OFF_W3 + j] : 0.0f;
-            s.d2[j] = d2;
-#pragma unroll
-            for (int c = 0; c < NH; ++c)
-                acc1[c] = fmaf(P[OFF_W2 + j * NH + c], d2, acc1[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < NH; ++c)
-            s.d1[c] = h[c] > 0.0f ? acc1[c] : 0.0f;
+        xs[ss * XS + c] = v;
     }
-    red[threadIdx.x] = li;
     __syncthreads();
-    for (int o = MAX_BATCH / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && loss)
-        *loss = red[0] / (float)n;
-}
+    const int u0 = q * UPT;
+    SampleScratch *sc = scr + (live ? i : 0);   // dereferenced only when live
 
-__global__ __launch_bounds__(MAX_BATCH) void mlp_sample_kernel(const float *params,
-                                                               const float *x, const float *y,
-                                                               const int32_t *idx, int32_t n,
-                                                               SampleScratch *scr, float *loss)
-{
-    mlp_sample_block(params, x, y, idx, n, scr, loss);
+    // layer 1: h1 = relu(W1 x + b1)
+    {
+        float a[UPT];
+#pragma unroll
+        for (int u = 0; u < UPT; ++u)
+            a[u] = P[OFF_B1 + u0 + u];
+        for (int c = 0; c < NI; ++c) {
+            const float xv = xs[s * XS + c];
+#pragma unroll
+            for (int u = 0; u < UPT; ++u)
+                a[u] = fmaf(P[OFF_W1 + (u0 + u) * NI + c], xv, a[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const float h = fmaxf(a[u], 0.0f);
+            h1s[s * HS + u0 + u] = h;
+            if (live)
+                sc->h1[u0 + u] = h;
+        }
+    }
+    __syncthreads();
+
+    // layer 2 and the output: h2 = relu(W2 h1 + b2), z = w3 . h2 + b3
+    float g[UPT];
+    uint32_t active = 0;
+    float zp = 0.0f;
+    {
+        float a[UPT];
+#pragma unroll
+        for (int u = 0; u < UPT; ++u)
+            a[u] = P[OFF_B2 + u0 + u];
+        for (int c = 0; c < NH; ++c) {
+            const float hv = h1s[s * HS + c];
+#pragma unroll
+            for (int u = 0; u < UPT; ++u)
+                a[u] = fmaf(P[OFF_W2 + (u0 + u) * NH + c], hv, a[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            g[u] = fmaxf(a[u], 0.0f);
+            if (live)
+                sc->h2[u0 + u] = g[u];
+            active |= (uint32_t)(g[u] > 0.0f) << u;
+            zp = fmaf(P[OFF_W3 + u0 + u], g[u], zp);
+        }
+    }
+    const int quad = (threadIdx.x & 63) & ~3;   // lane of thread (s, 0)
+    float z = P[OFF_B3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        z += __shfl(zp, quad + k, 64);
+    const float yi = live ? y[idx ? idx[i] : i] : 0.0f;
+    const float li = live ? bce_with_logits(z, yi) : 0.0f;
+    const float dz = live ? (sigmoidf(z) - yi) / (float)n : 0.0f;
+    if (live && q == 0)
+        sc->dz = dz;
+
+    // backward: d2 = dz w3 on active units; d1 = (W2^T d2) on active
+    // layer-1 units, the sum over j in ascending order
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+        const float d2 = ((active >> u) & 1u) ? dz * P[OFF_W3 + u0 + u] : 0.0f;
+        d2s[s * HS + u0 + u] = d2;
+        if (live)
+            sc->d2[u0 + u] = d2;
+    }
+    __syncthreads();
+    {
+        float a[UPT];
+#pragma unroll
+        for (int u = 0; u < UPT; ++u)
+            a[u] = 0.0f;
+        for (int j = 0; j < NH; ++j) {
+            const float dv = d2s[s * HS + j];
+#pragma unroll
+            for (int u = 0; u < UPT; ++u)
+                a[u] = fmaf(P[OFF_W2 + j * NH + u0 + u], dv, a[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < UPT; ++u)
+            if (live)
+                sc->d1[u0 + u] = h1s[s * HS + u0 + u] > 0.0f ? a[u] : 0.0f;
+    }
+    if (q == 0)
+        ls[s] = li;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float sum = 0.0f;
+        for (int k = 0; k < SPB; ++k)
+            sum += ls[k];
+        part[blockIdx.x] = sum;
+    }
 }
 
 // Parameter gradients, one thread per parameter: the sum over samples
@@ -280,13 +327,22 @@ __global__ __launch_bounds__(MAX_BATCH) void mlp_sample_kernel(const float *para
 // gradient and an input (weights) or of the gradient alone (biases), into
 // grad[p].  With m != NULL also one Adam step (Kingma & Ba):
 // m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, and
-// theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+// theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).  Thread 0
+// also writes the mean loss.
 __global__ __launch_bounds__(256) void mlp_param_kernel(const SampleScratch *scr, int32_t n,
                                                         float *grad, float *params, float *m,
                                                         float *v, int64_t t, float lr,
-                                                        float beta1, float beta2, float eps)
+                                                        float beta1, float beta2, float eps,
+                                                        const float *part, float *loss)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0 && loss) {
+        // mean loss: the sample blocks' sums, added in block order
+        float sum = 0.0f;
+        for (int b = 0; b < (n + SPB - 1) / SPB; ++b)
+            sum += part[b];
+        *loss = sum / (float)n;
+    }
     if (p >= NP)
         return;
     float g = 0.0f;
@@ -481,7 +537,13 @@ int bml_standardize(float *d_x, int32_t n, const float *d_mean, const float *d_s
     return BML_OK;
 }
 
-size_t bml_mlp_scratch_bytes(void) { return sizeof(SampleScratch) * MAX_BATCH; }
+// Per-sample records, then the loss partial of every sample block.
+size_t bml_mlp_scratch_bytes(void) { return sizeof(SampleScratch) * MAX_BATCH + 64; }
+
+static float *loss_parts(void *d_scratch)
+{
+    return reinterpret_cast<float *>(static_cast<SampleScratch *>(d_scratch) + MAX_BATCH);
+}
 
 int bml_mlp_grad(const float *d_params, const float *d_x, const float *d_y, int32_t n,
                  void *d_scratch, float *d_grad, float *d_loss, void *hip_stream)
@@ -489,14 +551,14 @@ int bml_mlp_grad(const float *d_params, const float *d_x, const float *d_y, int3
     clear_error();
     if (!d_params || !d_x || !d_y || !d_scratch || !d_grad || n < 1 || n > MAX_BATCH)
         return fail(BML_EINVAL, "bml_mlp_grad: bad arguments (1 <= n <= %d)", MAX_BATCH);
-    hipLaunchKernelGGL(mlp_sample_kernel, dim3(1), dim3(MAX_BATCH), 0, (hipStream_t)hip_stream,
-                       d_params, d_x, d_y, (const int32_t *)nullptr, n,
-                       (SampleScratch *)d_scratch, d_loss);
+    hipLaunchKernelGGL(mlp_sample_kernel, dim3((n + SPB - 1) / SPB), dim3(256), 0,
+                       (hipStream_t)hip_stream, d_params, d_x, d_y, (const int32_t *)nullptr, n,
+                       (SampleScratch *)d_scratch, loss_parts(d_scratch));
     BML_HIP(hipGetLastError());
     hipLaunchKernelGGL(mlp_param_kernel, dim3((NP + 255) / 256), dim3(256), 0,
                        (hipStream_t)hip_stream, (const SampleScratch *)d_scratch, n, d_grad,
                        (float *)nullptr, (float *)nullptr, (float *)nullptr, (int64_t)0, 0.0f,
-                       0.0f, 0.0f, 0.0f);
+                       0.0f, 0.0f, 0.0f, (const float *)loss_parts(d_scratch), d_loss);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
@@ -511,12 +573,14 @@ int bml_mlp_train_step(float *d_params, float *d_m, float *d_v, float *d_grad, i
         n < 1 || n > MAX_BATCH || t < 1)
         return fail(BML_EINVAL, "bml_mlp_train_step: bad arguments (1 <= n <= %d, t >= 1)",
                     MAX_BATCH);
-    hipLaunchKernelGGL(mlp_sample_kernel, dim3(1), dim3(MAX_BATCH), 0, (hipStream_t)hip_stream,
-                       d_params, d_x, d_y, d_idx, n, (SampleScratch *)d_scratch, d_loss);
+    hipLaunchKernelGGL(mlp_sample_kernel, dim3((n + SPB - 1) / SPB), dim3(256), 0,
+                       (hipStream_t)hip_stream, d_params, d_x, d_y, d_idx, n,
+                       (SampleScratch *)d_scratch, loss_parts(d_scratch));
     BML_HIP(hipGetLastError());
     hipLaunchKernelGGL(mlp_param_kernel, dim3((NP + 255) / 256), dim3(256), 0,
                        (hipStream_t)hip_stream, (const SampleScratch *)d_scratch, n, d_grad,
-                       d_params, d_m, d_v, t, lr, beta1, beta2, eps);
+                       d_params, d_m, d_v, t, lr, beta1, beta2, eps,
+                       (const float *)loss_parts(d_scratch), d_loss);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
