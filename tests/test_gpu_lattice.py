@@ -664,6 +664,42 @@ def test_rect_large_sampled_windows(B, layout):
             (i0, j0)
 
 
+@pytest.fixture(scope="module")
+def max_lattice():
+    """The largest lattice the library takes, 65504 x 65504 (4.3 GB of byte
+    cells), initial state from the oracle."""
+    return oracle.init_cells(65504, 99, 0.3)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_maximum_size_lattice(B, layout, max_lattice):
+    """65504 x 65504 (every byte offset just below 2^32): the initial state
+    and 16 steps in the default launch shape, checked on windows at the
+    corners, the edges and inside against the oracle on padded windows;
+    counts conserved at every step and per row / column."""
+    n, steps, W = 65504, 16, 64
+    g0 = max_lattice
+    say(f"maximum size n={n} layout={layout}")
+    with make(B, n, 0.3, 99, layout, cap=steps) as lat:
+        init = lat.cells()
+        assert np.array_equal(init[:W, :W], g0[:W, :W])
+        assert np.array_equal(init[-W:, -W:], g0[-W:, -W:])
+        assert np.array_equal(init[::4097], g0[::4097])
+        del init
+        lat.step(steps)
+        got = lat.cells()
+        st = stats_array(lat.stats(0, steps))
+    assert (st[:, 0] == oracle.count(g0, 1)).all() and (st[:, 2] == oracle.count(g0, 2)).all()
+    assert np.array_equal((got == 1).sum(axis=1), (g0 == 1).sum(axis=1))
+    assert np.array_equal((got == 2).sum(axis=0), (g0 == 2).sum(axis=0))
+    picks = [(0, 0), (0, n - W), (n - W, 0), (n - W, n - W), (n // 2, n // 2), (12345, 60000)]
+    for i0, j0 in picks:
+        pad = window(g0, i0 - steps, j0 - steps, W + 2 * steps)
+        ref, _ = oracle.run(pad, steps)
+        assert np.array_equal(window(got, i0, j0, W), ref[steps:steps + W, steps:steps + W]), \
+            (i0, j0)
+
+
 def test_copy_reference_kernel(B):
     """The bandwidth reference copy moves every byte, including a tail that
     is not a multiple of the grid's stride."""
