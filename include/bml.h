@@ -124,7 +124,11 @@ int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
 /* Advance the lattice by n_steps steps (n_steps >= 0), asynchronously on the
  * handle's stream.  Each kernel pass advances every tile by up to
  * t_phases/2 steps (see bml_set_tuning).  Only the counts of the last
- * min(n_steps, stats_cap) steps of this call are kept in the ring. */
+ * min(n_steps, stats_cap) steps of this call are kept in the ring.  The
+ * step count, the current buffer of the ping-pong pair and the ring slots
+ * are kept on the host, so a call captured into a graph would replay with
+ * stale ones: to replay step sequences, use the batch API
+ * (bml_batch_capture), whose kernels read that state from device memory. */
 int bml_step(bml_lattice *L, int64_t n_steps);
 
 /* Device-to-device copy of `bytes` (a multiple of 16) from d_src to d_dst
