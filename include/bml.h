@@ -248,7 +248,9 @@ int bml_unpack(int32_t n, const uint32_t *d_planes, uint8_t *d_cells,
  * trace[(b * trace_steps + s) * 2 + 0] = LR moved, ... + 1] = TB moved, for
  * global step s < trace_steps (s counts every step the batch ran; a lattice
  * that was inactive during a step has 0 there).  Car counts are conserved;
- * bml_batch_check verifies that. */
+ * bml_batch_check verifies that.  Batches run the two-phase rule of Sec. 2
+ * on square tori (the single-lattice API covers the other rules, shapes
+ * and topologies). */
 typedef struct bml_batch bml_batch;
 
 /* Bytes of the caller-owned device arena that holds two state buffers per
