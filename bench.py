@@ -49,6 +49,26 @@ def bytes_per_cell_step(layout: int, k: int) -> float:
 
 ALU_PEAK_LANE_OPS = 256 * 4 * 64 / 4 * 2.4e9   # CUs x SIMDs x lanes / clocks per op x clock
 
+# The paper's fastest measured runs (Sec. 7, table of mean execution times:
+# rho 0.3, 1024 steps, times read as seconds), with their machines: context
+# for the numbers here, not a baseline of the same workload or hardware.
+PAPER_RUNS = [
+    ("CUDA", "GeForce GTX 1070 (1920 cores, 1.80 GHz)", 4096, 0.768),
+    ("CUDA", "GeForce GTX 1070 (1920 cores, 1.80 GHz)", 1024, 0.052),
+    ("OpenMP+SIMD, 12 cores", "Xeon E5-2603 (12 cores, 1.7 GHz)", 4096, 2.292),
+    ("OpenMP+SIMD, 4 cores", "Xeon E3-1220 (4 cores, 3.5 GHz)", 2048, 0.339),
+    ("CUDA", "Quadro K620 (384 cores, 1.12 GHz)", 4096, 5.970),
+]
+
+
+def paper_context() -> dict:
+    """The paper's runs above with GCUPS = N^2 * 1024 / t (derived)."""
+    return {"source": "arXiv:1804.07981 Sec. 7, mean execution times, rho 0.3, 1024 steps "
+                      "(seconds); GCUPS derived as N^2*1024/t",
+            "runs": [{"implementation": impl, "machine": m, "n": n, "seconds": t,
+                      "gcups": round(n * n * 1024 / t / 1e9, 2)}
+                     for impl, m, n, t in PAPER_RUNS]}
+
 
 def alu_roofline(layout: int, k: int, gcups: float, model: int = 1) -> dict:
     """Algorithmic lane-ops of the bitwise rule: 9 logic ops per 32-cell
@@ -619,6 +639,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         lt = wl.lattices[0]
         out["cpu_baseline"] = cpu_baseline(lt, model=args.model, coin_seed=args.coin_seed)
+    out["paper_context"] = paper_context()
 
     print(json.dumps(out), flush=True)
     return 0

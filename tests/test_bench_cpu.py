@@ -108,3 +108,11 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_paper_context_values():
+    """GCUPS derived from the paper's times: N^2 * 1024 steps / seconds."""
+    runs = {(r["implementation"], r["n"]): r for r in bench.paper_context()["runs"]}
+    assert runs[("CUDA", 4096)]["gcups"] == pytest.approx(4096**2 * 1024 / 0.768 / 1e9, abs=0.01)
+    assert runs[("CUDA", 4096)]["gcups"] == pytest.approx(22.37, abs=0.01)
+    assert runs[("OpenMP+SIMD, 12 cores", 4096)]["gcups"] == pytest.approx(7.50, abs=0.01)
