@@ -112,7 +112,9 @@ def test_more_than_one_gpu_is_refused():
 
 def test_paper_context_values():
     """GCUPS derived from the paper's times: N^2 * 1024 steps / seconds."""
-    runs = {(r["implementation"], r["n"]): r for r in bench.paper_context()["runs"]}
-    assert runs[("CUDA", 4096)]["gcups"] == pytest.approx(4096**2 * 1024 / 0.768 / 1e9, abs=0.01)
-    assert runs[("CUDA", 4096)]["gcups"] == pytest.approx(22.37, abs=0.01)
-    assert runs[("OpenMP+SIMD, 12 cores", 4096)]["gcups"] == pytest.approx(7.50, abs=0.01)
+    runs = {(r["machine"].split(" (")[0], r["n"]): r for r in bench.paper_context()["runs"]}
+    gtx = runs[("GeForce GTX 1070", 4096)]
+    assert gtx["gcups"] == pytest.approx(4096**2 * 1024 / 0.768 / 1e9, abs=0.01)
+    assert gtx["gcups"] == pytest.approx(22.37, abs=0.01)
+    assert runs[("Xeon E5-2603", 4096)]["gcups"] == pytest.approx(7.50, abs=0.01)
+    assert runs[("Quadro K620", 4096)]["gcups"] == pytest.approx(2.88, abs=0.01)
