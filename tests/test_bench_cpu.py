@@ -89,7 +89,7 @@ def test_committed_traffic_matches_the_kernel_source():
     """The stored counter summaries were taken on the current step-kernel
     source, so the benchmark line carries them."""
     for name, tuning in (("pass_u8_4096", (16, 16, 4)), ("pass_u8_32768", (0, 16, 4)),
-                         ("pass_u8_32768", (0, 2, 1))):
+                         ("pass_u8_32768", (0, 2, 1)), ("pass_bitplane_32768", (0, 16, 4))):
         assert bench.traffic_from_profile(name, tuning, 1.0) is not None, name
 
 
