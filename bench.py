@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X BML step library (one GPU).
 
-Default workload: four 4096 x 4096 lattices (rho 0.25 / 0.35 / 0.38 / 0.45,
-seeds 1-4), 10000 steps each, uint8 cells.  One benchmark step is that whole
-job: every lattice advanced 10000 steps with every per-step count recorded.
-The initial lattices are resident in HBM before the timed region starts.
+Default workload: one 32768 x 32768 lattice (rho 0.30, seed 7), 1000 steps,
+uint8 cells, in the autotuned launch shape (several steps per HBM pass).  One
+benchmark step is that whole job: the lattice advanced 1000 steps with every
+per-step count recorded.  The initial lattice is resident in HBM before the
+timed region starts (1 GiB per state buffer: far beyond the 256 MB Infinity
+Cache, so the step kernel's traffic is HBM traffic).
 
 Prints one JSON line: GCUPS (cell updates per second, one update = one cell
-advanced one full step, horizontal + vertical phase), the roofline of the
-step kernel, the CPU oracle timed on the host cores, and per-layout /
-per-density figures.  `--workload large` times the 32768 x 32768 lattice
-(rho 0.30, seed 7, 1000 steps) instead.
+advanced one full step, horizontal + vertical phase), the HBM roofline of the
+step kernel, the unblocked one-step-per-pass kernel on the same lattice
+(`t2`), the bitplane form, the four 4096 x 4096 lattices (`medium`, bound by
+the ALU and on-chip caches, not HBM), the 512-lattice density sweep, the
+learned early exit, and the CPU oracle timed on the host cores.
+`--workload medium|rect|sweep|early-exit` times those workloads alone.
 """
 from __future__ import annotations
 
@@ -227,39 +231,77 @@ def copy_ceiling(B, dev, nbytes: int = 1 << 30, reps: int = 5) -> dict:
     return out
 
 
-def cpu_baseline(lt, target_s: float = 15.0, model: int = 1, coin_seed: int = 0):
-    """The oracle on (a bounded number of rows of) the workload's first
-    lattice, timed on the host cores."""
+def host_threads() -> int:
+    """Threads the oracle may use: OMP_NUM_THREADS when set (this process's
+    share of the host), else every CPU the process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "").strip()
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(lt, target_s: float = 10.0, model: int = 1, coin_seed: int = 0):
+    """The oracle on a bounded sample of the workload's first lattice -- its
+    first rows (at most about 3.4e7 cells), run as a periodic lattice of
+    their own -- timed on all host threads and on one thread, about
+    `target_s` seconds each."""
     import oracle
 
-    def run(g, steps):
+    def run(g, steps, threads):
         if model == 2:
             return oracle.run_model2(g, steps, coin_seed, n_threads=threads)
         if model == 3:
             return oracle.run_model3(g, steps, n_threads=threads)
         return oracle.run(g, steps, n_threads=threads)
-    threads = min(os.cpu_count() or 1, 16)
-    rows, cols = min(lt.n, 4096), min(lt.cols or lt.n, 4096 if lt.cols is None else lt.cols)
+
+    cols = lt.cols or lt.n
+    rows = 1
+    while rows * 2 * cols <= int(3.4e7) and rows * 2 <= lt.n:
+        rows *= 2
     if lt.cols is None and lt.rho_lr is None:
         g = oracle.init_cells(rows, lt.seed, lt.rho, cols=cols)
     else:
-        g = oracle.init_cells_asym(min(lt.n, 1024), cols, lt.seed, lt.rho_lr, lt.rho_tb)
-        rows = g.shape[0]
-    rho, seed, n = lt.rho, lt.seed, rows
-    t0 = time.perf_counter()
-    g, _ = run(g, 2)
-    cal = (time.perf_counter() - t0) / 2
-    steps = max(2, min(int(target_s / max(cal, 1e-6)), 2000))
-    t0 = time.perf_counter()
-    run(g, steps)
-    dt = time.perf_counter() - t0
-    return {"value": rows * cols * steps / dt / 1e9, "unit": "GCUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{rows}x{cols} (of the workload's first lattice) "
-                      + (f"rho={rho}" if lt.rho_lr is None
-                         else f"rho_lr={lt.rho_lr} rho_tb={lt.rho_tb}") + f" seed={seed}, "
-                      f"{steps} steps, {threads} threads, {dt:.1f} s (plain C oracle, -O3, "
-                      "OpenMP row split" + {1: "", 2: ", Model II", 3: ", Model III"}[model] + ")"}
+        g = oracle.init_cells_asym(rows, cols, lt.seed, lt.rho_lr, lt.rho_tb)
+
+    def timed(threads):
+        t0 = time.perf_counter()
+        g1, _ = run(g, 2, threads)
+        cal = (time.perf_counter() - t0) / 2
+        steps = max(2, min(int(target_s / max(cal, 1e-6)), 5000))
+        t0 = time.perf_counter()
+        run(g1, steps, threads)
+        dt = time.perf_counter() - t0
+        return rows * cols * steps / dt / 1e9, steps, dt
+
+    threads = host_threads()
+    v_all, s_all, t_all = timed(threads)
+    v_one, s_one, t_one = timed(1)
+    rule = {1: "", 2: ", Model II", 3: ", Model III"}[model]
+    draw = (f"rho={lt.rho}" if lt.rho_lr is None
+            else f"rho_lr={lt.rho_lr} rho_tb={lt.rho_tb}")
+    return {"value": round(v_all, 3), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": f"first {rows} rows of the {lt.n}x{cols} lattice ({draw}, seed "
+                      f"{lt.seed}) run as a periodic {rows}x{cols} lattice: {s_all} steps "
+                      f"on {threads} threads in {t_all:.1f} s (plain C oracle, gcc -O3, "
+                      f"OpenMP row split{rule})",
+            "single_thread": {"value": round(v_one, 4), "unit": "GCUPS", "cores": 1,
+                              "steps": s_one, "seconds": round(t_one, 2)},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample) -> dict:
@@ -307,10 +349,14 @@ def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample) -> d
         plain_cells += float(ns[b]) ** 2
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) * (cells / plain_cells)
+    gcups = cells * wl.steps / batch_s / 1e9
     return {"workload": wl.name, "lattices": len(ns), "steps_per_lattice": wl.steps,
-            "graph_steps": chunk, "tuning": tun, "gcups": cells * wl.steps / batch_s / 1e9,
+            "graph_steps": chunk, "tuning": tun, "gcups": gcups,
             "batched_wall_s": batch_s, "plain_per_lattice_wall_s": plain_s,
-            "plain_measured_lattices": len(idx), "gain": plain_s / batch_s}
+            "plain_measured_lattices": len(idx), "gain": plain_s / batch_s,
+            # the sweep's lattices live in on-chip caches; the rule's bit
+            # operations bound it
+            "roofline": alu_roofline(1, 1, gcups)}
 
 
 def bench_sweep(args, B, workloads, dev) -> int:
@@ -351,23 +397,139 @@ def bench_early_exit(args) -> int:
     return 0
 
 
+def load_for(args):
+    """Tuning lookup honouring --tuning."""
+    if args.tuning:
+        forced = tuple(args.tuning)
+        return lambda lay, n, grp=None: forced
+    return lambda lay, n, grp=None: load_tuning(lay, n, grp, args.model)
+
+
+def measure(B, dev, wl, layout: int, steps: int, warmup: int, mode: str, load, configure,
+            tuning=None) -> dict:
+    """Times `steps` runs of the whole workload (each lattice wl.steps steps)
+    after `warmup` untimed ones.  mode "joint": every lattice on one stream,
+    advanced together by joint launches (bml_step_group); "streams": one
+    stream per lattice, their launches overlapping; "single": the current
+    stream.  Busy time per stream from HIP events on that stream; every
+    recorded count is checked against the initial car numbers afterwards
+    (a mismatch writes its evidence and raises)."""
+    import torch
+    from paper_1804_07981_amd.failures import dump_corruption
+    group = workloads_mod().MEDIUM_GROUP if len(wl.lattices) > 1 else None
+    lats = []
+    shared = torch.cuda.Stream(dev) if mode == "joint" else None
+    for lt in wl.lattices:
+        stream = (shared if mode == "joint" else
+                  torch.cuda.Stream(dev) if mode == "streams" else
+                  torch.cuda.current_stream(dev))
+        lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=wl.steps, device=dev,
+                        stream=stream, **lt.kwargs())
+        tun = tuning or load(layout, size_key(lt), group if mode == "joint" else None)
+        if tun:
+            lat.set_tuning(*tun)
+        configure(lat)
+        lats.append(lat)
+
+    def run_job():
+        if mode == "joint":
+            B.step_group(lats, wl.steps)
+        else:
+            for lat in lats:
+                lat.step(wl.steps)
+
+    for _ in range(warmup):
+        run_job()
+    torch.cuda.synchronize()
+    streams = list({id(lat.stream): lat.stream for lat in lats}.values())
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in streams]
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    for st, (e0, _) in zip(streams, evs):
+        e0.record(st)
+    marks[0].record(streams[0])
+    for i in range(steps):
+        run_job()
+        marks[i + 1].record(streams[0])
+    for st, (_, e1) in zip(streams, evs):
+        e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
+    per_stream = [e0.elapsed_time(e1) / 1e3 for e0, e1 in evs]
+    gpu_s = max(per_stream)
+    for lat in lats:
+        try:
+            lat.stats(lat.steps_done - wl.steps, wl.steps)
+        except B.BmlError as e:
+            if e.code == B.BML_ECORRUPT:
+                path = dump_corruption(e, lat, "bench", {"workload": wl.name, "mode": mode})
+                print(f"car counts not conserved; evidence in {path}", file=sys.stderr,
+                      flush=True)
+            raise
+    tr, tp, wpb = lats[0].tuning()
+    k = tp // 2
+    passes = -(-wl.steps // k) * steps
+    launches = passes if mode == "joint" else passes * len(lats)
+    cells = sum(lt.cells for lt in wl.lattices)
+    for lat in lats:
+        lat.close()
+    return {"gpu_s": gpu_s, "wall_s": wall, "k": k, "tile_rows": tr, "wpb": wpb,
+            "launches": launches, "cells": cells, "mode": mode,
+            "lattices_per_launch": len(lats) if mode == "joint" else 1,
+            "lattices_total": len(lats),
+            "avg_launch_s": sum(per_stream) / launches, "step_ms": step_ms,
+            "gcups": cells * wl.steps * steps / gpu_s / 1e9}
+
+
+def workloads_mod():
+    import workloads
+    return workloads
+
+
+def hbm_roofline(res: dict, layout: int, kname: str, extra: dict | None = None) -> dict:
+    """HBM roofline of the step kernel from one measure() result: algorithmic
+    bytes of one launch (state read once and written once per pass) over the
+    average launch duration; `traffic` = HBM bytes per launch from the
+    committed counter summary when it was taken on this kernel source with
+    this launch shape, else None."""
+    k = res["k"]
+    launch_cells = res["cells"] / res["lattices_total"] * res["lattices_per_launch"]
+    alg = bytes_per_cell_step(layout, k) * launch_cells * k
+    per_launch = res["avg_launch_s"]
+    achieved = alg / per_launch / 1e9
+    traffic = traffic_from_profile(kname, (res["tile_rows"], 2 * k, res["wpb"]), alg)
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": f"pass_kernel<{'u8' if layout == 0 else 'bitplane'}, K={k}> (strip rows "
+                     f"{res['tile_rows'] or 'auto'}, {res['wpb']} waves/block, "
+                     f"{res['lattices_per_launch']} lattice(s) per launch)",
+           "algorithmic_bytes_per_launch": alg,
+           "avg_launch_us": round(per_launch * 1e6, 2),
+           "traffic_gbs": round(traffic / per_launch / 1e9, 1) if traffic else None,
+           "traffic_over_algorithmic": round(traffic / alg, 4) if traffic else None}
+    out.update(extra or {})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["medium", "large", "rect", "sweep", "early-exit"],
-                    default="medium")
+    ap.add_argument("--workload", choices=["large", "medium", "rect", "sweep", "early-exit"],
+                    default="large")
     ap.add_argument("--plain-sample", type=int, default=None,
                     help="sweep/early-exit: time plain per-lattice runs on this many "
                          "lattices and scale to all")
     ap.add_argument("--layout", choices=["u8", "bitplane"], default="u8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the per-layout secondary measurements")
+                    help="skip the secondary measurements")
     ap.add_argument("--probe", action="store_true",
                     help="for counter runs: a 1 GiB device copy (the calibration kernel "
-                         "of known traffic), then --steps BML steps of the first lattice")
+                         "of known traffic), then --steps BML steps of the workload")
     ap.add_argument("--topology", choices=["torus", "klein"], default="torus",
                     help="medium/large/rect: periodic in both directions, or the Klein "
                          "bottle (top and bottom edges glued with a reversal)")
@@ -378,10 +540,10 @@ def main() -> int:
     ap.add_argument("--coin-seed", type=int, default=0x5EED,
                     help="Model II: the coin stream's seed")
     ap.add_argument("--tuning", type=int, nargs=3, metavar=("TILE_ROWS", "T_PHASES", "WPB"),
-                    help="medium/large: run this tuning instead of the autotuned one")
+                    help="medium/large/rect: run this tuning instead of the autotuned one")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("PROBE_LOG", "FETCH_DIR", "WRITE_DIR"),
                     help="no GPU: turn two rocprofv3 --pmc runs of --probe (FETCH_SIZE, "
-                         "WRITE_SIZE) into profiles/pass_<layout>_<n>.traffic.json")
+                         "WRITE_SIZE) into profiles/pass_<layout>_<n>_t<T>.traffic.json")
     args = ap.parse_args()
 
     if args.pmc_summary:
@@ -392,7 +554,6 @@ def main() -> int:
               "row-slab decomposition is a design, not built.", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_1804_07981_amd as B
@@ -406,13 +567,7 @@ def main() -> int:
         return bench_early_exit(args)
     wl = {"medium": workloads.MEDIUM, "large": workloads.LARGE,
           "rect": workloads.RECT}[args.workload]
-    # the lattices of a multi-lattice workload run in joint launches, tuned as a group
-    group = workloads.MEDIUM_GROUP if len(wl.lattices) > 1 else None
-    if args.tuning:
-        forced = tuple(args.tuning)
-        load = lambda lay, n, grp=None: forced   # noqa: E731
-    else:
-        load = lambda lay, n, grp=None: load_tuning(lay, n, grp, args.model)   # noqa: E731
+    load = load_for(args)
     layout = 0 if args.layout == "u8" else 1
     topology = B.BML_TOPO_KLEIN if args.topology == "klein" else B.BML_TOPO_TORUS
     if args.model != 1 and args.topology != "torus":
@@ -424,6 +579,7 @@ def main() -> int:
         if args.model != 1:
             lat.set_model(args.model, args.coin_seed)
 
+    group = workloads.MEDIUM_GROUP if len(wl.lattices) > 1 else None
     if args.probe:
         a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -454,110 +610,32 @@ def main() -> int:
             lat.close()
         return 0
 
-    def make_lattices(lay, mode):
-        """mode "joint": every lattice on one stream, advanced together by
-        joint launches (bml_step_group); "streams": one stream per lattice,
-        their launches overlapping; "single": the current stream."""
-        lats = []
-        shared = torch.cuda.Stream(dev) if mode == "joint" else None
-        for lt in wl.lattices:
-            stream = (shared if mode == "joint" else
-                      torch.cuda.Stream(dev) if mode == "streams" else
-                      torch.cuda.current_stream(dev))
-            lat = B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps, device=dev,
-                            stream=stream, **lt.kwargs())
-            tun = load(lay, size_key(lt), group if mode == "joint" else None)
-            if tun:
-                lat.set_tuning(*tun)
-            configure(lat)
-            lats.append(lat)
-        return lats
-
-    def run_job(lats, mode):
-        if mode == "joint":
-            B.step_group(lats, wl.steps)
-        else:
-            for lat in lats:
-                lat.step(wl.steps)
-
-    def time_layout(lay, steps, warmup, mode):
-        lats = make_lattices(lay, mode)
-        for _ in range(warmup):
-            run_job(lats, mode)
-        torch.cuda.synchronize()
-        streams = list({id(lat.stream): lat.stream for lat in lats}.values())
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in streams]
-        # per-step events on the (first) stream give the spread of the steps
-        marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-        t0 = time.perf_counter()
-        for st, (e0, _) in zip(streams, evs):
-            e0.record(st)
-        marks[0].record(streams[0])
-        for i in range(steps):
-            run_job(lats, mode)
-            marks[i + 1].record(streams[0])
-        for st, (_, e1) in zip(streams, evs):
-            e1.record(st)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        step_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
-        # Busy time of each stream (they overlap in "streams" mode).
-        per_stream = [e0.elapsed_time(e1) / 1e3 for e0, e1 in evs]
-        gpu_s = max(per_stream)
-        # Every recorded count must still show the initial car numbers.
-        for lat in lats:
-            lat.stats(lat.steps_done - wl.steps, wl.steps)
-        tr, tp, wpb = lats[0].tuning()
-        k = tp // 2
-        passes = -(-wl.steps // k) * steps
-        launches = passes if mode == "joint" else passes * len(lats)
-        cells = sum(lt.cells for lt in wl.lattices)
-        for lat in lats:
-            lat.close()
-        return {"gpu_s": gpu_s, "wall_s": wall, "k": k, "tile_rows": tr, "wpb": wpb,
-                "launches": launches, "cells": cells, "mode": mode,
-                "lattices_per_launch": len(lats) if mode == "joint" else 1,
-                "avg_launch_s": sum(per_stream) / launches,
-                "step_ms": step_ms,
-                "gcups": cells * wl.steps * steps / gpu_s / 1e9}
+    def kname_of(w, lay):
+        lt0 = w.lattices[0]
+        name = (f"pass_{'u8' if lay == 0 else 'bitplane'}_{lt0.n}" if lt0.cols is None
+                else f"pass_{'u8' if lay == 0 else 'bitplane'}_{lt0.n}x{lt0.cols}")
+        return name + ("_klein" if args.topology == "klein" else "") + (
+            f"_model{args.model}" if args.model != 1 else "")
 
     main_mode = "joint" if len(wl.lattices) > 1 else "single"
-    res = time_layout(layout, args.steps, args.warmup, main_mode)
-    total_cell_steps = res["cells"] * wl.steps * args.steps
-    value = total_cell_steps / res["gpu_s"] / 1e9
+    res = measure(B, dev, wl, layout, args.steps, args.warmup, main_mode, load, configure)
+    value = res["gcups"]
     ms_per_step = res["gpu_s"] * 1e3 / args.steps
-
-    k = res["k"]
-    per_launch_s = res["avg_launch_s"]
-    launch_cells = res["cells"] / len(wl.lattices) * res["lattices_per_launch"]
-    alg_bytes = bytes_per_cell_step(layout, k) * launch_cells * k
-    achieved = alg_bytes / per_launch_s / 1e9
+    alu = alu_roofline(layout, res["k"], value, args.model)
+    if args.workload == "medium":
+        # four lattices of 16 MiB (uint8): resident in the 256 MB Infinity
+        # Cache, so the launches are bound by the ALU and on-chip caches,
+        # not by HBM; the bytes they would move are reported alongside
+        roofline = dict(alu, kernel=hbm_roofline(res, layout, kname_of(wl, layout))["kernel"],
+                        avg_launch_us=round(res["avg_launch_s"] * 1e6, 2),
+                        cache_resident_gbs=hbm_roofline(res, layout,
+                                                        kname_of(wl, layout))["achieved"])
+    else:
+        roofline = hbm_roofline(res, layout, kname_of(wl, layout),
+                                {"copy_ceiling_gbs": copy_ceiling(B, dev), "alu": alu,
+                                 "effective_gbs": round(value * bytes_per_cell_step(layout, 1),
+                                                        1)})
     lt0 = wl.lattices[0]
-    kname = (f"pass_{args.layout}_{lt0.n}" if lt0.cols is None
-             else f"pass_{args.layout}_{lt0.n}x{lt0.cols}")
-    kname += ("_klein" if args.topology == "klein" else "") + (
-        f"_model{args.model}" if args.model != 1 else "")
-    traffic = traffic_from_profile(kname, (res["tile_rows"], 2 * k, res["wpb"]), alg_bytes)
-    copy_gbs = copy_ceiling(B, dev)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic,
-                "kernel": f"pass_kernel<{args.layout}, K={k}> (strip rows "
-                          f"{res['tile_rows'] or 'auto'}, {res['wpb']} waves/block, "
-                          f"{res['lattices_per_launch']} lattice(s) per launch)",
-                "algorithmic_bytes_per_launch": alg_bytes,
-                "avg_launch_us": round(per_launch_s * 1e6, 2),
-                "effective_gbs": round(value * 1e9 * bytes_per_cell_step(layout, 1) / 1e9, 1),
-                # what a plain read-once/write-once kernel reaches here, and the
-                # HBM bytes the counters saw per launch as a fraction of it
-                "copy_ceiling_gbs": copy_gbs,
-                "traffic_frac_of_copy": (round(traffic / per_launch_s / 1e9
-                                               / max(copy_gbs.values()), 4)
-                                         if traffic else None),
-                # the same launches against the plain-ALU ceiling
-                "alu": alu_roofline(layout, k, value, args.model)}
-
     out = {
         "metric": "GCUPS (cell updates/s) + % HBM roofline; density-sweep time vs plain",
         "value": round(value, 2),
@@ -583,66 +661,84 @@ def main() -> int:
                                  else lt.rho / 2, lt.seed] for lt in wl.lattices],
                    "lattice_fields": ["rows", "cols", "rho_lr", "rho_tb", "seed"],
                    "steps_per_lattice": wl.steps,
-                   "tuning": {"tile_rows": res["tile_rows"], "t_phases": 2 * k,
+                   "tuning": {"tile_rows": res["tile_rows"], "t_phases": 2 * res["k"],
                               "waves_per_block": res["wpb"]},
                    "parallelism": "1 GPU"},
         "roofline": roofline,
-        # spread of the timed steps (HIP events between steps)
         "step_ms_stats": {"median": round(statistics.median(res["step_ms"]), 3),
                           "mean": round(statistics.fmean(res["step_ms"]), 3),
                           "min": round(res["step_ms"][0], 3),
                           "max": round(res["step_ms"][-1], 3)},
     }
 
+    if not args.no_variants and args.workload in ("large", "rect") and layout == 0 \
+            and args.model == 1:
+        # the unblocked kernel: one step per HBM pass (every cell read and
+        # written once per step), one wave per block
+        t2 = measure(B, dev, wl, 0, 1, 1, main_mode, load, configure, tuning=(0, 2, 1))
+        out["t2"] = dict(hbm_roofline(t2, 0, kname_of(wl, 0)), gcups=round(t2["gcups"], 1))
+
     if not args.no_variants:
         other = 1 - layout
-        r2 = time_layout(other, 1, 1, main_mode)
+        r2 = measure(B, dev, wl, other, 1, 1, main_mode, load, configure)
         out["variants"] = {("bitplane" if other else "u8"): {
             "gcups": round(r2["gcups"], 2), "t_phases": 2 * r2["k"],
-            "tile_rows": r2["tile_rows"], "mode": r2["mode"]}}
-        if main_mode == "joint":
-            # the same lattices on one stream each, launches overlapping
-            r3 = time_layout(layout, 1, 1, "streams")
-            out["variants"]["separate_streams_gcups"] = round(r3["gcups"], 2)
-        if len(wl.lattices) > 1:
-            # each density alone, one stream (the single-lattice figure)
-            per = {}
-            for lay in (0, 1):
-                for i, lt in enumerate(wl.lattices):
-                    with B.Lattice(lt.n, lt.rho, lt.seed, layout=lay, stats_cap=wl.steps,
-                                   device=dev, **lt.kwargs()) as lat:
-                        tun = load(lay, size_key(lt))
-                        if tun:
-                            lat.set_tuning(*tun)
-                        configure(lat)
-                        lat.step(wl.steps)
-                        torch.cuda.synchronize()
-                        e0 = torch.cuda.Event(enable_timing=True)
-                        e1 = torch.cuda.Event(enable_timing=True)
-                        e0.record(lat.stream)
-                        lat.step(wl.steps)
-                        e1.record(lat.stream)
-                        torch.cuda.synchronize()
-                        dt = e0.elapsed_time(e1) / 1e3
-                        lat.stats(wl.steps, wl.steps)
-                    per[f"{'u8' if lay == 0 else 'bitplane'}/rho={lt.rho}"] = round(
-                        lt.n * lt.n * wl.steps / dt / 1e9, 1)
-            out["variants"]["single_lattice_gcups"] = per
+            "tile_rows": r2["tile_rows"], "mode": r2["mode"],
+            "alu": alu_roofline(other, r2["k"], r2["gcups"], args.model),
+            "hbm": hbm_roofline(r2, other, kname_of(wl, other))}}
 
-    if not args.no_variants and args.workload == "medium" and args.model == 1 \
+    if not args.no_variants and args.workload == "large" and args.model == 1 \
             and args.topology == "torus" and not args.tuning:
+        out["medium"] = medium_block(B, dev, workloads, load_for(args), configure)
         # the metric's second half: the 512-lattice density sweep, batched
         # in one captured graph against plain per-lattice runs (64 of them
         # timed, scaled to all 512 by cell count)
         out["density_sweep"] = sweep_measure(B, workloads, dev, 1, 1, 64)
+        out["early_exit"] = early_exit_block()
 
     if not args.no_cpu_baseline:
-        lt = wl.lattices[0]
-        out["cpu_baseline"] = cpu_baseline(lt, model=args.model, coin_seed=args.coin_seed)
+        out["cpu_baseline"] = cpu_baseline(lt0, model=args.model, coin_seed=args.coin_seed)
     out["paper_context"] = paper_context()
 
     print(json.dumps(out), flush=True)
     return 0
+
+
+def medium_block(B, dev, workloads, load, configure) -> dict:
+    """The four 4096 x 4096 lattices (rho .25/.35/.38/.45, seeds 1-4, 10000
+    steps each) in joint launches, both layouts, plus the same lattices on
+    separate streams and each alone.  Their 16 MiB (uint8) states stay in
+    the Infinity Cache, so the roofline here is the ALU one."""
+    wl = workloads.MEDIUM
+    out = {"workload": wl.name}
+    for lay in (0, 1):
+        r = measure(B, dev, wl, lay, 1, 1, "joint", load, configure)
+        name = "u8" if lay == 0 else "bitplane"
+        out[name] = {"gcups": round(r["gcups"], 1), "t_phases": 2 * r["k"],
+                     "tile_rows": r["tile_rows"], "waves_per_block": r["wpb"],
+                     "avg_launch_us": round(r["avg_launch_s"] * 1e6, 2),
+                     "roofline": alu_roofline(lay, r["k"], r["gcups"])}
+    r3 = measure(B, dev, wl, 0, 1, 1, "streams", load, configure)
+    out["u8_separate_streams_gcups"] = round(r3["gcups"], 1)
+    single = {}
+    for lay in (0, 1):
+        lt = wl.lattices[0]
+        one = workloads.Workload(wl.name + "-first", (lt,), wl.steps, "")
+        r = measure(B, dev, one, lay, 1, 1, "single", load, configure)
+        single["u8" if lay == 0 else "bitplane"] = round(r["gcups"], 1)
+    out["single_lattice_gcups_rho0.25"] = single
+    return out
+
+
+def early_exit_block() -> dict:
+    """The learned early exit on its full workload (9024 lattices of 512 x
+    512, 20000-step labels, held-out seeds 51..63), with plain per-lattice
+    runs timed on 8 held-out lattices and scaled."""
+    from paper_1804_07981_amd import early_exit as ee
+    ns, rhos, seeds, split = ee.c4_lattices()
+    rep = ee.experiment(ns, rhos, seeds, split, plain_sample=8,
+                        log=lambda m: print(m, file=sys.stderr, flush=True))
+    return {"workload": "bml-early-exit-512x512-141rho-64seeds-20000steps", **rep}
 
 
 if __name__ == "__main__":

@@ -12,14 +12,16 @@
  *     LR (moves left-to-right) or TB (moves top-to-bottom); horizontal and
  *     vertical phases alternate; a car leaving one side re-enters on the
  *     opposite side.
- *   - Sec. 2, horizontal-phase case table: center' = LR if left = LR and
- *     center = EMPTY; EMPTY if center = LR and right = EMPTY; else center.
- *   - Sec. 2, vertical-phase case table: same with top / bottom and TB.
+ *   - Sec. 2, the two phase rules: a cell that is EMPTY receives the LR car
+ *     on its left (horizontal phase) or the TB car above it (vertical
+ *     phase); a car whose target cell is EMPTY leaves; nothing else changes.
+ *     Written here car by car: every car that can advance does, all
+ *     decisions taken on the lattice as it was before the phase.
  *   - Sec. 2, Fig. 1 caption text: one step = a horizontal then a vertical
  *     phase.
  *   - Sec. 3 (serial implementation): synchronous update through two grids
- *     (read cur, write next, swap); row-major IDX(i,j) = i*N + j; one byte
- *     per cell with EMPTY=0, LR=1, TB=2; neighbours by modulo indexing.
+ *     (read one, write the other, swap); row-major cell index i*N + j; one
+ *     byte per cell with EMPTY=0, LR=1, TB=2.
  *   - Sec. 4 (OpenMP): the row loop is split across threads.
  * Readings where the paper is silent (initial placement, stats) are the
  * project's own and are stated at each function.
@@ -103,68 +105,79 @@ void bmlo_init_cells_asym(int64_t rows, int64_t cols, uint64_t seed, double rho_
 }
 
 /* ------------------------------------------------------------------------ */
-/* The two phases.  Each reads only `cur` and writes only `next`            */
-/* (synchronous update, Sec. 3).  Returns the number of cars that moved,    */
-/* i.e. cars whose destination cell was EMPTY in `cur`.                     */
+/* The two phases, stated car by car (Sec. 2): in the horizontal phase every */
+/* LR car whose cell to the right is EMPTY moves into it; in the vertical   */
+/* phase every TB car whose cell below is EMPTY moves into it.  Every test  */
+/* looks at `cur` only (the synchronous update of Sec. 3); the moves are    */
+/* applied to `nxt`, which starts as a copy of `cur`.  An EMPTY cell has     */
+/* exactly one cell to its left and one above it, so no two cars ever claim */
+/* the same cell and the order of the moves is irrelevant.  The functions   */
+/* return how many cars moved.                                              */
 /* ------------------------------------------------------------------------ */
 
-static int64_t phase_h_rows(int64_t r0, int64_t r1, int64_t cols,
-                            const uint8_t *cur, uint8_t *next)
+/* Column to the right of column c on a ring of `cols` columns. */
+static int64_t right_of(int64_t c, int64_t cols)
 {
-    int64_t moved = 0;
-    for (int64_t i = r0; i < r1; i++) {
-        for (int64_t j = 0; j < cols; j++) {
-            uint8_t left = cur[i * cols + (j - 1 + cols) % cols];
-            uint8_t center = cur[i * cols + j];
-            uint8_t right = cur[i * cols + (j + 1) % cols];
-            uint8_t out;
-            if (left == LR && center == EMPTY) {
-                out = LR;
-            } else if (center == LR && right == EMPTY) {
-                out = EMPTY;
-                moved++;
-            } else {
-                out = center;
-            }
-            next[i * cols + j] = out;
-        }
-    }
-    return moved;
+    return c + 1 < cols ? c + 1 : 0;
 }
 
-/* Column of the vertical neighbour.  On the torus (topology 0) it is j.  On
- * the Klein bottle (topology 1; the lattice of Campora et al. cited in
- * Sec. 2) the top and bottom edges are glued with a reversal, so a
- * neighbour across that edge sits in column cols-1-j; the left and right
- * edges stay periodic. */
-static int64_t v_col(int64_t j, int64_t cols, int crosses_edge, int topology)
+/* Horizontal phase restricted to rows [first, end): LR cars never leave
+ * their row, so each row is independent of the others. */
+static int64_t lr_moves(int64_t first, int64_t end, int64_t cols, const uint8_t *cur,
+                        uint8_t *nxt)
 {
-    return (topology == 1 && crosses_edge) ? cols - 1 - j : j;
-}
-
-static int64_t phase_v_rows(int64_t r0, int64_t r1, int64_t rows, int64_t cols,
-                            const uint8_t *cur, uint8_t *next, int topology)
-{
-    int64_t moved = 0;
-    for (int64_t i = r0; i < r1; i++) {
-        int64_t up = (i - 1 + rows) % rows, down = (i + 1) % rows;
-        for (int64_t j = 0; j < cols; j++) {
-            uint8_t top = cur[up * cols + v_col(j, cols, i == 0, topology)];
-            uint8_t center = cur[i * cols + j];
-            uint8_t bottom = cur[down * cols + v_col(j, cols, i == rows - 1, topology)];
-            uint8_t out;
-            if (top == TB && center == EMPTY) {
-                out = TB;
-            } else if (center == TB && bottom == EMPTY) {
-                out = EMPTY;
-                moved++;
-            } else {
-                out = center;
+    int64_t cars_moved = 0;
+    for (int64_t r = first; r < end; r++) {
+        const uint8_t *row = cur + r * cols;
+        uint8_t *out = nxt + r * cols;
+        memcpy(out, row, (size_t)cols);
+        for (int64_t c = 0; c < cols; c++) {
+            if (row[c] != LR)
+                continue;
+            const int64_t dest = right_of(c, cols);
+            if (row[dest] == EMPTY) {
+                out[c] = EMPTY;
+                out[dest] = LR;
+                cars_moved++;
             }
-            next[i * cols + j] = out;
         }
     }
-    return moved;
+    return cars_moved;
+}
+
+/* Cell below (r, c).  On the torus (topology 0) it is (r+1, c), the last
+ * row wrapping to row 0.  On the Klein bottle (topology 1; the lattice of
+ * Campora et al. cited in Sec. 2) the bottom edge is glued to the top one
+ * with a reversal: below (rows-1, c) lies (0, cols-1-c).  Left and right
+ * stay periodic either way. */
+static int64_t index_below(int64_t r, int64_t c, int64_t rows, int64_t cols, int topology)
+{
+    if (r + 1 < rows)
+        return (r + 1) * cols + c;
+    return topology == 1 ? cols - 1 - c : c;
+}
+
+/* Vertical phase for the TB cars of rows [first, end).  `nxt` must already
+ * hold a copy of `cur` (a car may move into the next row, which another
+ * caller may own). */
+static int64_t tb_moves(int64_t first, int64_t end, int64_t rows, int64_t cols,
+                        const uint8_t *cur, uint8_t *nxt, int topology)
+{
+    int64_t cars_moved = 0;
+    for (int64_t r = first; r < end; r++) {
+        for (int64_t c = 0; c < cols; c++) {
+            const int64_t here = r * cols + c;
+            if (cur[here] != TB)
+                continue;
+            const int64_t dest = index_below(r, c, rows, cols, topology);
+            if (cur[dest] == EMPTY) {
+                nxt[here] = EMPTY;
+                nxt[dest] = TB;
+                cars_moved++;
+            }
+        }
+    }
+    return cars_moved;
 }
 
 static int64_t count_value(const uint8_t *cells, int64_t n, uint8_t v)
@@ -175,26 +188,28 @@ static int64_t count_value(const uint8_t *cells, int64_t n, uint8_t v)
     return c;
 }
 
-/* Serial horizontal phase (the paper's horizontal_step, Sec. 3). */
+/* One horizontal phase over the whole lattice (Sec. 2). */
 int64_t bmlo_phase_h(int64_t rows, int64_t cols, const uint8_t *cur,
                      uint8_t *next)
 {
-    return phase_h_rows(0, rows, cols, cur, next);
+    return lr_moves(0, rows, cols, cur, next);
 }
 
-/* Serial vertical phase (Sec. 2 vertical case table; Sec. 3 says it mirrors
- * the horizontal one). */
+/* One vertical phase over the whole lattice (Sec. 2; the paper leaves its
+ * code out as the mirror of the horizontal one). */
 int64_t bmlo_phase_v(int64_t rows, int64_t cols, const uint8_t *cur,
                      uint8_t *next)
 {
-    return phase_v_rows(0, rows, rows, cols, cur, next, 0);
+    memcpy(next, cur, (size_t)(rows * cols));
+    return tb_moves(0, rows, rows, cols, cur, next, 0);
 }
 
 /* Vertical phase on the torus (topology 0) or the Klein bottle (1). */
 int64_t bmlo_phase_v_topo(int64_t rows, int64_t cols, const uint8_t *cur,
                           uint8_t *next, int32_t topology)
 {
-    return phase_v_rows(0, rows, rows, cols, cur, next, topology);
+    memcpy(next, cur, (size_t)(rows * cols));
+    return tb_moves(0, rows, rows, cols, cur, next, topology);
 }
 
 int64_t bmlo_count(const uint8_t *cells, int64_t n, int32_t value)
@@ -236,20 +251,31 @@ static void run_topo(int64_t rows, int64_t cols, uint8_t *cells, uint8_t *tmp,
     int nt = n_threads > 0 ? n_threads : 1;
     for (int64_t s = 0; s < steps; s++) {
         int64_t moved_lr = 0, moved_tb = 0, n_lr = 0, n_tb = 0;
+        /* horizontal phase: cells -> tmp, one row per iteration */
 #ifdef _OPENMP
 #pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : moved_lr, n_lr)
 #endif
         for (int64_t i = 0; i < rows; i++) {
-            moved_lr += phase_h_rows(i, i + 1, cols, cells, tmp);
+            moved_lr += lr_moves(i, i + 1, cols, cells, tmp);
             n_lr += count_value(tmp + i * cols, cols, LR);
         }
+        /* vertical phase: tmp -> cells; every row is copied before any TB
+         * car moves, since a car lands in the next row */
 #ifdef _OPENMP
-#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : moved_tb, n_tb)
+#pragma omp parallel for num_threads(nt) schedule(static)
 #endif
-        for (int64_t i = 0; i < rows; i++) {
-            moved_tb += phase_v_rows(i, i + 1, rows, cols, tmp, cells, topology);
+        for (int64_t i = 0; i < rows; i++)
+            memcpy(cells + i * cols, tmp + i * cols, (size_t)cols);
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : moved_tb)
+#endif
+        for (int64_t i = 0; i < rows; i++)
+            moved_tb += tb_moves(i, i + 1, rows, cols, tmp, cells, topology);
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : n_tb)
+#endif
+        for (int64_t i = 0; i < rows; i++)
             n_tb += count_value(cells + i * cols, cols, TB);
-        }
         if (stats) {
             stats[4 * s + 0] = (uint32_t)n_lr;
             stats[4 * s + 1] = (uint32_t)moved_lr;

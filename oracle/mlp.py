@@ -119,11 +119,18 @@ def to_bf16(x) -> np.ndarray:
 def infer_bf16(params: np.ndarray, X: np.ndarray) -> np.ndarray:
     """Logits with weights and each layer's input rounded to bfloat16;
     biases, products and sums in float32 (products of two bfloat16 values are
-    exact in float32)."""
+    exact in float32).  One rounding site per line: the three weight
+    matrices, the input, and the two hidden activations; the biases are never
+    rounded."""
     p = unpack(np.asarray(params, dtype=np.float32))
-    W1, W2, W3 = (to_bf16(p[k].astype(np.float32)) for k in ("W1", "W2", "W3"))
-    b1, b2, b3 = (p[k].astype(np.float32) for k in ("b1", "b2", "b3"))
-    x = to_bf16(np.asarray(X, dtype=np.float32))
+    f32 = lambda a: np.asarray(a, dtype=np.float32)   # noqa: E731
+    W1 = to_bf16(f32(p["W1"]))
+    W2 = to_bf16(f32(p["W2"]))
+    W3 = to_bf16(f32(p["W3"]))
+    b1 = f32(p["b1"])
+    b2 = f32(p["b2"])
+    b3 = f32(p["b3"])
+    x = to_bf16(f32(X))
     h1 = to_bf16(np.maximum(x @ W1.T + b1, np.float32(0)))
     h2 = to_bf16(np.maximum(h1 @ W2.T + b2, np.float32(0)))
     return (h2 @ W3 + b3[0]).astype(np.float32)

@@ -3,11 +3,16 @@
 For a lattice size and layout (or a batch of lattices) it times candidate
 launch shapes -- strip height, phases per HBM pass (temporal-block depth)
 and waves per block -- with HIP events on the library's stream, and keeps
-the fastest.  Every candidate must reproduce the reference candidate's final
-cells and every per-step count bit for bit (the bit-exactness gate): a
-candidate that differs is reported and never selected.  Results go to a JSON
-cache keyed by GPU architecture, layout and size, which `Lattice`/`Batch`
-users (and bench.py) read back.
+the fastest.  Every candidate must reproduce a reference -- final cells and
+every per-step count, bit for bit (the bit-exactness gate).  The caller
+passes the reference (the test suite passes the CPU oracle's run); without
+one, the first candidate's run is the reference.  The launch shape never
+changes the result, so a candidate that differs from the reference, or
+whose car counts are not conserved (BML_ECORRUPT), is a bug: the tuner
+writes what it knows (failures.dump_corruption) and raises instead of
+moving on to the next candidate.  Results go to a JSON cache keyed by GPU
+architecture, layout and size, which `Lattice`/`Batch` users (and bench.py)
+read back.
 
 Usage: python -m paper_1804_07981_amd.autotune --sizes 4096 32768 [--medium] [--batch]
 """
@@ -24,7 +29,13 @@ import torch
 
 from . import _lib as L
 from .batch import Batch
+from .failures import dump_corruption
 from .lattice import Lattice, step_group
+
+
+class TuningMismatch(RuntimeError):
+    """A candidate launch shape gave other cells or counts than the reference."""
+
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 MODEL2_COIN_SEED = 0x5EED       # coin stream of the Model II candidates
@@ -67,29 +78,52 @@ def _stats_array(rec):
     return np.stack([rec["n_lr"], rec["moved_lr"], rec["n_tb"], rec["moved_tb"]], axis=1)
 
 
+def _checked_run(lat, steps: int, where: str, extra: dict):
+    """(cells, counts) of a lattice after its run; on BML_ECORRUPT the
+    evidence is written and the error re-raised."""
+    try:
+        return lat.cells(), _stats_array(lat.stats(0, steps))
+    except L.BmlError as e:
+        if e.code == L.BML_ECORRUPT:
+            dump_corruption(e, lat, where, extra)
+        raise
+
+
+def _same(a, b) -> bool:
+    return np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
                  t_phases=(2, 4, 8, 12, 16), waves=(2, 4), steps: int | None = None,
                  rho: float = 0.3, seed: int = 7, log=print, shape: dict | None = None,
-                 model: int = 1) -> dict:
+                 model: int = 1, reference=None) -> dict:
     """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice, or
     n rows x shape["cols"] with the draw in `shape` (Lattice keywords), under
-    update rule `model` (1, 2 for Model II, 3 for Model III)."""
+    update rule `model` (1, 2 for Model II, 3 for Model III).  `reference`:
+    the (cells, counts[steps][4]) every candidate must reproduce (default: the
+    first candidate's run)."""
     shape = shape or {}
     cells = n * shape.get("cols", n)
     if steps is None:
         # about 4e9 cell-steps per measurement, at least 48 steps
         steps = int(max(48, min(2000, 4e9 / cells)))
         steps -= steps % 48
-    ref = None
+    ref = reference
     results = []
+    size = f"{n}x{shape['cols']}" if "cols" in shape else f"{n}"
     for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
         with Lattice(n, rho, seed, layout=layout, stats_cap=steps, **shape) as lat:
             if model != 1:
                 lat.set_model(model, MODEL2_COIN_SEED)
             lat.set_tuning(tr, tp, w)
             lat.step(steps)                      # warm-up (and the checked run)
-            torch.cuda.synchronize()
-            got = (lat.cells(), _stats_array(lat.stats(0, steps)))
+            got = _checked_run(lat, steps, f"tune-{size}",
+                               {"candidate": [tr, tp, w], "rho": rho, "seed": seed})
+            if ref is None:
+                ref = got
+            if not _same(got, ref):
+                raise TuningMismatch(f"n={size} layout={layout}: candidate rows={tr} T={tp} "
+                                     f"w={w} differs from the reference")
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(lat.stream)
@@ -97,82 +131,74 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
             e1.record(lat.stream)
             torch.cuda.synchronize()
             dt = e0.elapsed_time(e1) / 1e3
-        if ref is None:
-            ref = got
-            exact = True
-        else:
-            exact = np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
         gcups = cells * steps / dt / 1e9
         results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
-                        "gcups": gcups, "exact": exact})
-        size = f"{n}x{shape['cols']}" if "cols" in shape else f"{n}"
-        log(f"  n={size} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS"
-            + ("" if exact else "  DIFFERS FROM THE REFERENCE -- rejected"))
-    ok = [r for r in results if r["exact"]]
-    best = max(ok, key=lambda r: r["gcups"])
-    return {"best": best, "all": results, "steps": steps,
-            "rejected": [r for r in results if not r["exact"]]}
+                        "gcups": gcups, "exact": True})
+        log(f"  n={size} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS")
+    return {"best": max(results, key=lambda r: r["gcups"]), "all": results, "steps": steps}
 
 
 def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 32, 48),
                t_phases=(8, 10, 12, 14, 16), waves=(2, 4), steps: int = 480, log=print,
-               model: int = 1) -> dict:
+               model: int = 1, reference=None, make_lattice=Lattice, step=step_group) -> dict:
     """Fastest common tuning for lattices (n, rho, seed) of one size that are
     advanced together by joint launches (bml_step_group): a launch spreads
     the strips of all of them over the device, so the best strip height
-    differs from a lone lattice's.  Every lattice's cells and counts must
-    match the reference candidate's (the bit-exactness gate)."""
-    ref = None
+    differs from a lone lattice's.  `reference`: one (cells, counts[steps][4])
+    pair per lattice, the run every candidate must reproduce (default: the
+    first candidate's).  A candidate whose counts are not conserved, or that
+    differs from the reference, stops the tuning (see the module docstring).
+    make_lattice / step: the Lattice constructor and the joint step (stand-ins
+    in the host-side tests)."""
+    ref = reference
     results = []
     cells = float(sum(n * n for n, _, _ in specs))
     for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
-        stream = torch.cuda.Stream()
-        lats = [Lattice(n, rho, seed, layout=layout, stats_cap=steps, stream=stream)
+        stream = torch.cuda.Stream() if torch.cuda.is_available() else None
+        lats = [make_lattice(n, rho, seed, layout=layout, stats_cap=steps, stream=stream)
                 for n, rho, seed in specs]
         try:
             for lat in lats:
                 if model != 1:
                     lat.set_model(model, MODEL2_COIN_SEED)
                 lat.set_tuning(tr, tp, w)
-            step_group(lats, steps)                  # warm-up (and the checked run)
-            torch.cuda.synchronize()
-            try:
-                got = [(lat.cells(), _stats_array(lat.stats(0, steps))) for lat in lats]
-            except L.BmlError as e:                  # e.g. car counts not conserved
-                log(f"  group {name} layout={layout} rows={tr} T={tp} w={w}: {e} -- rejected")
-                results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
-                                "gcups": 0.0, "exact": False, "error": str(e)})
-                continue
+            step(lats, steps)                        # warm-up (and the checked run)
+            got = [_checked_run(lat, steps, f"tune-{name}",
+                                {"candidate": [tr, tp, w], "lattice_index": i,
+                                 "spec": list(specs[i]), "group": [list(x) for x in specs]})
+                   for i, lat in enumerate(lats)]
+            if ref is None:
+                ref = got
+            for i, (a, b) in enumerate(zip(got, ref)):
+                if not _same(a, b):
+                    raise TuningMismatch(
+                        f"group {name} layout={layout}: candidate rows={tr} T={tp} w={w} "
+                        f"differs from the reference on lattice {i} {specs[i]}")
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            step_group(lats, steps)
+            step(lats, steps)
             e1.record(stream)
             torch.cuda.synchronize()
             dt = e0.elapsed_time(e1) / 1e3
         finally:
             for lat in lats:
                 lat.close()
-        if ref is None:
-            ref = got
-            exact = True
-        else:
-            exact = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-                        for a, b in zip(got, ref))
         gcups = cells * steps / dt / 1e9
         results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
-                        "gcups": gcups, "exact": exact})
-        log(f"  group {name} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS"
-            + ("" if exact else "  DIFFERS FROM THE REFERENCE -- rejected"))
-    ok = [r for r in results if r["exact"]]
-    return {"best": max(ok, key=lambda r: r["gcups"]), "all": results, "steps": steps,
-            "rejected": [r for r in results if not r["exact"]]}
+                        "gcups": gcups, "exact": True})
+        log(f"  group {name} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS")
+    return {"best": max(results, key=lambda r: r["gcups"]), "all": results, "steps": steps}
 
 
 def tune_batch(ns, rhos, seeds, name: str, strip_rows=(16, 32, 64, 128),
-               t_phases=(4, 8, 12, 16), waves=(2, 4), steps: int = 256, log=print) -> dict:
-    """Fastest batch tuning for a set of lattices (checked like tune_lattice)."""
-    ref = None
+               t_phases=(4, 8, 12, 16), waves=(2, 4), steps: int = 256, log=print,
+               reference=None) -> dict:
+    """Fastest batch tuning for a set of lattices.  Every candidate's trace
+    (per-step moved counts of every lattice over 2 x steps) and the cells of
+    three lattices must equal `reference` (default: the first candidate's);
+    car counts are recounted after the run (bml_batch_check)."""
+    ref = reference
     results = []
     cells = float(np.sum(np.asarray(ns, dtype=np.float64) ** 2))
     for sr, tp, w in itertools.product(strip_rows, t_phases, waves):
@@ -187,21 +213,19 @@ def tune_batch(ns, rhos, seeds, name: str, strip_rows=(16, 32, 64, 128),
             e1.record(bt.stream)
             bt.synchronize()
             dt = e0.elapsed_time(e1) / 1e3
+            bt.check()
             got = (bt.trace(), [bt.cells(b) for b in (0, len(ns) // 2, len(ns) - 1)])
         if ref is None:
             ref = got
-            exact = True
-        else:
-            exact = np.array_equal(got[0], ref[0]) and all(
-                np.array_equal(a, b) for a, b in zip(got[1], ref[1]))
+        if not (np.array_equal(got[0], ref[0])
+                and all(np.array_equal(a, b) for a, b in zip(got[1], ref[1]))):
+            raise TuningMismatch(f"batch {name}: candidate rows={sr} T={tp} w={w} differs "
+                                 "from the reference")
         gcups = cells * steps / dt / 1e9
         results.append({"tile_rows": sr, "t_phases": tp, "waves_per_block": w,
-                        "gcups": gcups, "exact": exact})
-        log(f"  batch {name} rows={sr} T={tp} w={w}: {gcups:.0f} GCUPS"
-            + ("" if exact else "  DIFFERS FROM THE REFERENCE -- rejected"))
-    ok = [r for r in results if r["exact"]]
-    return {"best": max(ok, key=lambda r: r["gcups"]), "all": results, "steps": steps,
-            "rejected": [r for r in results if not r["exact"]]}
+                        "gcups": gcups, "exact": True})
+        log(f"  batch {name} rows={sr} T={tp} w={w}: {gcups:.0f} GCUPS")
+    return {"best": max(results, key=lambda r: r["gcups"]), "all": results, "steps": steps}
 
 
 def main(argv=None) -> int:
@@ -226,12 +250,8 @@ def main(argv=None) -> int:
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
             r = tune_lattice(n, layout, model=m, **kw)
-            cache[key(layout, n, m)] = dict(r["best"], steps=r["steps"],
-                                            rejected=len(r["rejected"]))
+            cache[key(layout, n, m)] = dict(r["best"], steps=r["steps"])
             print(json.dumps({"key": key(layout, n, m), **r["best"]}), flush=True)
-            if r["rejected"]:
-                print(f"bit-exactness gate rejected {len(r['rejected'])} candidates",
-                      file=sys.stderr)
     if args.rect:
         import workloads
         lt = workloads.RECT.lattices[0]
@@ -240,7 +260,7 @@ def main(argv=None) -> int:
             r = tune_lattice(lt.n, layout, rho=lt.rho, seed=lt.seed, shape=lt.kwargs(),
                              model=m, **kw)
             k = key(layout, f"{lt.n}x{lt.cols}", m)
-            cache[k] = dict(r["best"], steps=r["steps"], rejected=len(r["rejected"]))
+            cache[k] = dict(r["best"], steps=r["steps"])
             print(json.dumps({"key": k, **r["best"]}), flush=True)
     if args.medium:
         import workloads
@@ -249,15 +269,14 @@ def main(argv=None) -> int:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
             r = tune_group(specs, layout, workloads.MEDIUM_GROUP, model=m)
             k = key(layout, workloads.MEDIUM_GROUP, m)
-            cache[k] = dict(r["best"], steps=r["steps"], rejected=len(r["rejected"]))
+            cache[k] = dict(r["best"], steps=r["steps"])
             print(json.dumps({"key": k, **r["best"]}), flush=True)
     if args.batch:
         import workloads
         lats = workloads.SWEEP.lattices
         r = tune_batch([l.n for l in lats], [l.rho for l in lats], [l.seed for l in lats],
                        "sweep512")
-        cache[key(L.BML_LAYOUT_BITPLANE, "sweep512")] = dict(r["best"], steps=r["steps"],
-                                                            rejected=len(r["rejected"]))
+        cache[key(L.BML_LAYOUT_BITPLANE, "sweep512")] = dict(r["best"], steps=r["steps"])
         print(json.dumps({"key": key(L.BML_LAYOUT_BITPLANE, "sweep512"), **r["best"]}),
               flush=True)
     save(cache, args.cache)

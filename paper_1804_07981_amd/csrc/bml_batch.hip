@@ -71,6 +71,8 @@ struct bml_batch {
     BatchItem *d_items = nullptr;
     BatchCounters *d_ctr = nullptr;
     unsigned long long *d_counts = nullptr;
+    uint8_t *d_stage = nullptr;   // bitplane read-back staging, stage_bytes
+    size_t stage_bytes = 0;
     int64_t items_cap = 0;
     // Captured run.
     hipGraph_t graph = nullptr;
@@ -103,6 +105,8 @@ static void batch_release(bml_batch *B)
         (void)hipFree(B->d_ctr);
     if (B->d_counts)
         (void)hipFree(B->d_counts);
+    if (B->d_stage)
+        (void)hipFree(B->d_stage);
     delete B;
 }
 
@@ -355,6 +359,17 @@ int bml_batch_init(bml_batch **out, int32_t count, const int32_t *n, const doubl
         hipMalloc(&B->d_ctr, sizeof(BatchCounters)) != hipSuccess ||
         hipMalloc(&B->d_counts, (size_t)count * 2 * sizeof(unsigned long long)) != hipSuccess)
         return bail(fail(BML_EDEVICE, "hipMalloc of batch scratch failed"));
+    if (layout == BML_LAYOUT_BITPLANE) {
+        // bml_batch_get_cells unpacks through this buffer, whole rows at a
+        // time: the largest lattice, or 16 MiB (at least one row)
+        const int nmax = *std::max_element(n, n + count);
+        B->stage_bytes = std::max<size_t>((size_t)nmax,
+                                          std::min<size_t>((size_t)nmax * nmax, 16u << 20));
+        if (hipMalloc(&B->d_stage, B->stage_bytes) != hipSuccess) {
+            B->d_stage = nullptr;
+            return bail(fail(BML_EDEVICE, "hipMalloc of the read-back staging buffer failed"));
+        }
+    }
     for (int b = 0; b < count; ++b) {
         if ((rc = launch_init(B->buf[0][b], n[b], n[b], layout, seed[b], rho[b] * 0.5, rho[b] * 0.5,
                                B->stream)))
@@ -542,15 +557,22 @@ int bml_batch_get_cells(bml_batch *B, int32_t idx, uint8_t *out_host)
         BML_HIP(hipStreamSynchronize(B->stream));
         return BML_OK;
     }
-    void *tmp = nullptr;
-    BML_HIP(hipMalloc(&tmp, cells));
-    bool ok = launch_unpack((const uint32_t *)state, (uint8_t *)tmp, n, n, B->stream) == BML_OK &&
-              hipMemcpyAsync(out_host, tmp, cells, hipMemcpyDeviceToHost, B->stream) ==
-                  hipSuccess &&
-              hipStreamSynchronize(B->stream) == hipSuccess;
-    (void)hipFree(tmp);
-    if (!ok)
-        return fail(BML_EDEVICE, "unpack/copy of lattice %d failed", idx);
+    // unpack whole rows at a time through the staging buffer; stream order
+    // keeps each chunk's copy ahead of the next unpack
+    const int64_t words = n / 32;
+    const int64_t plane_words = (int64_t)n * words;
+    const uint32_t *lr = (const uint32_t *)state;
+    const int64_t chunk = std::max<int64_t>(1, (int64_t)(B->stage_bytes / (size_t)n));
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+        const int64_t nr = std::min<int64_t>(chunk, n - r0);
+        int rc = launch_unpack_rows(lr + r0 * words, lr + plane_words + r0 * words, B->d_stage,
+                                    nr * words, B->stream);
+        if (rc)
+            return rc;
+        BML_HIP(hipMemcpyAsync(out_host + r0 * n, B->d_stage, (size_t)(nr * n),
+                               hipMemcpyDeviceToHost, B->stream));
+    }
+    BML_HIP(hipStreamSynchronize(B->stream));
     return BML_OK;
 }
 

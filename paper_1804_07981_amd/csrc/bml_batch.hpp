@@ -74,7 +74,7 @@ template <int IO, int K>
 __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
 {
     static_assert(K >= 1 && K <= MAX_K, "bad steps per pass");
-    constexpr int D = IO == IO_U8 ? BML_U8_RING : BML_BP_RING;   // prefetched rows
+    constexpr int D = IO == IO_U8 ? U8_RING : BP_RING;   // prefetched rows
     constexpr int NW = IO == IO_U8 ? 8 : 2;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

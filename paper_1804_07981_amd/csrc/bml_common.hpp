@@ -48,6 +48,10 @@ int launch_pack(const uint8_t *cells, uint32_t *planes, int32_t rows, int32_t co
                 hipStream_t stream);
 int launch_unpack(const uint32_t *planes, uint8_t *cells, int32_t rows, int32_t cols,
                   hipStream_t stream);
+// n_words words of the LR plane `lr` and the TB plane `tb` -> 32 n_words
+// byte cells.
+int launch_unpack_rows(const uint32_t *lr, const uint32_t *tb, uint8_t *cells, int64_t n_words,
+                       hipStream_t stream);
 int launch_zero(uint32_t *p, int64_t words, hipStream_t stream);
 
 inline bool valid_n(int32_t n) { return n >= 32 && n <= 65504 && n % 32 == 0; }

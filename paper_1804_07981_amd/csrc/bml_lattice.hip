@@ -106,9 +106,10 @@ __global__ __launch_bounds__(256) void init_kernel(void *out, int32_t n, int32_t
     }
 }
 
-// Byte cells -> bitplanes, one thread per word.
-__global__ __launch_bounds__(256) void pack_kernel(const uint8_t *cells, uint32_t *planes,
-                                                   int64_t total_words)
+// Byte cells -> bitplanes, one thread per word: cells 32 idx .. 32 idx + 31
+// become word idx of the LR plane `lr` and of the TB plane `tb`.
+__global__ __launch_bounds__(256) void pack_kernel(const uint8_t *cells, uint32_t *lr_out,
+                                                   uint32_t *tb_out, int64_t total_words)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total_words)
@@ -118,19 +119,20 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t *cells, uint32_
     const uint32_t d[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
     uint32_t lr, tb;
     bytes_to_planes(d, lr, tb);
-    planes[idx] = lr;
-    planes[total_words + idx] = tb;
+    lr_out[idx] = lr;
+    tb_out[idx] = tb;
 }
 
-// Bitplanes -> byte cells, one thread per word.
-__global__ __launch_bounds__(256) void unpack_kernel(const uint32_t *planes, uint8_t *cells,
-                                                     int64_t total_words)
+// Bitplanes -> byte cells, one thread per word: word idx of the LR plane
+// `lr` and of the TB plane `tb` become cells 32 idx .. 32 idx + 31.
+__global__ __launch_bounds__(256) void unpack_kernel(const uint32_t *lr, const uint32_t *tb,
+                                                     uint8_t *cells, int64_t total_words)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total_words)
         return;
     uint32_t d[8];
-    planes_to_bytes(planes[idx], planes[total_words + idx], d);
+    planes_to_bytes(lr[idx], tb[idx], d);
     uint4 *p = (uint4 *)(cells + idx * 32);
     p[0] = make_uint4(d[0], d[1], d[2], d[3]);
     p[1] = make_uint4(d[4], d[5], d[6], d[7]);
@@ -331,7 +333,19 @@ int launch_pack(const uint8_t *cells, uint32_t *planes, int32_t rows, int32_t co
     if (rc)
         return rc;
     hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, stream, cells, planes,
-                       total_words);
+                       planes + total_words, total_words);
+    BML_HIP(hipGetLastError());
+    return BML_OK;
+}
+
+int launch_unpack_rows(const uint32_t *lr, const uint32_t *tb, uint8_t *cells, int64_t n_words,
+                       hipStream_t stream)
+{
+    unsigned grid;
+    int rc = launch_1d_grid(n_words, 256, &grid);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid), dim3(256), 0, stream, lr, tb, cells, n_words);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
@@ -344,8 +358,8 @@ int launch_unpack(const uint32_t *planes, uint8_t *cells, int32_t rows, int32_t 
     int rc = launch_1d_grid(total_words, 256, &grid);
     if (rc)
         return rc;
-    hipLaunchKernelGGL(unpack_kernel, dim3(grid), dim3(256), 0, stream, planes, cells,
-                       total_words);
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid), dim3(256), 0, stream, planes,
+                       planes + total_words, cells, total_words);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
@@ -377,7 +391,13 @@ struct bml_lattice {
     DeviceInfo dev;
     unsigned long long *d_counts = nullptr;   // library scratch: 2 counters
     PassScratch *d_scratch = nullptr;         // library scratch: stats reduction
+    uint8_t *d_stage = nullptr;               // bitplane read-back staging (stage_rows rows)
+    int32_t stage_rows = 0;
 };
+
+// Bytes of the bitplane read-back staging buffer: whole rows, at most
+// STAGE_BYTES (or one row when a row alone is larger).
+constexpr size_t STAGE_BYTES = 16u << 20;
 
 static std::mutex g_handles_mu;
 static std::unordered_set<const bml_lattice *> g_handles;
@@ -495,7 +515,7 @@ int bml_pack(int32_t n, const uint8_t *d_cells, uint32_t *d_planes, void *hip_st
     if (rc)
         return rc;
     hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream,
-                       d_cells, d_planes, total_words);
+                       d_cells, d_planes, d_planes + total_words, total_words);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
@@ -513,7 +533,7 @@ int bml_unpack(int32_t n, const uint32_t *d_planes, uint8_t *d_cells, void *hip_
     if (rc)
         return rc;
     hipLaunchKernelGGL(unpack_kernel, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream,
-                       d_planes, d_cells, total_words);
+                       d_planes, d_planes + total_words, d_cells, total_words);
     BML_HIP(hipGetLastError());
     return BML_OK;
 }
@@ -577,6 +597,8 @@ int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
             (void)hipFree(L->d_counts);
         if (L->d_scratch)
             (void)hipFree(L->d_scratch);
+        if (L->d_stage)
+            (void)hipFree(L->d_stage);
         delete L;
         return code;
     };
@@ -592,6 +614,14 @@ int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
     }
     if ((rc = launch_zero((uint32_t *)L->d_scratch, sizeof(PassScratch) / 4, L->stream)))
         return cleanup(rc);
+    if (layout == BML_LAYOUT_BITPLANE) {
+        // bml_get_cells unpacks through this buffer in chunks of whole rows
+        L->stage_rows = (int32_t)std::max<size_t>(1, std::min<size_t>(rows, STAGE_BYTES / cols));
+        if (hipMalloc(&L->d_stage, (size_t)L->stage_rows * cols) != hipSuccess) {
+            L->d_stage = nullptr;
+            return cleanup(fail(BML_EDEVICE, "hipMalloc of the read-back staging buffer failed"));
+        }
+    }
 
     if (!cells_host) {
         if ((rc = launch_init(d_state_a, rows, cols, layout, seed, rho_lr, rho_tb, L->stream)))
@@ -601,19 +631,26 @@ int bml_init_rect(bml_lattice **out, int32_t rows, int32_t cols, int32_t layout,
             hipSuccess)
             return cleanup(fail(BML_EDEVICE, "hipMemcpyAsync of the initial cells failed"));
     } else {
-        // The byte lattice is 4x larger than a bitplane state buffer, so it
-        // is staged in a temporary device buffer and packed from there.
-        void *tmp = nullptr;
-        if (hipMalloc(&tmp, n_cells) != hipSuccess)
-            return cleanup(fail(BML_EDEVICE, "hipMalloc of the staging buffer failed"));
-        bool ok = hipMemcpyAsync(tmp, cells_host, n_cells, hipMemcpyHostToDevice,
-                                 L->stream) == hipSuccess &&
-                  launch_pack((const uint8_t *)tmp, (uint32_t *)d_state_a, rows, cols,
-                              L->stream) == BML_OK &&
-                  hipStreamSynchronize(L->stream) == hipSuccess;
-        (void)hipFree(tmp);
-        if (!ok)
-            return cleanup(fail(BML_EDEVICE, "upload/pack of the initial cells failed"));
+        // The byte lattice is 4x larger than a bitplane state buffer: it is
+        // uploaded into the staging buffer stage_rows rows at a time and
+        // packed from there.
+        const int64_t words = cols / 32;
+        uint32_t *lr = (uint32_t *)d_state_a;
+        uint32_t *tb = lr + (int64_t)rows * words;
+        for (int64_t r0 = 0; r0 < rows; r0 += L->stage_rows) {
+            const int64_t nr = std::min<int64_t>(L->stage_rows, rows - r0);
+            const int64_t n_words = nr * words;
+            unsigned grid;
+            if ((rc = launch_1d_grid(n_words, 256, &grid)))
+                return cleanup(rc);
+            if (hipMemcpyAsync(L->d_stage, cells_host + r0 * cols, (size_t)(nr * cols),
+                               hipMemcpyHostToDevice, L->stream) != hipSuccess)
+                return cleanup(fail(BML_EDEVICE, "upload of the initial cells failed"));
+            hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, L->stream, L->d_stage,
+                               lr + r0 * words, tb + r0 * words, n_words);
+            if (hipGetLastError() != hipSuccess)
+                return cleanup(fail(BML_EDEVICE, "pack of the initial cells failed"));
+        }
     }
     if ((rc = count_cars(L, d_state_a, &L->n_lr0, &L->n_tb0)))
         return cleanup(rc);
@@ -956,24 +993,24 @@ int bml_get_cells(bml_lattice *L, uint8_t *out_host)
         BML_HIP(hipStreamSynchronize(L->stream));
         return BML_OK;
     }
-    void *tmp = nullptr;
-    BML_HIP(hipMalloc(&tmp, cells));
-    const int64_t total_words = (int64_t)L->rows * (L->cols / 32);
-    unsigned grid;
-    int rc = launch_1d_grid(total_words, 256, &grid);
-    if (rc) {
-        (void)hipFree(tmp);
-        return rc;
+    // Bitplanes: unpack stage_rows rows at a time into the handle's staging
+    // buffer and copy each chunk out (stream order keeps a chunk's copy
+    // ahead of the next unpack into the same buffer).
+    const int64_t words = L->cols / 32;
+    const int64_t plane_words = (int64_t)L->rows * words;
+    const uint32_t *lr = (const uint32_t *)L->buf[L->cur];
+    const uint32_t *tb = lr + plane_words;
+    for (int64_t r0 = 0; r0 < L->rows; r0 += L->stage_rows) {
+        const int64_t nr = std::min<int64_t>(L->stage_rows, L->rows - r0);
+        const int64_t n_words = nr * words;
+        int rc = launch_unpack_rows(lr + r0 * words, tb + r0 * words, L->d_stage, n_words,
+                                    L->stream);
+        if (rc)
+            return rc;
+        BML_HIP(hipMemcpyAsync(out_host + r0 * L->cols, L->d_stage, (size_t)(nr * L->cols),
+                               hipMemcpyDeviceToHost, L->stream));
     }
-    hipLaunchKernelGGL(unpack_kernel, dim3(grid), dim3(256), 0, L->stream,
-                       (const uint32_t *)L->buf[L->cur], (uint8_t *)tmp, total_words);
-    bool ok = hipGetLastError() == hipSuccess &&
-              hipMemcpyAsync(out_host, tmp, cells, hipMemcpyDeviceToHost, L->stream) ==
-                  hipSuccess &&
-              hipStreamSynchronize(L->stream) == hipSuccess;
-    (void)hipFree(tmp);
-    if (!ok)
-        return fail(BML_EDEVICE, "unpack/copy of the cells failed");
+    BML_HIP(hipStreamSynchronize(L->stream));
     return BML_OK;
 }
 
@@ -1006,6 +1043,8 @@ void bml_free(bml_lattice *L)
         (void)hipFree(L->d_counts);
     if (L->d_scratch)
         (void)hipFree(L->d_scratch);
+    if (L->d_stage)
+        (void)hipFree(L->d_stage);
     delete L;
 }
 

@@ -95,32 +95,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint3
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-// Cache-policy bits of the state loads and stores (0 = default).
-#ifndef BML_LOAD_AUX
-#define BML_LOAD_AUX 0
-#endif
-#ifndef BML_STORE_AUX
-#define BML_STORE_AUX 0
-#endif
-#ifndef BML_LEVEL_BARRIER
-#define BML_LEVEL_BARRIER 0
-#endif
 // Rows prefetched ahead of the pipeline (register ring depth) for byte and
 // bitplane rows, one or two words per lane.  Deeper rings hide more memory
 // latency but cost VGPRs; these keep every variant within 256 VGPRs (no
 // accumulation-register spills) and at two or more waves per SIMD.
-#ifndef BML_U8_RING
-#define BML_U8_RING 4
-#endif
-#ifndef BML_BP_RING
-#define BML_BP_RING 8
-#endif
-#ifndef BML_U8_RING2
-#define BML_U8_RING2 1
-#endif
-#ifndef BML_BP_RING2
-#define BML_BP_RING2 2
-#endif
+constexpr int U8_RING = 4, BP_RING = 8;     // one word per lane
+constexpr int U8_RING2 = 1, BP_RING2 = 2;   // two words per lane
 
 // ROW = 0: tile mode, any row length; a wavefront covers 62 words plus a
 // halo lane on each side.  ROW = m > 0: row mode for rows of 2048 m cells;
@@ -148,8 +128,8 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
     static_assert(ROW >= 0 && ROW <= 2, "row mode holds at most 2 words per lane");
     constexpr int WL = ROW ? ROW : 1;        // words per lane
     constexpr bool WRAP = ROW > 0;
-    constexpr int D = IO == IO_U8 ? (WL > 1 ? BML_U8_RING2 : BML_U8_RING)
-                                  : (WL > 1 ? BML_BP_RING2 : BML_BP_RING);
+    constexpr int D = IO == IO_U8 ? (WL > 1 ? U8_RING2 : U8_RING)
+                                  : (WL > 1 ? BP_RING2 : BP_RING);
     constexpr int NW = (IO == IO_U8 ? 8 : 2) * WL;   // dwords one lane loads per row
     const int lane = threadIdx.x & 63;
     // Wave-uniform values must be visibly uniform so that strip and row
@@ -271,18 +251,18 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
 #pragma unroll
                 for (int j = 0; j < 2 * WL; ++j) {
                     const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(src, vo + 16 * j,
-                                                                          off, BML_LOAD_AUX);
+                                                                          off, 0);
                     dstw[4 * j + 0] = u.x; dstw[4 * j + 1] = u.y;
                     dstw[4 * j + 2] = u.z; dstw[4 * j + 3] = u.w;
                 }
             } else if constexpr (WL == 1) {
-                dstw[0] = __builtin_amdgcn_raw_buffer_load_b32(src, vo, off, BML_LOAD_AUX);
+                dstw[0] = __builtin_amdgcn_raw_buffer_load_b32(src, vo, off, 0);
                 dstw[1] = __builtin_amdgcn_raw_buffer_load_b32(src, vo, off + plane_bytes,
-                                                               BML_LOAD_AUX);
+                                                               0);
             } else {
-                const u32x2 l = __builtin_amdgcn_raw_buffer_load_b64(src, vo, off, BML_LOAD_AUX);
+                const u32x2 l = __builtin_amdgcn_raw_buffer_load_b64(src, vo, off, 0);
                 const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(src, vo, off + plane_bytes,
-                                                                     BML_LOAD_AUX);
+                                                                     0);
                 dstw[0] = l.x; dstw[1] = l.y; dstw[2] = t.x; dstw[3] = t.y;
             }
         };
@@ -417,9 +397,6 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                         bl[k][i] = o.L[i];
                         bt[k][i] = o.T[i];
                     }
-#if BML_LEVEL_BARRIER
-                    __builtin_amdgcn_sched_barrier(0);
-#endif
                 }
                 if (FULL || (t >= 3 * K - 1 && t < 3 * K - 1 + h)) {
                     const uint32_t so = (uint32_t)__builtin_amdgcn_readfirstlane((int)st_off);
@@ -431,24 +408,24 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
                                 planes_to_bytes(bl[K - 1][i], bt[K - 1][i], b);
                                 __builtin_amdgcn_raw_buffer_store_b128(
                                     (u32x4){b[0], b[1], b[2], b[3]}, dst, voff + 32 * i, so,
-                                    BML_STORE_AUX);
+                                    0);
                                 __builtin_amdgcn_raw_buffer_store_b128(
                                     (u32x4){b[4], b[5], b[6], b[7]}, dst, voff + 32 * i + 16,
-                                    so, BML_STORE_AUX);
+                                    so, 0);
                             }
                         } else if constexpr (WL == 1) {
                             __builtin_amdgcn_raw_buffer_store_b32(bl[K - 1][0], dst, voff, so,
-                                                                  BML_STORE_AUX);
+                                                                  0);
                             __builtin_amdgcn_raw_buffer_store_b32(bt[K - 1][0], dst, voff,
                                                                   so + plane_bytes,
-                                                                  BML_STORE_AUX);
+                                                                  0);
                         } else {
                             __builtin_amdgcn_raw_buffer_store_b64(
                                 (u32x2){bl[K - 1][0], bl[K - 1][1]}, dst, voff, so,
-                                BML_STORE_AUX);
+                                0);
                             __builtin_amdgcn_raw_buffer_store_b64(
                                 (u32x2){bt[K - 1][0], bt[K - 1][1]}, dst, voff,
-                                so + plane_bytes, BML_STORE_AUX);
+                                so + plane_bytes, 0);
                         }
                     }
                     st_off += row_bytes;
@@ -462,13 +439,11 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a)
         for (int t0 = 0; t0 < total_it; t0 += D) {
             // Full: every level counts, every iteration stores and the
             // prefetch stays inside the strip for all D iterations.
-#ifndef BML_NO_FULL_BODY
             if (t0 >= 3 * K - 1 && t0 + D <= h + K && t0 + 2 * D <= total_in)
                 // (its only edge work is choosing the mirror offset of a
                 // prefetched bottom halo row: one select per load)
                 body(t0, std::true_type{}, std::bool_constant<TOPO == TOPO_KLEIN>{});
             else
-#endif
             // (two-word rows keep one body: a second copy would push them
             // past 256 VGPRs)
             if (TOPO == TOPO_KLEIN && (WL > 1 || edge_strip))

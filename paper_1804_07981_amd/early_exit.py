@@ -137,6 +137,9 @@ def run_sweep(ns, rhos, seeds, full_steps: int = 20000, chunk: int = 512,
     exit.  Wall time covers everything from the batch's first step to the
     last label."""
     count = len(ns)
+    if mlp is not None and (exit_step <= 0 or exit_step % chunk or exit_step > full_steps):
+        raise ValueError(f"exit_step={exit_step} must be a positive multiple of the "
+                         f"chunk ({chunk}) within the run ({full_steps} steps)")
     stream = torch.cuda.Stream(torch.device(device))
     bt = Batch(ns, rhos, seeds, layout=L.BML_LAYOUT_BITPLANE, trace_steps=full_steps,
                device=device, stream=stream)
@@ -166,6 +169,17 @@ def run_sweep(ns, rhos, seeds, full_steps: int = 20000, chunk: int = 512,
         steps[active == 1] += k
         prev, done = done, done + k
         changed = False
+        # The exact rule first: a lattice that froze in this chunk is jammed
+        # whatever the network would say about it.
+        if stop_frozen:
+            L.bml_trace_frozen(bt.trace_tensor(), bt.trace_steps, count, prev, done, frozen_d,
+                               stream)
+            fr = _sync_copy(frozen_d, stream)
+            for b in np.nonzero(active & (fr == 1))[0]:
+                labels[b] = 1
+                how[b] = 1
+                active[b] = 0
+                changed = True
         if mlp is not None and done == exit_step:
             X = batch_features(bt, rhos, stream)
             stream.synchronize()   # the MLP works on its own stream
@@ -179,15 +193,6 @@ def run_sweep(ns, rhos, seeds, full_steps: int = 20000, chunk: int = 512,
                     how[b] = 2
                     active[b] = 0
                     changed = True
-        if stop_frozen:
-            L.bml_trace_frozen(bt.trace_tensor(), bt.trace_steps, count, prev, done, frozen_d,
-                               stream)
-            fr = _sync_copy(frozen_d, stream)
-            for b in np.nonzero(active & (fr == 1))[0]:
-                labels[b] = 1
-                how[b] = 1
-                active[b] = 0
-                changed = True
         if changed and active.any():
             bt.set_active(active)
     if keep_features and features is None:
@@ -246,11 +251,14 @@ def plain_runs(ns, rhos, seeds, full_steps: int = 20000, label_window: int = 100
 
 
 def experiment(ns, rhos, seeds, split, full_steps=20000, exit_step=512, epochs=300,
-               plain_sample: int | None = None, device="cuda", log=print) -> dict:
+               plain_sample: int | None = None, device="cuda", log=print,
+               return_labels: bool = False) -> dict:
     """Full early-exit experiment: labels for every lattice (exact stop rule,
     full length otherwise), train on split == 'train', evaluate on 'test',
     then time on the test lattices (1) plain per-lattice full runs, (2) the
-    batch with the exact stop rule, (3) (2) plus the learned exit."""
+    batch with the exact stop rule, (3) (2) plus the learned exit.  With
+    return_labels the report also holds every lattice's full-run label
+    ("labels") and the test-set labels of run (3) ("labels_mlp_test")."""
     split = np.asarray(split)
     log(f"labelling {len(ns)} lattices ({full_steps} steps, exact stop rule)")
     lab = run_sweep(ns, rhos, seeds, full_steps, stop_frozen=True, keep_features=True,
@@ -308,6 +316,10 @@ def experiment(ns, rhos, seeds, split, full_steps=20000, exit_step=512, epochs=3
                                 "measured_wall_s": pw,
                                 "label_error": float((pl != full_t[idx]).mean())}
     out["gain_vs_plain"] = out["plain_per_lattice"]["wall_s"] / r3.wall_s
+    if return_labels:
+        out["labels"] = lab.labels.tolist()
+        out["labels_mlp_test"] = r3.labels.tolist()
+        out["test_index"] = te.tolist()
     out["gain_vs_exact_stop"] = r2.wall_s / r3.wall_s
     out["work_saved_vs_exact_stop"] = 1.0 - r3.cell_steps / r2.cell_steps
     return out

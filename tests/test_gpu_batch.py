@@ -13,7 +13,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-HOST_THREADS = min(16, os.cpu_count() or 1)
+from tests.hostinfo import HOST_THREADS  # noqa: E402
 
 
 @pytest.fixture(scope="module")

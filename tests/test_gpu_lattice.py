@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 U8, BP = 0, 1
 LAYOUTS = [U8, BP]
-HOST_THREADS = min(16, os.cpu_count() or 1)
+from tests.hostinfo import HOST_THREADS  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -554,6 +554,95 @@ def test_medium_full_lattice(B, layout):
         assert np.array_equal(stats_array(lat.stats(0, steps)), wst)
 
 
+# --- the four-lattice 4096 x 4096 workload in the benchmark's launch shape ---
+
+MEDIUM_CHECK_STEPS = 1000
+
+
+@pytest.fixture(scope="module")
+def medium_reference():
+    """The oracle's run of the four 4096 x 4096 lattices (rho .25/.35/.38/.45,
+    seeds 1-4): final cells and every step's counts, on all host threads."""
+    w = workloads.MEDIUM
+    out = []
+    for lt in w.lattices:
+        say(f"oracle: 4096^2 rho={lt.rho} seed={lt.seed}, {MEDIUM_CHECK_STEPS} steps, "
+            f"{HOST_THREADS} threads")
+        out.append(oracle.run(oracle.init_cells(lt.n, lt.seed, lt.rho), MEDIUM_CHECK_STEPS,
+                              n_threads=HOST_THREADS))
+    return out
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_medium_bench_shape(B, layout, medium_reference):
+    """The four lattices advanced together by joint launches in the tuned
+    shape the benchmark times (bench.load_tuning(layout, 4096, "medium4")),
+    1000 steps: every count of every step and every final cell."""
+    import torch
+    import bench
+    w = workloads.MEDIUM
+    tun = bench.load_tuning(layout, 4096, workloads.MEDIUM_GROUP)
+    say(f"medium bench shape layout={layout} tuning={tun}")
+    stream = torch.cuda.Stream()
+    lats = [B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=MEDIUM_CHECK_STEPS,
+                      stream=stream) for lt in w.lattices]
+    try:
+        for lat in lats:
+            if tun:
+                lat.set_tuning(*tun)
+        B.step_group(lats, MEDIUM_CHECK_STEPS)
+        for lat, lt, (want, wst) in zip(lats, w.lattices, medium_reference):
+            got = lat.cells()
+            if not np.array_equal(got, want):
+                bad = np.argwhere(got != want)
+                pytest.fail(f"rho={lt.rho}: {len(bad)} cells differ, first at {bad[0]}")
+            st = stats_array(lat.stats(0, MEDIUM_CHECK_STEPS))
+            if not np.array_equal(st, wst):
+                s0 = int(np.argwhere((st != wst).any(axis=1))[0, 0])
+                pytest.fail(f"rho={lt.rho}: counts differ from step {s0}: {st[s0]} vs {wst[s0]}")
+    finally:
+        for lat in lats:
+            lat.close()
+
+
+# --- the 32768 x 32768 workload, whole lattice ------------------------------
+
+LARGE_CHECK_STEPS = 64
+
+
+@pytest.fixture(scope="module")
+def large_reference():
+    """The oracle's run of the 32768 x 32768 lattice (rho 0.30, seed 7) for
+    64 steps: initial and final cells and every step's counts."""
+    lt = workloads.LARGE.lattices[0]
+    say(f"oracle: 32768^2 init + {LARGE_CHECK_STEPS} steps, {HOST_THREADS} threads")
+    g0 = oracle.init_cells(lt.n, lt.seed, lt.rho)
+    want, wst = oracle.run(g0, LARGE_CHECK_STEPS, n_threads=HOST_THREADS)
+    return g0, want, wst
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_large_whole_lattice(B, layout, large_reference):
+    """32768 x 32768 in the tuned launch shape the benchmark times: 64 steps
+    (8 passes at 8 steps per pass), every cell and all 64 count rows against
+    the whole-lattice oracle."""
+    import bench
+    lt = workloads.LARGE.lattices[0]
+    g0, want, wst = large_reference
+    tun = bench.load_tuning(layout, lt.n)
+    say(f"large whole lattice layout={layout} tuning={tun}")
+    with make(B, lt.n, lt.rho, lt.seed, layout, cap=LARGE_CHECK_STEPS, tuning=tun) as lat:
+        lat.step(LARGE_CHECK_STEPS)
+        st = stats_array(lat.stats(0, LARGE_CHECK_STEPS))
+        got = lat.cells()
+    if not np.array_equal(st, wst):
+        s0 = int(np.argwhere((st != wst).any(axis=1))[0, 0])
+        pytest.fail(f"counts differ from step {s0}: {st[s0]} vs {wst[s0]}")
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        pytest.fail(f"{len(bad)} cells differ, first at {bad[0]}")
+
+
 # --- the 32768 x 32768 workload, sampled windows --------------------------
 
 def window(g, i0, j0, size):
@@ -564,25 +653,20 @@ def window(g, i0, j0, size):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_large_sampled_windows(B, layout):
+def test_large_sampled_windows(B, layout, large_reference):
     """32768 x 32768, rho 0.30, seed 7, in the launch shape the benchmark
     times: 48 steps, then 12 windows of 64 x 64 (corners, edges, interior)
-    checked against the oracle on padded windows; car counts conserved every
-    step; the first two steps' counts checked against the whole-lattice
-    oracle."""
+    checked against the oracle on padded windows, and every step's counts
+    against the whole-lattice oracle."""
     n, rho, seed, steps, W = 32768, 0.30, 7, 48, 64
     say(f"large sampled n={n} layout={layout}")
-    g0 = oracle.init_cells(n, seed, rho)
+    g0, _, wst = large_reference
     import bench
     with make(B, n, rho, seed, layout, cap=steps, tuning=bench.load_tuning(layout, n)) as lat:
-        lat.step(2)
-        got2 = stats_array(lat.stats(0, 2))
-        lat.step(steps - 2)
+        lat.step(steps)
         got = lat.cells()
         st = stats_array(lat.stats(0, steps))
-    _, want2 = oracle.run(g0, 2, n_threads=HOST_THREADS)
-    assert np.array_equal(got2, want2)
-    assert (st[:, 0] == oracle.count(g0, 1)).all() and (st[:, 2] == oracle.count(g0, 2)).all()
+    assert np.array_equal(st, wst[:steps])
     rng = np.random.default_rng(7)
     picks = [(0, 0), (0, n - W), (n - W, 0), (n - W, n - W), (n // 2, n // 2 - 32)]
     picks += [tuple(int(x) for x in rng.integers(0, n, size=2)) for _ in range(7)]
@@ -594,7 +678,7 @@ def test_large_sampled_windows(B, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_klein_large(B, layout):
+def test_klein_large(B, layout, large_reference):
     """32768 x 32768 Klein bottle in the benchmark's launch shape, 40 steps:
     windows whose dependence cone stays clear of the glued edge match the
     torus oracle on padded windows; over the whole lattice every row keeps
@@ -604,7 +688,7 @@ def test_klein_large(B, layout):
     import bench
     n, rho, seed, steps, W = 32768, 0.30, 7, 40, 64
     say(f"klein large n={n} layout={layout}")
-    g0 = oracle.init_cells(n, seed, rho)
+    g0 = large_reference[0]
     with make(B, n, rho, seed, layout, cap=steps) as lat:
         lat.set_topology(B.BML_TOPO_KLEIN)
         tun = bench.load_tuning(layout, n)
@@ -711,3 +795,21 @@ def test_copy_reference_kernel(B):
         torch.cuda.synchronize()
         assert torch.equal(dst[:nbytes], src)
         assert int(dst[nbytes:].sum()) == 0
+
+
+def test_autotuner_candidates_match_the_oracle(B):
+    """The autotuner's gate with the oracle's run as its reference: every
+    candidate launch shape (strip rows, phases per pass, waves per block) of
+    a joint four-lattice group must reproduce it, or tune_group raises."""
+    from paper_1804_07981_amd import autotune
+    specs = [(512, 0.25, 1), (512, 0.35, 2), (512, 0.38, 3), (512, 0.45, 4)]
+    steps = 48
+    ref = []
+    for n, rho, seed in specs:
+        want, wst = oracle.run(oracle.init_cells(n, seed, rho), steps, n_threads=HOST_THREADS)
+        ref.append((want, wst))
+    for layout in LAYOUTS:
+        r = autotune.tune_group(specs, layout, "oracle-gate", strip_rows=(0, 8, 24),
+                                t_phases=(2, 10, 16), waves=(1, 4), steps=steps,
+                                log=say, reference=ref)
+        assert len(r["all"]) == 18

@@ -13,7 +13,7 @@ import oracle
 from oracle import mlp as omlp
 
 pytestmark = pytest.mark.gpu
-HOST_THREADS = min(16, os.cpu_count() or 1)
+from tests.hostinfo import HOST_THREADS  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -107,10 +107,14 @@ def test_gradient_matches_fp64_oracle(B, n):
     l64, g64 = omlp.grad(params.astype(np.float64), X.astype(np.float64), y.astype(np.float64))
     g32 = g.cpu().numpy().astype(np.float64)
     assert abs(loss.item() - l64) <= 1e-5 * max(1.0, abs(l64))
-    assert np.linalg.norm(g32 - g64) <= 1e-4 * np.linalg.norm(g64)
-    # entry-wise, for entries that are not tiny
-    big = np.abs(g64) > 1e-3 * np.abs(g64).max()
-    assert np.allclose(g32[big], g64[big], rtol=1e-3)
+    # Element by element: rtol 1e-4, plus an absolute floor of 1e-6 of the
+    # largest entry for entries that are sums of terms cancelling each other
+    # (an fp32 sum of n terms of size t carries about sqrt(n) 2^-24 t of
+    # rounding, far below the floor for these problem sizes).
+    err = np.abs(g32 - g64)
+    bound = 1e-4 * np.abs(g64) + 1e-6 * np.abs(g64).max()
+    worst = int(np.argmax(err / bound))
+    assert (err <= bound).all(), (worst, g32[worst], g64[worst])
 
 
 def test_adam_step_matches_oracle(B):
@@ -134,14 +138,23 @@ def test_adam_step_matches_oracle(B):
     p64 = params.astype(np.float64)
     m64 = np.zeros(omlp.NP)
     v64 = np.zeros(omlp.NP)
+    gs = []
     for t in (1, 2):
         _, gg = omlp.grad(p64, X[idx].astype(np.float64), y[idx].astype(np.float64))
         p64, m64, v64 = omlp.adam_step(p64, m64, v64, gg, t)
+        gs.append(gg)
     step = p64 - params
     got = P.cpu().numpy().astype(np.float64) - params
-    # steps are ~1e-3 in size; allow for fp32 gradients of near-zero entries
-    assert np.linalg.norm(got - step) <= 2e-2 * np.linalg.norm(step)
-    assert np.allclose(m.cpu().numpy(), m64, rtol=1e-3, atol=1e-7)
+    # The update lr * mhat / (sqrt(vhat) + eps) is determined to fp32
+    # precision wherever the gradient is well above eps = 1e-8 at both steps;
+    # there it must agree to 1e-3 of lr entry by entry.  Entries whose
+    # gradient is within a few eps of zero flip with any rounding of g and
+    # are only bounded (|step| <= 2 lr after two steps).
+    firm = np.minimum(np.abs(gs[0]), np.abs(gs[1])) > 1e-5
+    assert firm.mean() > 0.5
+    assert np.abs(got - step)[firm].max() <= 1e-3 * 1e-3
+    assert np.abs(got).max() <= 2.0 * 1e-3 + 1e-9
+    assert np.allclose(m.cpu().numpy(), m64, rtol=1e-4, atol=1e-7)
 
 
 def test_inference_fp32_and_bf16_match_oracle(B):
@@ -169,6 +182,24 @@ def test_inference_fp32_and_bf16_match_oracle(B):
     assert np.array_equal((zb < -t)[far], (ze < -t)[far])
 
 
+def test_bf16_inference_of_hand_built_network(B):
+    """The hand-built network whose bfloat16 logit is exact (every value a
+    short binary fraction): the GPU kernel must give that logit bit for bit,
+    and the fp32 kernel the unrounded one."""
+    import torch
+    from tests import bf16_network
+    params, X = bf16_network.network()
+    X = np.repeat(X, 300, axis=0)      # several blocks of samples
+    zbf = torch.empty(len(X), dtype=torch.float32, device="cuda")
+    z32 = torch.empty(len(X), dtype=torch.float32, device="cuda")
+    B.bml_mlp_infer_bf16(dev(params), dev(X), len(X), zbf)
+    B.bml_mlp_forward(dev(params), dev(X), len(X), z32)
+    torch.cuda.synchronize()
+    assert (zbf.cpu().numpy() == np.float32(bf16_network.EXPECTED_LOGIT)).all()
+    z64, _ = omlp.forward(params.astype(np.float64), X[:1].astype(np.float64))
+    assert (z32.cpu().numpy() == np.float32(z64[0])).all()
+
+
 def test_early_exit_saves_work(B):
     """Reduced sweep (128 x 128, rho 0.20..0.55, 8 seeds each, 3000 steps):
     train on 6 seeds, exit at step 512 when confident.  Lattices that do not
@@ -189,3 +220,38 @@ def test_early_exit_saves_work(B):
     assert ml["mlp_exits"] > 0
     assert ml["cell_steps"] < ex["cell_steps"]
     assert ml["label_error"] <= 0.05
+
+
+def test_full_early_exit_sweep(B):
+    """The whole learned early-exit workload: 9024 lattices of 512 x 512
+    (141 densities x 64 seeds), labels from 20000-step runs, the network
+    trained on the GPU, held-out seeds 51..63.  The exact stop rule alone is
+    exact; the learned exit keeps the held-out label error within 1 % and
+    finishes sooner than the exact rule alone.  The full-run labels of 12
+    held-out lattices across the transition are checked against the oracle
+    run for the full 20000 steps."""
+    from paper_1804_07981_amd import early_exit as ee
+    ns, rhos, seeds, split = ee.c4_lattices()
+    rep = ee.experiment(ns, rhos, seeds, split, plain_sample=2, log=say, return_labels=True)
+    summary = {k: v for k, v in rep.items() if k not in ("labels", "labels_mlp_test",
+                                                          "test_index")}
+    say(summary)
+    assert rep["n_lattices"] == 9024 and rep["n_test"] == 1833
+    assert rep["batch_full"]["label_error"] == 0.0
+    assert rep["batch_exact_stop"]["label_error"] == 0.0
+    ml = rep["batch_exact_stop_mlp"]
+    assert ml["mlp_exits"] > 0
+    assert ml["label_error"] <= 0.01
+    assert rep["gain_vs_exact_stop"] > 1.0
+    assert rep["work_saved_vs_exact_stop"] > 0.0
+    # oracle labels of held-out lattices around the transition
+    te = np.asarray(rep["test_index"])
+    mid = [i for i in te if 0.30 <= rhos[i] <= 0.42]
+    pick = [mid[j] for j in np.linspace(0, len(mid) - 1, 12).astype(int)]
+    say(f"oracle: {len(pick)} lattices of 512^2, 20000 steps, {HOST_THREADS} threads")
+    outs, stats = oracle.run_many([oracle.init_cells(ns[i], seeds[i], rhos[i]) for i in pick],
+                                  20000, n_threads=HOST_THREADS)
+    for i, st in zip(pick, stats):
+        cars = int(st[0, 0] + st[0, 2])
+        want = omlp.jam_label(st[:, 1], st[:, 3], cars, last=1000, threshold=0.05)
+        assert rep["labels"][i] == want, (i, rhos[i], seeds[i])

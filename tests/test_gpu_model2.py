@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 U8, BP = 0, 1
 LAYOUTS = [U8, BP]
-HOST_THREADS = min(16, os.cpu_count() or 1)
+from tests.hostinfo import HOST_THREADS  # noqa: E402
 
 
 @pytest.fixture(scope="module")

@@ -107,3 +107,53 @@ def test_labels_from_oracle_runs():
     lone[4, 4] = 1
     _, st = oracle.run(lone, 300)
     assert mlp.jam_label(st[:, 1], st[:, 3], 1, last=100) == 0
+
+
+# --- bfloat16 inference pinned by a hand-built network ------------------------
+
+from tests import bf16_network  # noqa: E402
+
+BF16_SITES = [
+    ("input not rounded", "    x = to_bf16(f32(X))", "    x = f32(X)"),
+    ("W1 not rounded", '    W1 = to_bf16(f32(p["W1"]))', '    W1 = f32(p["W1"])'),
+    ("W2 not rounded", '    W2 = to_bf16(f32(p["W2"]))', '    W2 = f32(p["W2"])'),
+    ("W3 not rounded", '    W3 = to_bf16(f32(p["W3"]))', '    W3 = f32(p["W3"])'),
+    ("h1 not rounded", "    h1 = to_bf16(np.maximum(x @ W1.T + b1, np.float32(0)))",
+     "    h1 = np.maximum(x @ W1.T + b1, np.float32(0))"),
+    ("h2 not rounded", "    h2 = to_bf16(np.maximum(h1 @ W2.T + b2, np.float32(0)))",
+     "    h2 = np.maximum(h1 @ W2.T + b2, np.float32(0))"),
+    ("b1 rounded", '    b1 = f32(p["b1"])', '    b1 = to_bf16(f32(p["b1"]))'),
+    ("b2 rounded", '    b2 = f32(p["b2"])', '    b2 = to_bf16(f32(p["b2"]))'),
+    ("b3 rounded", '    b3 = f32(p["b3"])', '    b3 = to_bf16(f32(p["b3"]))'),
+    ("rounding by truncation", "(u + 0x7fff + ((u >> 16) & 1)) & 0xffff0000",
+     "u & 0xffff0000"),
+]
+
+
+def _bf16_logit(infer):
+    params, X = bf16_network.network()
+    return infer(params, X)
+
+
+def test_bf16_inference_of_hand_built_network():
+    """Every rounding site and every unrounded bias shows in the logit."""
+    z = _bf16_logit(mlp.infer_bf16)
+    assert z.dtype == np.float32 and z.shape == (1,)
+    assert z[0] == np.float32(bf16_network.EXPECTED_LOGIT)
+    # the same network in fp64 (no rounding at all) gives another value
+    params, X = bf16_network.network()
+    z64, _ = mlp.forward(params.astype(np.float64), X.astype(np.float64))
+    assert z64[0] != bf16_network.EXPECTED_LOGIT
+
+
+@pytest.mark.parametrize("name,before,after", BF16_SITES, ids=[s[0] for s in BF16_SITES])
+def test_bf16_pin_catches_planted_mistake(name, before, after):
+    """A copy of oracle/mlp.py with one rounding site dropped (or a bias
+    rounded) gives another logit for the hand-built network."""
+    import types
+    src = open(mlp.__file__).read()
+    assert before in src, "mutation site not found"
+    mod = types.ModuleType("mlp_mutant")
+    exec(compile(src.replace(before, after, 1), "mlp_mutant", "exec"), mod.__dict__)
+    z = _bf16_logit(mod.infer_bf16)
+    assert z[0] != np.float32(bf16_network.EXPECTED_LOGIT), name

@@ -10,19 +10,25 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "bml_oracle.c")
 
 MUTATIONS = [
-    ("right neighbour taken on the left", "(j + 1) % cols", "(j + cols - 1) % cols"),
-    ("top and bottom swapped",
-     "int64_t up = (i - 1 + rows) % rows, down = (i + 1) % rows;",
-     "int64_t down = (i - 1 + rows) % rows, up = (i + 1) % rows;"),
-    ("TB enters any non-TB cell", "if (top == TB && center == EMPTY) {",
-     "if (top == TB && center != TB) {"),
-    ("LR leaves into any non-LR cell", "} else if (center == LR && right == EMPTY) {",
-     "} else if (center == LR && right != LR) {"),
-    ("V phase reads the pre-H lattice",
-     "moved_tb += phase_v_rows(i, i + 1, rows, cols, tmp, cells, topology);",
-     "moved_tb += phase_v_rows(i, i + 1, rows, cols, cells, tmp, topology);"),
-    ("moved counts the arrivals twice", "                moved++;\n            } else {\n                out = center;\n            }\n            next[i * cols + j] = out;\n        }\n    }\n    return moved;\n}\n\n/* Column of the vertical neighbour",
-     "                moved += 2;\n            } else {\n                out = center;\n            }\n            next[i * cols + j] = out;\n        }\n    }\n    return moved;\n}\n\n/* Column of the vertical neighbour"),
+    ("right neighbour taken on the left", "return c + 1 < cols ? c + 1 : 0;",
+     "return c > 0 ? c - 1 : cols - 1;"),
+    ("TB cars move up instead of down",
+     "if (r + 1 < rows)\n        return (r + 1) * cols + c;\n    return topology == 1 ? cols - 1 - c : c;",
+     "if (r > 0)\n        return (r - 1) * cols + c;\n    return (rows - 1) * cols + (topology == 1 ? cols - 1 - c : c);"),
+    ("TB enters any non-TB cell", "            if (cur[dest] == EMPTY) {\n                nxt[here] = EMPTY;",
+     "            if (cur[dest] != TB) {\n                nxt[here] = EMPTY;"),
+    ("LR leaves into any non-LR cell", "            if (row[dest] == EMPTY) {",
+     "            if (row[dest] != LR) {"),
+    ("LR moves decided on the partly updated row", "            if (row[dest] == EMPTY) {",
+     "            if (out[dest] == EMPTY) {"),
+    ("V phase decides on the lattice it is updating",
+     "moved_tb += tb_moves(i, i + 1, rows, cols, tmp, cells, topology);",
+     "moved_tb += tb_moves(i, i + 1, rows, cols, cells, cells, topology);"),
+    ("V phase applied to the pre-H lattice (row copy dropped)",
+     "            memcpy(cells + i * cols, tmp + i * cols, (size_t)cols);",
+     "            (void)0;"),
+    ("moved counts each LR move twice", "                out[dest] = LR;\n                cars_moved++;",
+     "                out[dest] = LR;\n                cars_moved += 2;"),
     ("LR threshold off by a factor of two", "*thr_lr = (uint64_t)ldexp(rho * 0.5, 53);",
      "*thr_lr = (uint64_t)ldexp(rho * 0.5, 52);"),
     ("SplitMix64 shift constant", "z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
@@ -33,12 +39,12 @@ MUTATIONS = [
      "if (c == TB)\n                    b |= 1u << (31 - bit);"),
     ("stats fields swapped", "stats[4 * s + 1] = (uint32_t)moved_lr;",
      "stats[4 * s + 1] = (uint32_t)moved_tb;"),
-    ("Klein seam mirrors the top neighbour only on the torus side",
-     "uint8_t bottom = cur[down * cols + v_col(j, cols, i == rows - 1, topology)];",
-     "uint8_t bottom = cur[down * cols + j];"),
-    ("Klein seam mirrors at the wrong row",
-     "uint8_t top = cur[up * cols + v_col(j, cols, i == 0, topology)];",
-     "uint8_t top = cur[up * cols + v_col(j, cols, i == 1, topology)];"),
+    ("Klein seam glued without the reversal",
+     "return topology == 1 ? cols - 1 - c : c;\n}",
+     "return c;\n}"),
+    ("Klein seam reversal off by one column",
+     "return topology == 1 ? cols - 1 - c : c;\n}",
+     "return topology == 1 ? (cols - c) % cols : c;\n}"),
     ("Model II: the TB car obeys the coin the wrong way round",
      "if (!contested || !model2_coin(coin_seed, step, f, down, j)) {",
      "if (!contested || model2_coin(coin_seed, step, f, down, j)) {"),
