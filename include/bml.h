@@ -150,6 +150,39 @@ int bml_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream);
  * repeated handle or a mismatch, ESTATE on an invalid handle. */
 int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps);
 
+/* Allocation-free stepping, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the launches of bml_step_group on caller buffers, with no
+ * handle and no library-allocated memory.  The per-launch stats-reduction
+ * scratch lives in a static device array of the library, sized for
+ * BML_STATIC_MAX_LATTICES lattices (about 1 KiB each); each device that
+ * calls this holds its own copy until the process ends.
+ *   count        lattices, 1..BML_STATIC_MAX_LATTICES (EINVAL beyond)
+ *   rows, cols, layout  as for bml_init_rect; the same for every lattice
+ *   d_state_a/b  count device buffers each (host arrays of device
+ *                pointers): lattice i's state at step first_step is in
+ *                d_state_a[i]; the buffers ping-pong as for bml_init
+ *   d_stats      count device rings of stats_cap bml_step_stats: the counts
+ *                of global step s land in slot s % stats_cap; only the last
+ *                min(n_steps, stats_cap) steps of the call are kept
+ *   first_step   global number of the first step (for the ring slots)
+ *   t_phases     phases per kernel pass (even, 2..16), as bml_set_tuning;
+ *                strip height automatic, 4 waves per block
+ *   result_in_b  out: 1 if the states after the call are in d_state_b,
+ *                0 if in d_state_a
+ * Model of Sec. 2 on the torus.  Asynchronous on hip_stream.  The counts
+ * are written but not checked: compare n_lr / n_tb with the initial car
+ * counts to detect corruption.  Every call on one device shares that
+ * device's scratch array, so calls that overlap in time on one device (two
+ * host threads, or two streams running at once) race: serialise them.
+ * EINVAL on bad arguments, EDEVICE on a HIP failure. */
+#define BML_STATIC_MAX_LATTICES 8
+int bml_step_group_static(int32_t count, int32_t rows, int32_t cols, int32_t layout,
+                          void *const *d_state_a, void *const *d_state_b,
+                          bml_step_stats *const *d_stats, int64_t stats_cap,
+                          int64_t first_step, int64_t n_steps, int32_t t_phases,
+                          void *hip_stream, int32_t *result_in_b);
+
 /* Copy the counts of steps first_step .. first_step+count-1 (global step
  * numbers, 0 = the first step after bml_init) to out_host.  The steps must
  * have been run and still be in the ring: first_step >= steps_done -

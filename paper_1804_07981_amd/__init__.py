@@ -18,6 +18,7 @@ from ._lib import (BML_EBADARG, BML_ECORRUPT, BML_EDEVICE, BML_EINVAL,
                    bml_state_bytes, bml_state_bytes_rect, bml_init_rect, bml_stats,
                    bml_set_topology, bml_get_topology, BML_TOPO_TORUS, BML_TOPO_KLEIN,
                    bml_set_model, bml_get_model, bml_step, bml_step_count, bml_step_group, bml_copy,
+                   bml_step_group_static,
                    bml_unpack, exported_symbols, lib, library_path,
                    bml_batch_arena_bytes, bml_batch_init, bml_batch_set_tuning,
                    bml_batch_set_active, bml_batch_run, bml_batch_capture,
@@ -35,7 +36,7 @@ __all__ = [
     "BML_ECORRUPT", "BML_EBADARG", "BML_LAYOUT_U8", "BML_LAYOUT_BITPLANE",
     "STEP_STATS_DTYPE", "BmlError", "Lattice", "lib", "library_path",
     "exported_symbols", "bml_state_bytes", "bml_init", "bml_step", "bml_stats",
-    "bml_step_group", "step_group", "bml_copy", "bml_state_bytes_rect", "bml_init_rect",
+    "bml_step_group", "step_group", "bml_step_group_static", "bml_copy", "bml_state_bytes_rect", "bml_init_rect",
     "bml_set_topology", "bml_get_topology", "BML_TOPO_TORUS", "BML_TOPO_KLEIN",
     "bml_set_model", "bml_get_model",
     "bml_get_cells", "bml_initial_counts", "bml_set_tuning", "bml_get_tuning",

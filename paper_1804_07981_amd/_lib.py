@@ -55,6 +55,9 @@ _SIGNATURES = {
                        _vp, _i64, _vp], ctypes.c_int),
     "bml_step": ([_vp, _i64], ctypes.c_int),
     "bml_step_group": ([ctypes.POINTER(_vp), _i32, _i64], ctypes.c_int),
+    "bml_step_group_static": ([_i32, _i32, _i32, _i32, ctypes.POINTER(_vp),
+                               ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i64, _i64, _i64,
+                               _i32, _vp, ctypes.POINTER(_i32)], ctypes.c_int),
     "bml_copy": ([_vp, _vp, _sz, _vp], ctypes.c_int),
     "bml_stats": ([_vp, _i64, _i64, _vp], ctypes.c_int),
     "bml_get_cells": ([_vp, _vp], ctypes.c_int),
@@ -227,6 +230,23 @@ def bml_step_group(handles, n_steps: int) -> None:
     joint launches."""
     arr = (_vp * len(handles))(*[int(h) for h in handles])
     _check(lib().bml_step_group(arr, len(handles), n_steps))
+
+
+def bml_step_group_static(rows: int, cols: int, layout: int, d_state_a, d_state_b, d_stats,
+                          stats_cap: int, first_step: int, n_steps: int, t_phases: int,
+                          stream=None) -> int:
+    """Allocation-free stepping of len(d_state_a) lattices (lists of device
+    buffers, one per lattice); returns 1 if the results are in the d_state_b
+    buffers, 0 if in d_state_a."""
+    count = len(d_state_a)
+    if len(d_state_b) != count or len(d_stats) != count:
+        raise BmlError(BML_EINVAL, "one state pair and one stats ring per lattice")
+    arr = lambda xs: (_vp * count)(*[_ptr(x) for x in xs])  # noqa: E731
+    out = _i32()
+    _check(lib().bml_step_group_static(count, rows, cols, layout, arr(d_state_a), arr(d_state_b),
+                                       arr(d_stats), stats_cap, first_step, n_steps, t_phases,
+                                       _stream_ptr(stream), ctypes.byref(out)))
+    return int(out.value)
 
 
 def bml_stats(handle: int, first_step: int, count: int, check: bool = True) -> np.ndarray:

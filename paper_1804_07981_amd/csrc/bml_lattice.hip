@@ -949,6 +949,126 @@ int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps)
     return step_group(handles, count, n_steps);
 }
 
+} // extern "C"
+
+// ============================================================================
+// Allocation-free stepping
+// ============================================================================
+
+namespace bml {
+
+// Stats-reduction scratch of bml_step_group_static: one PassScratch per
+// lattice of a call, in device memory the library never allocates.  In
+// host code this name is a host-side stand-in, not a device address; the
+// device address is looked up once per device and only that pointer is
+// passed to kernels.  Each device holds its own copy until the process ends.
+constexpr int STATIC_MAX_LATTICES = BML_STATIC_MAX_LATTICES;
+static_assert(STATIC_MAX_LATTICES <= MAX_GROUP, "a launch advances at most MAX_GROUP lattices");
+static __device__ __align__(256) PassScratch scratch[STATIC_MAX_LATTICES];
+
+constexpr int STATIC_MAX_DEVICES = 64;
+
+// Device address of `scratch` on the current device (looked up on the
+// first call on that device, with that device current).
+static int static_scratch(PassScratch **out)
+{
+    static std::mutex mu;
+    static PassScratch *addr[STATIC_MAX_DEVICES] = {};
+    int dev = 0;
+    BML_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES)
+        return fail(BML_EDEVICE, "device %d: the static scratch table holds %d devices", dev,
+                    STATIC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(BML_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        addr[dev] = (PassScratch *)p;
+    }
+    *out = addr[dev];
+    return BML_OK;
+}
+
+} // namespace bml
+
+extern "C" {
+
+int bml_step_group_static(int32_t count, int32_t rows, int32_t cols, int32_t layout,
+                          void *const *d_state_a, void *const *d_state_b,
+                          bml_step_stats *const *d_stats, int64_t stats_cap,
+                          int64_t first_step, int64_t n_steps, int32_t t_phases,
+                          void *hip_stream, int32_t *result_in_b)
+{
+    clear_error();
+    if (count < 1 || count > STATIC_MAX_LATTICES)
+        return fail(BML_EINVAL, "count=%d: the static scratch holds 1 to %d lattices", count,
+                    STATIC_MAX_LATTICES);
+    size_t bytes = 0;
+    int rc = bml_state_bytes_rect(rows, cols, layout, &bytes);
+    if (rc)
+        return rc;
+    if (!d_state_a || !d_state_b || !d_stats || !result_in_b)
+        return fail(BML_EINVAL, "NULL argument");
+    if (stats_cap < 1 || stats_cap > 0x7fffffff)
+        return fail(BML_EINVAL, "stats_cap=%lld must be in [1, 2^31-1]", (long long)stats_cap);
+    if (first_step < 0 || n_steps < 0)
+        return fail(BML_EINVAL, "first_step and n_steps must be >= 0");
+    if (t_phases < 2 || t_phases > 2 * MAX_K || t_phases % 2)
+        return fail(BML_EINVAL, "t_phases=%d must be even in [2, %d]", t_phases, 2 * MAX_K);
+    for (int i = 0; i < count; ++i) {
+        if (!d_state_a[i] || !d_state_b[i] || !d_stats[i])
+            return fail(BML_EINVAL, "lattice %d: NULL buffer", i);
+        if (!aligned256(d_state_a[i]) || !aligned256(d_state_b[i]) || !aligned256(d_stats[i]))
+            return fail(BML_EINVAL, "lattice %d: device buffers must be 256-byte aligned", i);
+        const uintptr_t a = (uintptr_t)d_state_a[i], b = (uintptr_t)d_state_b[i];
+        if (a < b + bytes && b < a + bytes)
+            return fail(BML_EINVAL, "lattice %d: state buffers overlap", i);
+    }
+    *result_in_b = 0;
+    if (n_steps == 0)
+        return BML_OK;
+    PassScratch *ptr = nullptr;
+    if ((rc = static_scratch(&ptr)))
+        return rc;
+    // Host-side descriptors only (no device memory): the same launches as
+    // bml_step_group with the automatic strip height and 4 waves per block.
+    bml_lattice lats[STATIC_MAX_LATTICES];
+    bml_lattice *G[STATIC_MAX_LATTICES];
+    DeviceInfo dev;
+    if ((rc = device_info(&dev)))
+        return rc;
+    for (int i = 0; i < count; ++i) {
+        bml_lattice &L = lats[i];
+        L.rows = rows;
+        L.cols = cols;
+        L.layout = layout;
+        L.buf[0] = d_state_a[i];
+        L.buf[1] = d_state_b[i];
+        L.stats = (uint32_t *)d_stats[i];
+        L.cap = stats_cap;
+        L.stream = (hipStream_t)hip_stream;
+        L.steps_done = first_step;
+        L.t_phases = t_phases;
+        L.tile_rows = 0;
+        L.wpb = 4;
+        L.dev = dev;
+        L.d_scratch = ptr + i;
+        G[i] = &L;
+    }
+    // The reduction needs its scratch at zero; the array keeps whatever the
+    // last call (possibly one that failed mid-way) left there.
+    if ((rc = launch_zero((uint32_t *)ptr, (int64_t)count * sizeof(PassScratch) / 4,
+                          (hipStream_t)hip_stream)))
+        return rc;
+    if ((rc = step_group(G, count, n_steps)))
+        return rc;
+    *result_in_b = lats[0].cur;
+    return BML_OK;
+}
+
 int bml_stats(bml_lattice *L, int64_t first_step, int64_t count, bml_step_stats *out_host)
 {
     clear_error();
