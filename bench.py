@@ -304,12 +304,16 @@ def cpu_baseline(lt, target_s: float = 10.0, model: int = 1, coin_seed: int = 0)
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
-def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample) -> dict:
+def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample,
+                  resident_max_n: int = 1024) -> dict:
     """512 lattices of uneven N and rho, 4096 steps each, in one batch: a
     captured 512-step graph replayed 8 times (mean of `steps` timed runs
     after `warmup`); against plain per-lattice runs through the
     single-lattice API (all lattices, or an evenly spaced sample scaled to
-    all by cell count)."""
+    all by cell count; plain_sample=0 skips them).  resident_max_n: the
+    batch's register-resident limit (1024: every lattice of the sweep stays
+    in registers, one launch per replay; 0: the streaming kernel, one launch
+    per pass)."""
     import numpy as np
     import torch
     wl = workloads.SWEEP
@@ -324,6 +328,8 @@ def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample) -> d
         with B.Batch(ns, rhos, seeds, layout=1, trace_steps=wl.steps, device=dev) as bt:
             if tun:
                 bt.set_tuning(*tun)
+            bt.set_resident(resident_max_n)
+            resident = bt.resident
             bt.capture(chunk)
             bt.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -337,6 +343,16 @@ def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample) -> d
                 times.append(e0.elapsed_time(e1) / 1e3)
             bt.check()
     batch_s = float(np.mean(times))
+    gcups = cells * wl.steps / batch_s / 1e9
+    out = {"workload": wl.name, "lattices": len(ns), "steps_per_lattice": wl.steps,
+           "graph_steps": chunk, "kernel": "resident_kernel (registers, one launch per "
+           "replay)" if resident else "batch_kernel (streaming, one launch per pass)",
+           "tuning": None if resident else tun, "gcups": gcups, "batched_wall_s": batch_s,
+           # the sweep's lattices live in registers / on-chip caches; the
+           # rule's bit operations bound it
+           "roofline": alu_roofline(1, 1, gcups)}
+    if plain_sample == 0:
+        return out
     idx = list(range(len(ns))) if plain_sample is None else list(
         np.linspace(0, len(ns) - 1, plain_sample).astype(int))
     torch.cuda.synchronize()
@@ -349,19 +365,15 @@ def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample) -> d
         plain_cells += float(ns[b]) ** 2
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) * (cells / plain_cells)
-    gcups = cells * wl.steps / batch_s / 1e9
-    return {"workload": wl.name, "lattices": len(ns), "steps_per_lattice": wl.steps,
-            "graph_steps": chunk, "tuning": tun, "gcups": gcups,
-            "batched_wall_s": batch_s, "plain_per_lattice_wall_s": plain_s,
-            "plain_measured_lattices": len(idx), "gain": plain_s / batch_s,
-            # the sweep's lattices live in on-chip caches; the rule's bit
-            # operations bound it
-            "roofline": alu_roofline(1, 1, gcups)}
+    out.update({"plain_per_lattice_wall_s": plain_s, "plain_measured_lattices": len(idx),
+                "gain": plain_s / batch_s})
+    return out
 
 
 def bench_sweep(args, B, workloads, dev) -> int:
     """The density sweep as its own benchmark line (GCUPS of the batch)."""
-    sw = sweep_measure(B, workloads, dev, args.steps, args.warmup, args.plain_sample)
+    sw = sweep_measure(B, workloads, dev, args.steps, args.warmup, args.plain_sample,
+                       resident_max_n=args.resident_max_n)
     out = {"metric": "GCUPS (cell updates/s); density-sweep time vs plain",
            "value": round(sw["gcups"], 1),
            "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -370,9 +382,11 @@ def bench_sweep(args, B, workloads, dev) -> int:
            "data": "synthetic (SplitMix64 iid lattices)",
            "config": {"workload": sw["workload"], "lattices": sw["lattices"],
                       "steps_per_lattice": sw["steps_per_lattice"],
-                      "graph_steps": sw["graph_steps"], "tuning": sw["tuning"]},
-           "sweep": {k: sw[k] for k in ("batched_wall_s", "plain_per_lattice_wall_s",
-                                        "plain_measured_lattices", "gain")}}
+                      "graph_steps": sw["graph_steps"], "kernel": sw["kernel"],
+                      "tuning": sw["tuning"]},
+           "roofline": sw["roofline"],
+           "sweep": {k: sw.get(k) for k in ("batched_wall_s", "plain_per_lattice_wall_s",
+                                            "plain_measured_lattices", "gain")}}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -524,6 +538,9 @@ def main() -> int:
                     help="sweep/early-exit: time plain per-lattice runs on this many "
                          "lattices and scale to all")
     ap.add_argument("--layout", choices=["u8", "bitplane"], default="u8")
+    ap.add_argument("--resident-max-n", type=int, default=1024,
+                    help="sweep: the batch's register-resident limit (0: the streaming "
+                         "kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the secondary measurements")
@@ -694,6 +711,9 @@ def main() -> int:
         # in one captured graph against plain per-lattice runs (64 of them
         # timed, scaled to all 512 by cell count)
         out["density_sweep"] = sweep_measure(B, workloads, dev, 1, 1, 64)
+        st = sweep_measure(B, workloads, dev, 1, 1, 0, resident_max_n=0)
+        out["density_sweep"]["streaming"] = {k: st[k] for k in ("kernel", "tuning", "gcups",
+                                                                "batched_wall_s", "roofline")}
         out["early_exit"] = early_exit_block()
 
     if not args.no_cpu_baseline:

@@ -304,6 +304,20 @@ int bml_batch_init(bml_batch **out, int32_t count, const int32_t *n, const doubl
 int bml_batch_set_tuning(bml_batch *B, int32_t strip_rows, int32_t t_phases,
                          int32_t waves_per_block);
 
+/* Register-resident runs.  When every lattice of the batch has N <= max_n
+ * (max_n in [0, 1024]; 0 = never; the default is 1024), a run is one kernel
+ * launch in which each lattice lives in the registers of one workgroup for
+ * all its steps: one row per lane, the horizontal phase inside the lane,
+ * the vertical phase through neighbouring lanes and, across wavefronts,
+ * through LDS, one barrier per step.  The state is read once at the start
+ * of the run and written once at the end.  Otherwise the streaming kernel
+ * runs, one launch per pass of t_phases/2 steps (bml_batch_set_tuning).
+ * Results are identical either way.  Drops a captured graph.  Synchronises.
+ * bml_batch_get_resident: 1 if runs are register-resident, 0 if streaming,
+ * < 0 on error. */
+int bml_batch_set_resident(bml_batch *B, int32_t max_n);
+int bml_batch_get_resident(const bml_batch *B);
+
 /* active_host: `count` bytes, non-zero = the lattice advances in later runs
  * (NULL = all).  Inactive lattices keep their state.  Synchronises. */
 int bml_batch_set_active(bml_batch *B, const uint8_t *active_host);

@@ -21,7 +21,8 @@ from ._lib import (BML_EBADARG, BML_ECORRUPT, BML_EDEVICE, BML_EINVAL,
                    bml_step_group_static,
                    bml_unpack, exported_symbols, lib, library_path,
                    bml_batch_arena_bytes, bml_batch_init, bml_batch_set_tuning,
-                   bml_batch_set_active, bml_batch_run, bml_batch_capture,
+                   bml_batch_set_active, bml_batch_set_resident, bml_batch_get_resident,
+                   bml_batch_run, bml_batch_capture,
                    bml_batch_replay, bml_batch_step_count, bml_batch_lattice_steps,
                    bml_batch_initial_counts, bml_batch_get_cells, bml_batch_check,
                    bml_batch_free, bml_features, bml_trace_frozen, bml_trace_mobility,
@@ -42,7 +43,8 @@ __all__ = [
     "bml_get_cells", "bml_initial_counts", "bml_set_tuning", "bml_get_tuning",
     "bml_step_count", "bml_current_state", "bml_free", "bml_last_error",
     "bml_pack", "bml_unpack", "Batch", "bml_batch_arena_bytes", "bml_batch_init",
-    "bml_batch_set_tuning", "bml_batch_set_active", "bml_batch_run", "bml_batch_capture",
+    "bml_batch_set_tuning", "bml_batch_set_active", "bml_batch_set_resident",
+    "bml_batch_get_resident", "bml_batch_run", "bml_batch_capture",
     "bml_batch_replay", "bml_batch_step_count", "bml_batch_lattice_steps",
     "bml_batch_initial_counts", "bml_batch_get_cells", "bml_batch_check", "bml_batch_free",
     "bml_features", "bml_trace_frozen", "bml_trace_mobility", "bml_feature_stats",

@@ -35,6 +35,15 @@ class Batch:
     def set_tuning(self, strip_rows: int = 0, t_phases: int = 0, waves_per_block: int = 0):
         B.bml_batch_set_tuning(self.handle, strip_rows, t_phases, waves_per_block)
 
+    def set_resident(self, max_n: int):
+        """Register-resident runs when every lattice has N <= max_n (at most
+        1024; 0 = always the streaming kernel)."""
+        B.bml_batch_set_resident(self.handle, max_n)
+
+    @property
+    def resident(self) -> bool:
+        return B.bml_batch_get_resident(self.handle) == 1
+
     def set_active(self, active=None):
         B.bml_batch_set_active(self.handle, active)
 

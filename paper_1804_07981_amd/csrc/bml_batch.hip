@@ -13,6 +13,7 @@
 #include "bml.h"
 #include "bml_batch.hpp"
 #include "bml_common.hpp"
+#include "bml_resident.hpp"
 
 namespace bml {
 
@@ -28,6 +29,17 @@ struct BatchTable {
 static const BatchTable &batch_kernels()
 {
     static BatchTable t;
+    return t;
+}
+
+struct ResidentTable {
+    ResidentFn fn[2] = {};
+    ResidentTable() { resident_kernels(&fn[IO_U8], &fn[IO_BP]); }
+};
+
+static const ResidentTable &resident_table()
+{
+    static ResidentTable t;
     return t;
 }
 
@@ -64,11 +76,16 @@ struct bml_batch {
     int64_t trace_steps = 0;
     hipStream_t stream = nullptr;
     int32_t strip_target = 64, t_phases = 16, wpb = 4;
+    // Register-resident runs (bml_resident.hpp) when every lattice has
+    // N <= resident_max_n (at most 32 * RES_MAX_WORDS; 0 = never).
+    int32_t resident_max_n = 32 * RES_MAX_WORDS;
+    int32_t res_grid = 0;                   // bins per resident launch (fixed while captured)
     int64_t host_step = 0, host_pass = 0;
     DeviceInfo dev;
     // Library-owned device memory.
     BatchLattice *d_lat = nullptr;
     BatchItem *d_items = nullptr;
+    ResidentBin *d_bins = nullptr;
     BatchCounters *d_ctr = nullptr;
     unsigned long long *d_counts = nullptr;
     uint8_t *d_stage = nullptr;   // bitplane read-back staging, stage_bytes
@@ -101,6 +118,8 @@ static void batch_release(bml_batch *B)
         (void)hipFree(B->d_lat);
     if (B->d_items)
         (void)hipFree(B->d_items);
+    if (B->d_bins)
+        (void)hipFree(B->d_bins);
     if (B->d_ctr)
         (void)hipFree(B->d_ctr);
     if (B->d_counts)
@@ -131,6 +150,47 @@ static void lattice_geometry(const bml_batch *B, int b, int *H, int *groups, int
         *groups = 1;
         *tiles_x = (words + TILE_WORDS - 1) / TILE_WORDS;
     }
+}
+
+// True when the batch runs register-resident: every lattice (active or not,
+// so the mode does not change as lattices retire) fits.
+static bool use_resident(const bml_batch *B)
+{
+    if (B->resident_max_n <= 0)
+        return false;
+    const int nmax = *std::max_element(B->n.begin(), B->n.end());
+    return nmax <= std::min(B->resident_max_n, 32 * RES_MAX_WORDS);
+}
+
+// Bins of the resident kernel: the lattices flagged in `on`, grouped by
+// width, as many per bin as its 16 waves hold (ceil(W / 2) waves each),
+// the most expensive bins first so that they start first.
+static std::vector<ResidentBin> resident_bins(const bml_batch *B, const std::vector<uint8_t> &on)
+{
+    std::vector<ResidentBin> bins;
+    for (int W = 1; W <= RES_MAX_WORDS; ++W) {
+        const int per_bin = std::min(RES_MAX_LAT, RES_WAVES / ((W + 1) / 2));
+        ResidentBin cur{};
+        cur.words = W;
+        for (int b = 0; b < B->count; ++b) {
+            if (!on[b] || B->n[b] != 32 * W)
+                continue;
+            cur.lat[cur.n_lat++] = b;
+            if (cur.n_lat == per_bin) {
+                bins.push_back(cur);
+                cur = ResidentBin{};
+                cur.words = W;
+            }
+        }
+        if (cur.n_lat)
+            bins.push_back(cur);
+    }
+    auto cost = [](const ResidentBin &x) {
+        return (int64_t)x.words * x.n_lat * ((x.words + 1) / 2);
+    };
+    std::stable_sort(bins.begin(), bins.end(),
+                     [&](const ResidentBin &x, const ResidentBin &y) { return cost(x) > cost(y); });
+    return bins;
 }
 
 // Uploads the descriptors and the item list of the active lattices.
@@ -170,6 +230,27 @@ static int upload_work(bml_batch *B)
             return fail(BML_EDEVICE, "hipMalloc of the batch item list failed");
         B->items_cap = (int64_t)items.size();
     }
+    if (use_resident(B)) {
+        // The launch grid is the bin count with every lattice active, so a
+        // captured run stays valid as lattices retire: the bins of the
+        // active lattices come first, padding bins (no lattice) after.
+        if (B->res_grid == 0) {
+            const std::vector<uint8_t> all(B->count, 1);
+            B->res_grid = std::max<int32_t>(1, (int32_t)resident_bins(B, all).size());
+            if (B->d_bins)
+                (void)hipFree(B->d_bins);
+            B->d_bins = nullptr;
+            if (hipMalloc(&B->d_bins, (size_t)B->res_grid * sizeof(ResidentBin)) != hipSuccess) {
+                B->d_bins = nullptr;
+                B->res_grid = 0;
+                return fail(BML_EDEVICE, "hipMalloc of the resident bin list failed");
+            }
+        }
+        std::vector<ResidentBin> bins = resident_bins(B, B->active);
+        bins.resize(B->res_grid, ResidentBin{1, 0, {}});
+        BML_HIP(hipMemcpyAsync(B->d_bins, bins.data(), bins.size() * sizeof(ResidentBin),
+                               hipMemcpyHostToDevice, B->stream));
+    }
     BML_HIP(hipMemcpyAsync(B->d_lat, lat.data(), lat.size() * sizeof(BatchLattice),
                            hipMemcpyHostToDevice, B->stream));
     if (!items.empty())
@@ -203,7 +284,7 @@ __global__ void zero_trace_kernel(uint32_t *trace, int32_t count, int64_t trace_
     }
 }
 
-static int resident_batch_blocks(int io, int k, int threads, int *out)
+static int batch_blocks_per_cu(int io, int k, int threads, int *out)
 {
     static std::mutex mu;
     static int cache[8][2][MAX_K + 1][3];
@@ -235,13 +316,36 @@ static int enqueue_run(bml_batch *B, int64_t n_steps, int64_t *passes)
     hipLaunchKernelGGL(zero_trace_kernel, dim3(zgrid), dim3(256), 0, B->stream, B->trace,
                        B->count, B->trace_steps, B->d_ctr, n_steps);
     BML_HIP(hipGetLastError());
+    if (use_resident(B)) {
+        // One launch runs every step (up to 2^30 per launch): the states
+        // stay in registers throughout.
+        const ResidentFn fn = resident_table().fn[io];
+        int64_t s = 0, p = 0;
+        while (s < n_steps) {
+            const int64_t k = std::min<int64_t>(n_steps - s, (int64_t)1 << 30);
+            ResidentArgs a;
+            a.lat = B->d_lat;
+            a.bins = B->d_bins;
+            a.ctr = B->d_ctr;
+            a.trace = B->trace;
+            a.trace_steps = (int32_t)B->trace_steps;
+            a.n_steps = (int32_t)k;
+            hipLaunchKernelGGL(fn, dim3((unsigned)B->res_grid), dim3(64 * RES_WAVES), 0,
+                               B->stream, a);
+            BML_HIP(hipGetLastError());
+            s += k;
+            ++p;
+        }
+        *passes = p;
+        return BML_OK;
+    }
     const int K = B->t_phases / 2;
     const int threads = 64 * B->wpb;
     int64_t s = 0, p = 0;
     while (s < n_steps) {
         const int k = (int)std::min<int64_t>(K, n_steps - s);
         int per_cu = 1;
-        int rc = resident_batch_blocks(io, k, threads, &per_cu);
+        int rc = batch_blocks_per_cu(io, k, threads, &per_cu);
         if (rc)
             return rc;
         int64_t grid = (int64_t)per_cu * B->dev.cu_count;
@@ -423,6 +527,32 @@ int bml_batch_set_tuning(bml_batch *B, int32_t strip_rows, int32_t t_phases,
     return upload_work(B);
 }
 
+int bml_batch_set_resident(bml_batch *B, int32_t max_n)
+{
+    clear_error();
+    if (!batch_live(B))
+        return fail(BML_ESTATE, "invalid batch handle");
+    if (max_n < 0 || max_n > 32 * RES_MAX_WORDS)
+        return fail(BML_EINVAL, "max_n=%d must be in [0, %d]", max_n, 32 * RES_MAX_WORDS);
+    B->resident_max_n = max_n;
+    B->res_grid = 0;
+    if (B->graph_exec) {
+        (void)hipGraphExecDestroy(B->graph_exec);
+        (void)hipGraphDestroy(B->graph);
+        B->graph_exec = nullptr;
+        B->graph = nullptr;
+    }
+    return upload_work(B);
+}
+
+int bml_batch_get_resident(const bml_batch *B)
+{
+    clear_error();
+    if (!batch_live(B))
+        return fail(BML_ESTATE, "invalid batch handle");
+    return use_resident(B) ? 1 : 0;
+}
+
 int bml_batch_set_active(bml_batch *B, const uint8_t *active_host)
 {
     clear_error();
@@ -476,7 +606,7 @@ int bml_batch_capture(bml_batch *B, int64_t n_steps)
     const int io = B->layout == BML_LAYOUT_U8 ? IO_U8 : IO_BP;
     for (int k = 1; k <= MAX_K; ++k) {
         int nb;
-        int rc = resident_batch_blocks(io, k, 64 * B->wpb, &nb);
+        int rc = batch_blocks_per_cu(io, k, 64 * B->wpb, &nb);
         if (rc)
             return rc;
     }

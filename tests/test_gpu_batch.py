@@ -169,3 +169,122 @@ def test_batch_errors(B):
         assert bt.lattice_steps(0) == 20
         want, _ = oracle.run(oracle.init_cells(64, 1, 0.3), 20)
         assert np.array_equal(bt.cells(0), want)
+
+
+# --- register-resident runs (one launch per run, lattices in VGPRs) ---------
+
+# every width W = N / 32 from 1 to 32 (odd W: a half wavefront at the
+# bottom of each lattice), twice, plus 17 lattices of 64 x 64 (more than the
+# 16 one-wave lattices a workgroup holds)
+EVERY_WIDTH = [32 * w for w in range(1, 33)] * 2 + [64] * 17
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_resident_every_width(B, layout):
+    rng = np.random.default_rng(77 + layout)
+    ns = EVERY_WIDTH
+    rhos = [float(x) for x in rng.uniform(0.1, 0.7, len(ns))]
+    seeds = [int(x) for x in rng.integers(0, 2**40, len(ns))]
+    steps = 37
+    say(f"resident every width layout={layout} lattices={len(ns)} steps={steps}")
+    want, wst = oracle_runs(ns, rhos, seeds, steps)
+    with B.Batch(ns, rhos, seeds, layout=layout, trace_steps=64) as bt:
+        assert bt.resident
+        bt.run(steps)
+        check_batch(bt, ns, want, wst)
+        assert all(bt.lattice_steps(b) == steps for b in range(len(ns)))
+
+
+def test_resident_and_streaming_agree_in_runs(B):
+    """Runs of several lengths alternate between the register-resident and
+    the streaming kernel on the same batch; the result is the oracle's."""
+    ns = [96, 352, 608, 1024, 736]
+    rhos = [0.33, 0.38, 0.29, 0.41, 0.36]
+    seeds = [11, 12, 13, 14, 15]
+    runs = [(1024, 9), (0, 14), (1024, 1), (0, 3), (1024, 30)]
+    total = sum(k for _, k in runs)
+    want, wst = oracle_runs(ns, rhos, seeds, total)
+    with B.Batch(ns, rhos, seeds, trace_steps=total) as bt:
+        for max_n, k in runs:
+            bt.set_resident(max_n)
+            assert bt.resident == (max_n >= 1024)
+            bt.run(k)
+        check_batch(bt, ns, want, wst)
+
+
+def test_resident_mode_boundary(B):
+    """The mode follows the largest lattice: 1024 runs resident, 1056 does
+    not; a lower limit switches a batch back to streaming.  Both sides match
+    the oracle."""
+    for ns, limit, resident in (([1024, 64], 1024, True), ([1056, 64], 1024, False),
+                                ([544, 512], 512, False), ([512, 480], 512, True)):
+        rhos = [0.35] * len(ns)
+        seeds = [3, 4]
+        want, wst = oracle_runs(ns, rhos, seeds, 11)
+        with B.Batch(ns, rhos, seeds, trace_steps=16) as bt:
+            bt.set_resident(limit)
+            assert bt.resident == resident, (ns, limit)
+            bt.run(11)
+            check_batch(bt, ns, want, wst)
+    with B.Batch([64], [0.3], [1], trace_steps=8) as bt:
+        for bad in (-1, 1056):
+            with pytest.raises(B.BmlError) as e:
+                bt.set_resident(bad)
+            assert e.value.code == B.BML_EINVAL
+
+
+def test_resident_graph_with_retired_lattices(B):
+    """A captured resident run keeps its grid while lattices retire: the
+    active ones are re-binned, the rest padded.  Replays, eager runs and an
+    empty active set all match the oracle."""
+    ns = [64] * 20 + [96, 96, 480, 1024, 992]
+    rng = np.random.default_rng(5)
+    rhos = [float(x) for x in rng.uniform(0.2, 0.5, len(ns))]
+    seeds = list(range(100, 100 + len(ns)))
+    per = 16
+    with B.Batch(ns, rhos, seeds, trace_steps=128) as bt:
+        assert bt.resident
+        bt.capture(per)
+        bt.replay()
+        active = [1 if (b % 3) else 0 for b in range(len(ns))]
+        bt.set_active(active)
+        bt.replay()
+        bt.set_active([0] * len(ns))
+        bt.replay()                      # nothing active: states unchanged
+        bt.set_active(None)
+        bt.run(5)
+        bt.synchronize()
+        steps = [per + (per if active[b] else 0) + 5 for b in range(len(ns))]
+        tr = bt.trace()
+        for b in range(len(ns)):
+            assert bt.lattice_steps(b) == steps[b]
+            want, wst = oracle.run(oracle.init_cells(ns[b], seeds[b], rhos[b]), steps[b])
+            assert np.array_equal(bt.cells(b), want), b
+            assert np.array_equal(tr[b, :per, 0], wst[:per, 1]), b
+            assert np.array_equal(tr[b, :per, 1], wst[:per, 3]), b
+            if active[b]:
+                assert np.array_equal(tr[b, per:2 * per, 0], wst[per:2 * per, 1]), b
+                assert np.array_equal(tr[b, per:2 * per, 1], wst[per:2 * per, 3]), b
+            else:
+                assert (tr[b, per:2 * per] == 0).all(), b
+            assert (tr[b, 2 * per:3 * per] == 0).all(), b
+            assert np.array_equal(tr[b, 3 * per:3 * per + 5, 0], wst[-5:, 1]), b
+        bt.check()
+
+
+def test_resident_density_extremes(B):
+    """Empty, nearly empty (single cars crossing every wavefront boundary
+    and the periodic edges), nearly full and full lattices, with wide and
+    narrow rows and half-wavefront bottoms."""
+    ns, rhos = [], []
+    for n in (1024, 992, 96, 32, 64):
+        for rho in (0.0, 0.002, 0.95, 1.0):
+            ns.append(n)
+            rhos.append(rho)
+    seeds = list(range(len(ns)))
+    steps = 150
+    want, wst = oracle_runs(ns, rhos, seeds, steps)
+    with B.Batch(ns, rhos, seeds, trace_steps=steps) as bt:
+        assert bt.resident
+        bt.run(steps)
+        check_batch(bt, ns, want, wst)
