@@ -119,6 +119,17 @@ def load_tuning(layout: int, n, group: str | None = None, model: int = 1):
     return None
 
 
+def load_resident_split(group: str) -> int:
+    """Autotuned slab halo of the register-resident batch kernel for a
+    batch (0: whole lattices) from the tuning cache, else 0."""
+    path = os.path.join(ROOT, "paper_1804_07981_amd", "tune_cache.json")
+    try:
+        with open(path) as f:
+            return int(json.load(f).get(f"gfx950/resident/{group}", {}).get("split", 0))
+    except (OSError, ValueError, AttributeError):
+        return 0
+
+
 def traffic_from_profile(name: str, tuning, launches_bytes: float, profiles: str = PROFILES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source with the same tuning; else
@@ -305,15 +316,16 @@ def cpu_baseline(lt, target_s: float = 10.0, model: int = 1, coin_seed: int = 0)
 
 
 def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample,
-                  resident_max_n: int = 1024) -> dict:
+                  resident_max_n: int = 1024, split: int | None = None) -> dict:
     """512 lattices of uneven N and rho, 4096 steps each, in one batch: a
     captured 512-step graph replayed 8 times (mean of `steps` timed runs
     after `warmup`); against plain per-lattice runs through the
     single-lattice API (all lattices, or an evenly spaced sample scaled to
     all by cell count; plain_sample=0 skips them).  resident_max_n: the
     batch's register-resident limit (1024: every lattice of the sweep stays
-    in registers, one launch per replay; 0: the streaming kernel, one launch
-    per pass)."""
+    in registers; 0: the streaming kernel, one launch per pass); split: the
+    resident slab halo (0: whole lattices, one launch per replay; None: the
+    autotuned value)."""
     import numpy as np
     import torch
     wl = workloads.SWEEP
@@ -323,12 +335,14 @@ def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample,
     cells = float(np.sum(np.asarray(ns, dtype=np.float64) ** 2))
     chunk = 512
     tun = load_tuning(1, "sweep512")
+    if split is None:
+        split = load_resident_split("sweep512")
     times = []
     for rep in range(warmup + steps):
         with B.Batch(ns, rhos, seeds, layout=1, trace_steps=wl.steps, device=dev) as bt:
             if tun:
                 bt.set_tuning(*tun)
-            bt.set_resident(resident_max_n)
+            bt.set_resident(resident_max_n, split)
             resident = bt.resident
             bt.capture(chunk)
             bt.synchronize()
@@ -345,9 +359,12 @@ def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample,
     batch_s = float(np.mean(times))
     gcups = cells * wl.steps / batch_s / 1e9
     out = {"workload": wl.name, "lattices": len(ns), "steps_per_lattice": wl.steps,
-           "graph_steps": chunk, "kernel": "resident_kernel (registers, one launch per "
-           "replay)" if resident else "batch_kernel (streaming, one launch per pass)",
-           "tuning": None if resident else tun, "gcups": gcups, "batched_wall_s": batch_s,
+           "graph_steps": chunk,
+           "kernel": ("resident_kernel (registers, " + (f"slabs with {split} halo rows, "
+                      f"launches of {split} steps)" if split else "one launch per replay)"))
+           if resident else "batch_kernel (streaming, one launch per pass)",
+           "tuning": {"resident_split": split} if resident else tun, "gcups": gcups,
+           "batched_wall_s": batch_s,
            # the sweep's lattices live in registers / on-chip caches; the
            # rule's bit operations bound it
            "roofline": alu_roofline(1, 1, gcups)}
@@ -373,7 +390,7 @@ def sweep_measure(B, workloads, dev, steps: int, warmup: int, plain_sample,
 def bench_sweep(args, B, workloads, dev) -> int:
     """The density sweep as its own benchmark line (GCUPS of the batch)."""
     sw = sweep_measure(B, workloads, dev, args.steps, args.warmup, args.plain_sample,
-                       resident_max_n=args.resident_max_n)
+                       resident_max_n=args.resident_max_n, split=args.split)
     out = {"metric": "GCUPS (cell updates/s); density-sweep time vs plain",
            "value": round(sw["gcups"], 1),
            "unit": "GCUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -541,6 +558,9 @@ def main() -> int:
     ap.add_argument("--resident-max-n", type=int, default=1024,
                     help="sweep: the batch's register-resident limit (0: the streaming "
                          "kernel)")
+    ap.add_argument("--split", type=int, default=None,
+                    help="sweep: the resident slab halo (0: whole lattices; default: "
+                         "autotuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the secondary measurements")

@@ -305,17 +305,23 @@ int bml_batch_set_tuning(bml_batch *B, int32_t strip_rows, int32_t t_phases,
                          int32_t waves_per_block);
 
 /* Register-resident runs.  When every lattice of the batch has N <= max_n
- * (max_n in [0, 1024]; 0 = never; the default is 1024), a run is one kernel
- * launch in which each lattice lives in the registers of one workgroup for
- * all its steps: one row per lane, the horizontal phase inside the lane,
- * the vertical phase through neighbouring lanes and, across wavefronts,
- * through LDS, one barrier per step.  The state is read once at the start
- * of the run and written once at the end.  Otherwise the streaming kernel
- * runs, one launch per pass of t_phases/2 steps (bml_batch_set_tuning).
- * Results are identical either way.  Drops a captured graph.  Synchronises.
- * bml_batch_get_resident: 1 if runs are register-resident, 0 if streaming,
- * < 0 on error. */
-int bml_batch_set_resident(bml_batch *B, int32_t max_n);
+ * (max_n in [0, 1024]; 0 = never; the default is 1024), runs use a kernel
+ * in which the lattices live in the registers of workgroups for many
+ * steps: two rows per lane, the horizontal phase inside the lane, the
+ * vertical phase through the lane's two rows, neighbouring lanes and,
+ * across wavefronts, LDS, one barrier per step.  A workgroup holds up to
+ * 512 rows; a taller lattice is cut into the fewest slabs of rows that
+ * fit one, each held with K halo rows above and below in a workgroup of its
+ * own, and a launch then runs at most K steps (the halo rows are
+ * recomputed and absorb what the slab's edges cannot know for K steps).
+ * split_steps sets K (a multiple of 16, at most 240; 0 = 64); a batch with
+ * no lattice taller than 512 runs a whole run in one launch.  The state is
+ * read once at the start of a launch and written once at the end.
+ * Otherwise the streaming kernel runs, one launch per pass of t_phases/2
+ * steps (bml_batch_set_tuning).  Results are identical either way.  Drops
+ * a captured graph.  Synchronises.  bml_batch_get_resident: 1 if runs are
+ * register-resident, 0 if streaming, < 0 on error. */
+int bml_batch_set_resident(bml_batch *B, int32_t max_n, int32_t split_steps);
 int bml_batch_get_resident(const bml_batch *B);
 
 /* active_host: `count` bytes, non-zero = the lattice advances in later runs

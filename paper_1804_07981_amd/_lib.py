@@ -79,7 +79,7 @@ _SIGNATURES = {
     "bml_batch_init": ([ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _i32, _vp, _sz, _vp, _i64,
                         _vp], ctypes.c_int),
     "bml_batch_set_tuning": ([_vp, _i32, _i32, _i32], ctypes.c_int),
-    "bml_batch_set_resident": ([_vp, _i32], ctypes.c_int),
+    "bml_batch_set_resident": ([_vp, _i32, _i32], ctypes.c_int),
     "bml_batch_get_resident": ([_vp], ctypes.c_int),
     "bml_batch_set_active": ([_vp, _vp], ctypes.c_int),
     "bml_batch_run": ([_vp, _i64], ctypes.c_int),
@@ -332,8 +332,8 @@ def bml_batch_set_tuning(handle: int, strip_rows: int = 0, t_phases: int = 0,
     _check(lib().bml_batch_set_tuning(handle, strip_rows, t_phases, waves_per_block))
 
 
-def bml_batch_set_resident(handle: int, max_n: int) -> None:
-    _check(lib().bml_batch_set_resident(handle, max_n))
+def bml_batch_set_resident(handle: int, max_n: int, split_steps: int = 0) -> None:
+    _check(lib().bml_batch_set_resident(handle, max_n, split_steps))
 
 
 def bml_batch_get_resident(handle: int) -> int:

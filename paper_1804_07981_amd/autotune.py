@@ -14,6 +14,9 @@ moving on to the next candidate.  Results go to a JSON cache keyed by GPU
 architecture, layout and size, which `Lattice`/`Batch` users (and bench.py)
 read back.
 
+For the register-resident batch kernel it picks the slab halo (split_steps)
+of lattices taller than a workgroup.
+
 Usage: python -m paper_1804_07981_amd.autotune --sizes 4096 32768 [--medium] [--batch]
 """
 from __future__ import annotations
@@ -203,6 +206,7 @@ def tune_batch(ns, rhos, seeds, name: str, strip_rows=(16, 32, 64, 128),
     cells = float(np.sum(np.asarray(ns, dtype=np.float64) ** 2))
     for sr, tp, w in itertools.product(strip_rows, t_phases, waves):
         with Batch(ns, rhos, seeds, trace_steps=2 * steps) as bt:
+            bt.set_resident(0)           # the streaming kernel's launch shapes
             bt.set_tuning(sr, tp, w)
             bt.run(steps)
             bt.synchronize()
@@ -225,6 +229,47 @@ def tune_batch(ns, rhos, seeds, name: str, strip_rows=(16, 32, 64, 128),
         results.append({"tile_rows": sr, "t_phases": tp, "waves_per_block": w,
                         "gcups": gcups, "exact": True})
         log(f"  batch {name} rows={sr} T={tp} w={w}: {gcups:.0f} GCUPS")
+    return {"best": max(results, key=lambda r: r["gcups"]), "all": results, "steps": steps}
+
+
+def resident_key(name: str) -> str:
+    return f"{arch()}/resident/{name}"
+
+
+def tune_resident(ns, rhos, seeds, name: str, splits=(32, 48, 64, 80, 96),
+                  steps: int = 512, log=print, reference=None) -> dict:
+    """Fastest slab halo (split_steps) of the register-resident batch kernel
+    for a set of lattices.  Every candidate's trace over 2 x steps and the
+    cells of three lattices must equal `reference` (default: the first
+    candidate's); car counts are recounted (bml_batch_check)."""
+    ref = reference
+    results = []
+    cells = float(np.sum(np.asarray(ns, dtype=np.float64) ** 2))
+    for sp in splits:
+        with Batch(ns, rhos, seeds, trace_steps=2 * steps) as bt:
+            bt.set_resident(1024, sp)
+            if not bt.resident:
+                raise ValueError(f"batch {name}: lattices too large for the resident kernel")
+            bt.run(steps)
+            bt.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(bt.stream)
+            bt.run(steps)
+            e1.record(bt.stream)
+            bt.synchronize()
+            dt = e0.elapsed_time(e1) / 1e3
+            bt.check()
+            got = (bt.trace(), [bt.cells(b) for b in (0, len(ns) // 2, len(ns) - 1)])
+        if ref is None:
+            ref = got
+        if not (np.array_equal(got[0], ref[0])
+                and all(np.array_equal(a, b) for a, b in zip(got[1], ref[1]))):
+            raise TuningMismatch(f"batch {name}: resident candidate split={sp} differs from "
+                                 "the reference")
+        gcups = cells * steps / dt / 1e9
+        results.append({"split": sp, "gcups": gcups, "exact": True})
+        log(f"  resident {name} split={sp}: {gcups:.0f} GCUPS")
     return {"best": max(results, key=lambda r: r["gcups"]), "all": results, "steps": steps}
 
 
@@ -279,6 +324,10 @@ def main(argv=None) -> int:
         cache[key(L.BML_LAYOUT_BITPLANE, "sweep512")] = dict(r["best"], steps=r["steps"])
         print(json.dumps({"key": key(L.BML_LAYOUT_BITPLANE, "sweep512"), **r["best"]}),
               flush=True)
+        r = tune_resident([l.n for l in lats], [l.rho for l in lats], [l.seed for l in lats],
+                          "sweep512")
+        cache[resident_key("sweep512")] = dict(r["best"], steps=r["steps"])
+        print(json.dumps({"key": resident_key("sweep512"), **r["best"]}), flush=True)
     save(cache, args.cache)
     return 0
 

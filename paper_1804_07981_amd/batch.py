@@ -35,10 +35,12 @@ class Batch:
     def set_tuning(self, strip_rows: int = 0, t_phases: int = 0, waves_per_block: int = 0):
         B.bml_batch_set_tuning(self.handle, strip_rows, t_phases, waves_per_block)
 
-    def set_resident(self, max_n: int):
+    def set_resident(self, max_n: int, split_steps: int = 0):
         """Register-resident runs when every lattice has N <= max_n (at most
-        1024; 0 = always the streaming kernel)."""
-        B.bml_batch_set_resident(self.handle, max_n)
+        1024; 0 = always the streaming kernel); lattices taller than 512 rows
+        are cut into slabs with split_steps halo rows (0 = 64), and launches
+        then run at most that many steps."""
+        B.bml_batch_set_resident(self.handle, max_n, split_steps)
 
     @property
     def resident(self) -> bool:

@@ -79,6 +79,9 @@ struct bml_batch {
     // Register-resident runs (bml_resident.hpp) when every lattice has
     // N <= resident_max_n (at most 32 * RES_MAX_WORDS; 0 = never).
     int32_t resident_max_n = 32 * RES_MAX_WORDS;
+    // Halo rows of the slabs that lattices taller than a workgroup are cut
+    // into (0 = the default); a launch then runs at most that many steps.
+    int32_t resident_split = 0;
     int32_t res_grid = 0;                   // bins per resident launch (fixed while captured)
     int64_t host_step = 0, host_pass = 0;
     DeviceInfo dev;
@@ -86,6 +89,9 @@ struct bml_batch {
     BatchLattice *d_lat = nullptr;
     BatchItem *d_items = nullptr;
     ResidentBin *d_bins = nullptr;
+    SlabLattice *d_cut = nullptr;           // lattices cut into slabs (res_cut entries)
+    uint32_t *d_partial = nullptr;          // slabs' partial counts (res_parts rows)
+    int32_t res_cut = 0, res_parts = 0, res_halo = 0;
     BatchCounters *d_ctr = nullptr;
     unsigned long long *d_counts = nullptr;
     uint8_t *d_stage = nullptr;   // bitplane read-back staging, stage_bytes
@@ -120,6 +126,10 @@ static void batch_release(bml_batch *B)
         (void)hipFree(B->d_items);
     if (B->d_bins)
         (void)hipFree(B->d_bins);
+    if (B->d_cut)
+        (void)hipFree(B->d_cut);
+    if (B->d_partial)
+        (void)hipFree(B->d_partial);
     if (B->d_ctr)
         (void)hipFree(B->d_ctr);
     if (B->d_counts)
@@ -162,36 +172,110 @@ static bool use_resident(const bml_batch *B)
     return nmax <= std::min(B->resident_max_n, 32 * RES_MAX_WORDS);
 }
 
-// Bins of the resident kernel: the lattices flagged in `on`, grouped by
-// width, as many per bin as its 16 waves hold (ceil(W / 2) waves each),
-// the most expensive bins first so that they start first.
+// Work of a resident workgroup per step: row-words held (its items' width
+// times the rows they hold, halo rows included).
+static int64_t item_work(const ResidentItem &it, int W)
+{
+    return (int64_t)W * (it.rows + 2 * it.halo);
+}
+
+static int rows_waves(int rows) { return (rows + RES_WAVE_ROWS - 1) / RES_WAVE_ROWS; }
+
+static int held_waves(const ResidentItem &it) { return rows_waves(it.rows + 2 * it.halo); }
+
+constexpr int RES_BLOCK_ROWS = RES_WAVES * RES_WAVE_ROWS;   // rows one workgroup holds
+constexpr int RES_DEFAULT_SPLIT = 64;                       // halo when a cut is required
+constexpr int RES_MAX_SPLIT = (RES_BLOCK_ROWS - 32) / 2 / 16 * 16;   // a 32-row slab still fits
+
+// Halo rows of the slab plan: the configured value, or, when some lattice
+// is taller than a workgroup holds and none is configured, the default.
+static int plan_halo(const bml_batch *B)
+{
+    if (B->resident_split > 0)
+        return B->resident_split;
+    const int nmax = *std::max_element(B->n.begin(), B->n.end());
+    return nmax > RES_BLOCK_ROWS ? RES_DEFAULT_SPLIT : 0;
+}
+
+// How lattice n is cut for the resident kernel: 1 (whole) or the fewest
+// slabs of whole 32-row blocks that, held with K halo rows, fit one
+// workgroup.
+static int slab_count(int n, int K)
+{
+    if (n <= RES_BLOCK_ROWS)
+        return 1;
+    int P = 2;
+    while ((n / 32 + P - 1) / P * 32 + 2 * K > RES_BLOCK_ROWS)
+        ++P;
+    return P;
+}
+
+// Slabs of lattice b under the current plan (B->res_halo is set when the
+// plan is made).
+static int lattice_slabs(const bml_batch *B, int b) { return slab_count(B->n[b], B->res_halo); }
+
+// Bins of the resident kernel for the lattices flagged in `on`.  Slabs
+// take a bin each; whole lattices of one width share bins, as many as the
+// workgroup's waves hold.  The most expensive bins come first, so that
+// they start first.
 static std::vector<ResidentBin> resident_bins(const bml_batch *B, const std::vector<uint8_t> &on)
 {
     std::vector<ResidentBin> bins;
+    const int K = B->res_halo;
+    // Partial-count rows of the slabs: lattice by lattice, whatever is
+    // active, so that a row's meaning does not change while lattices retire.
+    std::vector<int> part_base(B->count, -1);
+    for (int b = 0, next = 0; b < B->count; ++b) {
+        const int P = lattice_slabs(B, b);
+        if (P > 1) {
+            part_base[b] = next;
+            next += P;
+        }
+    }
     for (int W = 1; W <= RES_MAX_WORDS; ++W) {
-        const int per_bin = std::min(RES_MAX_LAT, RES_WAVES / ((W + 1) / 2));
+        const int n = 32 * W;
         ResidentBin cur{};
         cur.words = W;
+        int cur_waves = 0;
         for (int b = 0; b < B->count; ++b) {
-            if (!on[b] || B->n[b] != 32 * W)
+            if (!on[b] || B->n[b] != n)
                 continue;
-            cur.lat[cur.n_lat++] = b;
-            if (cur.n_lat == per_bin) {
+            const int P = lattice_slabs(B, b);
+            if (P > 1) {
+                for (int i = 0; i < P; ++i) {
+                    const int lo = (n / 32) * i / P * 32, hi = (n / 32) * (i + 1) / P * 32;
+                    ResidentBin sb{};
+                    sb.words = W;
+                    sb.n_items = 1;
+                    sb.item[0] = ResidentItem{b, lo, hi - lo, K, part_base[b] + i};
+                    bins.push_back(sb);
+                }
+                continue;
+            }
+            const ResidentItem it{b, 0, n, 0, -1};
+            if (cur_waves + held_waves(it) > RES_WAVES || cur.n_items == RES_MAX_ITEMS) {
                 bins.push_back(cur);
                 cur = ResidentBin{};
                 cur.words = W;
+                cur_waves = 0;
             }
+            cur.item[cur.n_items++] = it;
+            cur_waves += held_waves(it);
         }
-        if (cur.n_lat)
+        if (cur.n_items)
             bins.push_back(cur);
     }
     auto cost = [](const ResidentBin &x) {
-        return (int64_t)x.words * x.n_lat * ((x.words + 1) / 2);
+        int64_t w = 0;
+        for (int i = 0; i < x.n_items; ++i)
+            w += item_work(x.item[i], x.words);
+        return w;
     };
     std::stable_sort(bins.begin(), bins.end(),
                      [&](const ResidentBin &x, const ResidentBin &y) { return cost(x) > cost(y); });
     return bins;
 }
+
 
 // Uploads the descriptors and the item list of the active lattices.
 // Synchronises the stream.
@@ -235,18 +319,51 @@ static int upload_work(bml_batch *B)
         // captured run stays valid as lattices retire: the bins of the
         // active lattices come first, padding bins (no lattice) after.
         if (B->res_grid == 0) {
+            // The plan's target is fixed with every lattice active: a
+            // subset then cuts the same lattices and needs no more bins.
+            B->res_halo = plan_halo(B);
             const std::vector<uint8_t> all(B->count, 1);
-            B->res_grid = std::max<int32_t>(1, (int32_t)resident_bins(B, all).size());
-            if (B->d_bins)
-                (void)hipFree(B->d_bins);
-            B->d_bins = nullptr;
-            if (hipMalloc(&B->d_bins, (size_t)B->res_grid * sizeof(ResidentBin)) != hipSuccess) {
-                B->d_bins = nullptr;
-                B->res_grid = 0;
-                return fail(BML_EDEVICE, "hipMalloc of the resident bin list failed");
+            const int32_t grid = std::max<int32_t>(1, (int32_t)resident_bins(B, all).size());
+            int32_t cut = 0, parts = 0;
+            for (int b = 0; b < B->count; ++b) {
+                const int P = lattice_slabs(B, b);
+                if (P > 1) {
+                    ++cut;
+                    parts += P;
+                }
             }
+            for (void **p : {(void **)&B->d_bins, (void **)&B->d_cut, (void **)&B->d_partial}) {
+                if (*p)
+                    (void)hipFree(*p);
+                *p = nullptr;
+            }
+            if (hipMalloc(&B->d_bins, (size_t)grid * sizeof(ResidentBin)) != hipSuccess ||
+                (cut && hipMalloc(&B->d_cut, (size_t)cut * sizeof(SlabLattice)) != hipSuccess) ||
+                (parts && hipMalloc(&B->d_partial, (size_t)parts * B->res_halo * 2 *
+                                                       sizeof(uint32_t)) != hipSuccess)) {
+                B->res_grid = 0;
+                return fail(BML_EDEVICE, "hipMalloc of the resident plan failed");
+            }
+            B->res_grid = grid;
+            B->res_cut = cut;
+            B->res_parts = parts;
+        }
+        if (B->res_cut) {
+            std::vector<SlabLattice> cut;
+            for (int b = 0, next = 0; b < B->count; ++b) {
+                const int P = lattice_slabs(B, b);
+                if (P > 1) {
+                    cut.push_back(SlabLattice{B->active[b] ? b : -1, next, P, 0});
+                    next += P;
+                }
+            }
+            BML_HIP(hipMemcpyAsync(B->d_cut, cut.data(), cut.size() * sizeof(SlabLattice),
+                                   hipMemcpyHostToDevice, B->stream));
         }
         std::vector<ResidentBin> bins = resident_bins(B, B->active);
+        if ((int64_t)bins.size() > B->res_grid)
+            return fail(BML_EDEVICE, "resident plan of %zu bins exceeds the %d of the launch",
+                        bins.size(), B->res_grid);
         bins.resize(B->res_grid, ResidentBin{1, 0, {}});
         BML_HIP(hipMemcpyAsync(B->d_bins, bins.data(), bins.size() * sizeof(ResidentBin),
                                hipMemcpyHostToDevice, B->stream));
@@ -284,6 +401,31 @@ __global__ void zero_trace_kernel(uint32_t *trace, int32_t count, int64_t trace_
     }
 }
 
+// Adds up the slabs' partial counts of the last resident launch (n_steps
+// steps, the device step counter already advanced past them) into the trace
+// of each cut lattice.  One thread per (cut lattice, step, count).
+__global__ __launch_bounds__(256) void slab_sum_kernel(const SlabLattice *cut, int32_t n_cut,
+                                                       const uint32_t *partial, int32_t part_steps,
+                                                       uint32_t *trace, int32_t trace_steps,
+                                                       const BatchCounters *ctr, int32_t n_steps)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_cut * n_steps * 2)
+        return;
+    const int e = (int)(i / (2 * n_steps));
+    const int st = (int)(i / 2 % n_steps), q = (int)(i & 1);
+    const SlabLattice c = cut[e];
+    const uint32_t gs = __hip_atomic_load(&ctr->step, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) - (uint32_t)n_steps +
+                        (uint32_t)st;
+    if (c.lattice < 0 || gs >= (uint32_t)trace_steps)
+        return;
+    uint32_t sum = 0;
+    for (int p = 0; p < c.count; ++p)
+        sum += partial[((size_t)(c.first + p) * part_steps + st) * 2 + q];
+    trace[((size_t)c.lattice * trace_steps + gs) * 2 + q] = sum;
+}
+
 static int batch_blocks_per_cu(int io, int k, int threads, int *out)
 {
     static std::mutex mu;
@@ -317,22 +459,34 @@ static int enqueue_run(bml_batch *B, int64_t n_steps, int64_t *passes)
                        B->count, B->trace_steps, B->d_ctr, n_steps);
     BML_HIP(hipGetLastError());
     if (use_resident(B)) {
-        // One launch runs every step (up to 2^30 per launch): the states
-        // stay in registers throughout.
+        // One launch runs every step (up to 2^30 per launch), the states
+        // staying in registers throughout; with slabs, at most as many
+        // steps as their halo rows.
         const ResidentFn fn = resident_table().fn[io];
+        const int64_t per = B->res_cut ? B->res_halo : (int64_t)1 << 30;
         int64_t s = 0, p = 0;
         while (s < n_steps) {
-            const int64_t k = std::min<int64_t>(n_steps - s, (int64_t)1 << 30);
+            const int64_t k = std::min<int64_t>(n_steps - s, per);
             ResidentArgs a;
             a.lat = B->d_lat;
             a.bins = B->d_bins;
             a.ctr = B->d_ctr;
             a.trace = B->trace;
+            a.partial = B->d_partial;
             a.trace_steps = (int32_t)B->trace_steps;
+            a.part_steps = B->res_halo;
             a.n_steps = (int32_t)k;
             hipLaunchKernelGGL(fn, dim3((unsigned)B->res_grid), dim3(64 * RES_WAVES), 0,
                                B->stream, a);
             BML_HIP(hipGetLastError());
+            if (B->res_cut) {
+                const int64_t threads = (int64_t)B->res_cut * k * 2;
+                hipLaunchKernelGGL(slab_sum_kernel, dim3((unsigned)((threads + 255) / 256)),
+                                   dim3(256), 0, B->stream, B->d_cut, B->res_cut, B->d_partial,
+                                   B->res_halo, B->trace, (int32_t)B->trace_steps, B->d_ctr,
+                                   (int32_t)k);
+                BML_HIP(hipGetLastError());
+            }
             s += k;
             ++p;
         }
@@ -527,14 +681,18 @@ int bml_batch_set_tuning(bml_batch *B, int32_t strip_rows, int32_t t_phases,
     return upload_work(B);
 }
 
-int bml_batch_set_resident(bml_batch *B, int32_t max_n)
+int bml_batch_set_resident(bml_batch *B, int32_t max_n, int32_t split_steps)
 {
     clear_error();
     if (!batch_live(B))
         return fail(BML_ESTATE, "invalid batch handle");
     if (max_n < 0 || max_n > 32 * RES_MAX_WORDS)
         return fail(BML_EINVAL, "max_n=%d must be in [0, %d]", max_n, 32 * RES_MAX_WORDS);
+    if (split_steps < 0 || split_steps > RES_MAX_SPLIT || split_steps % 16)
+        return fail(BML_EINVAL, "split_steps=%d must be 0 or a multiple of 16 up to %d",
+                    split_steps, RES_MAX_SPLIT);
     B->resident_max_n = max_n;
+    B->resident_split = split_steps;
     B->res_grid = 0;
     if (B->graph_exec) {
         (void)hipGraphExecDestroy(B->graph_exec);

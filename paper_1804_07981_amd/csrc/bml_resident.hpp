@@ -1,27 +1,40 @@
-// bml_resident.hpp -- register-resident batched BML kernel (gfx950): every
-// lattice of a batch with N <= 1024 stays in VGPRs for a whole run of many
-// steps, in one launch.
+// bml_resident.hpp -- register-resident batched BML kernel (gfx950): the
+// lattices of a batch with N <= 1024 stay in VGPRs for many steps per
+// launch.
 //
-// Layout: one row per lane.  Lane l of wave w of a lattice holds row
-// 64 w + l as W = N / 32 LR words and W TB words (bit b of word i = cell
-// 32 i + b), so the horizontal phase (Marzolla, arXiv:1804.07981, Sec. 2
-// case table for LR cars) is entirely inside the lane: a ring of W words,
-// periodic in x with no halo.  The vertical phase needs the rows above and
-// below, which are the neighbouring lanes (DPP wave shifts); the rows
-// across a wave boundary (and across the periodic top/bottom edge) come
-// from the neighbouring wave through LDS.  One barrier per step separates
+// Layout: two rows per lane.  A lane holds two consecutive rows, each as
+// W = N / 32 LR words and W TB words (bit b of word i = cell 32 i + b), so
+// the horizontal phase (Marzolla, arXiv:1804.07981, Sec. 2 case table for
+// LR cars) is entirely inside the lane: a ring of W words, periodic in x
+// with no halo.  The vertical phase passes cars from a lane's upper row to
+// its lower row in registers, and from its lower row to the next lane's
+// upper row by DPP wave shifts; rows across a wavefront boundary come from
+// the neighbouring wavefront through LDS.  One barrier per step separates
 // the exchange writes (after the horizontal phase) from the reads; the
 // exchange slots alternate between two buffers by step parity, so a wave
 // can never overwrite a slot a slower wave has yet to read.  Both phases
 // read only the state before the phase (the synchronous rule of Sec. 3):
 // the horizontal phase decides every move from the words before any of
 // them changes, and the vertical phase from the post-horizontal occupancy.
+// Two rows per lane halve the wave shifts per row and the per-wave work
+// that does not depend on W, and leave each lane up to 256 VGPRs (8
+// wavefronts per workgroup, one workgroup per CU).
 //
-// A block (16 waves) holds a bin of lattices of one size: as many as fit,
-// ceil(W / 2) waves each.  Per step and lattice the moved counts of the
-// two phases are summed (wave total, then LDS) and stored in the trace.
-// The state is read from HBM once at the start of the run and written once
-// at the end: the step loop itself touches only VGPRs and LDS.
+// Work items.  An item is either a whole lattice (halo 0: its last row's
+// lower neighbour is its first row, the periodic edge of Sec. 2) or a slab
+// of R rows of a lattice held with H halo rows above and below (rows
+// r0 - H .. r0 + R + H - 1, periodic in the lattice).  A slab's outermost
+// rows have no neighbour beyond them; what they miss travels at most one
+// row per step, so after at most H steps the R rows of the slab are still
+// exact (the halo absorbs the error) and only they are stored and counted.
+// Slabs let one lattice spread over several workgroups (CUs) for the K <= H
+// steps of a launch, at the price of recomputing the halo rows.
+//
+// A workgroup (8 wavefronts) runs a bin of items of one row width W:
+// ceil(rows held / 128) wavefronts each.  Per step and item the moved counts
+// of the two phases are summed (wave total, then LDS) and added to the
+// lattice's trace entry.  The state is read once at the start of a launch
+// and written once at the end: the step loop touches only VGPRs and LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,15 +46,26 @@
 namespace bml {
 
 constexpr int RES_MAX_WORDS = 32;   // N <= 1024
-constexpr int RES_WAVES = 16;       // waves per block
-constexpr int RES_MAX_LAT = 16;     // lattices per block (N <= 64: one wave each)
+constexpr int RES_WAVES = 4;        // waves per block (one per SIMD; two blocks per CU)
+constexpr int RES_WAVE_ROWS = 128;  // rows per wave: two per lane
+constexpr int RES_MAX_ITEMS = RES_WAVES;   // items per block (each starts a wave)
 constexpr int RES_GROUP = 4;        // words per scheduling group of the step loop
+constexpr int RES_CHUNK = 32;       // steps whose counts are gathered in LDS before a flush
 
-// Lattices of one size run by one block.
+// One lattice, or one slab of one.
+struct ResidentItem {
+    int32_t lattice;                // batch index
+    int32_t r0;                     // first row stored (0 for a whole lattice)
+    int32_t rows;                   // rows stored: N for a whole lattice
+    int32_t halo;                   // halo rows above and below (0: whole, periodic)
+    int32_t part;                   // slab's partial-count row (-1: whole lattice)
+};
+
+// Items of one row width run by one block.
 struct ResidentBin {
-    int32_t words;                  // W = N / 32 of every lattice in the bin
-    int32_t n_lat;                  // lattices in the bin
-    int32_t lat[RES_MAX_LAT];       // batch indices
+    int32_t words;                  // W = N / 32 of every item in the bin
+    int32_t n_items;
+    ResidentItem item[RES_MAX_ITEMS];
 };
 
 struct ResidentArgs {
@@ -49,8 +73,10 @@ struct ResidentArgs {
     const ResidentBin *bins;
     BatchCounters *ctr;
     uint32_t *trace;                // [lattice][trace_steps][2]: LR moved, TB moved
+    uint32_t *partial;              // [slab][part_steps][2]: a slab's moved counts
     int32_t trace_steps;
-    int32_t n_steps;                // steps of this launch
+    int32_t part_steps;             // steps per partial row (>= n_steps when slabs exist)
+    int32_t n_steps;                // steps of this launch (<= every slab's halo)
 };
 
 // Lane l receives v of lane l+1 (the row below); lane 63 keeps `old`.
@@ -68,219 +94,267 @@ __device__ __forceinline__ uint32_t from_above_or(uint32_t old, uint32_t v)
 }
 
 // Exchange slots: [step parity][wave][0: emptiness of the wave's first row
-// after the horizontal phase, 1: TB plane of its last row][word].
+// after the horizontal phase, 1: TB plane of its last row][word]; `none`
+// stands for the missing neighbour beyond a slab's outermost rows (no car
+// above, no empty cell below).
 struct ResidentShared {
     uint32_t x[2][RES_WAVES][2][RES_MAX_WORDS];
-    uint32_t cnt[2][RES_MAX_LAT][2];     // [step parity][lattice][LR, TB moved]
+    uint32_t none[RES_MAX_WORDS];
+    // Moved counts [chunk parity][step in chunk][item][LR, TB], gathered
+    // over RES_CHUNK steps and then added to the trace in one burst: a
+    // global write inside the step loop would hold the barrier until it
+    // completes, every step.
+    uint32_t cnt[2][RES_CHUNK][RES_MAX_ITEMS][2];
 };
 
 template <int IO, int W>
 __device__ __forceinline__ void resident_body(const ResidentArgs &a, const ResidentBin &bin,
                                               ResidentShared &sh)
 {
-    constexpr int WPL = (W + 1) / 2;     // waves per lattice: 32 W rows, 64 per wave
     constexpr int N = 32 * W;
-    constexpr bool HALF = (W & 1) != 0;  // the last wave of a lattice holds 32 rows
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int n_lat = __builtin_amdgcn_readfirstlane(bin.n_lat);
-    const int slot = wave / WPL;                 // lattice of this wave within the bin
-    const int wl = wave - slot * WPL;            // wave within its lattice
-    const bool wave_on = slot < n_lat;
-    const int row = wl * 64 + lane;
-    const bool row_ok = wave_on && row < N;
-    const bool tail = HALF && wl == WPL - 1;     // lanes 0..31 only
-    const int wdown = slot * WPL + (wl + 1 == WPL ? 0 : wl + 1);   // wave below (wrapping)
-    const int wup = slot * WPL + (wl == 0 ? WPL - 1 : wl - 1);     // wave above
-    const int last_lane = tail ? 31 : 63;
+    const int n_items = __builtin_amdgcn_readfirstlane(bin.n_items);
+    // This wave's item: items take consecutive waves, ceil(held rows / 128)
+    // each.
+    int slot = -1, first = 0, waves = 0;
+    for (int it = 0, w0 = 0; it < n_items; ++it) {
+        const int held = __builtin_amdgcn_readfirstlane(bin.item[it].rows) +
+                         2 * __builtin_amdgcn_readfirstlane(bin.item[it].halo);
+        const int nw = (held + RES_WAVE_ROWS - 1) / RES_WAVE_ROWS;
+        if (wave >= w0 && wave < w0 + nw) {
+            slot = it;
+            first = w0;
+            waves = nw;
+        }
+        w0 += nw;
+    }
+    const bool wave_on = slot >= 0;
+    int li = 0, r0 = 0, R = 0, H = 0;
+    if (wave_on) {
+        li = __builtin_amdgcn_readfirstlane(bin.item[slot].lattice);
+        r0 = __builtin_amdgcn_readfirstlane(bin.item[slot].r0);
+        R = __builtin_amdgcn_readfirstlane(bin.item[slot].rows);
+        H = __builtin_amdgcn_readfirstlane(bin.item[slot].halo);
+    }
+    const int held = R + 2 * H;
+    const int wl = wave - first;                 // wave within its item
+    const int row = wl * RES_WAVE_ROWS + 2 * lane;   // the lane's upper row within the item
+    const bool row_ok = wave_on && row < held;
+    // H and R are even, so a lane's two rows are both counted or neither.
+    const bool counted = row_ok && row >= H && row < H + R;
+    // Lanes of the item's last wave: held rows are a multiple of 32, so 16,
+    // 32, 48 or 64.
+    const int lanes = wave_on ? min(64, (held - wl * RES_WAVE_ROWS) / 2) : 64;
+    const int last_lane = lanes - 1;
+    // Neighbouring waves (exchange slots); across the item's ends: the
+    // other end for a whole lattice (periodic), none (-1) for a slab.
+    const bool open = H > 0;
+    const int wdown = wl + 1 < waves ? wave + 1 : open ? -1 : first;
+    const int wup = wl > 0 ? wave - 1 : open ? -1 : first + waves - 1;
     const uint32_t step0 = __builtin_amdgcn_readfirstlane(a.ctr->step);
     const uint32_t pass = __builtin_amdgcn_readfirstlane(a.ctr->pass);
     const int n_steps = a.n_steps;
 
-    int li = 0;
     uint8_t *dst = nullptr;
-    uint32_t L[W], T[W];
+    // Upper row (L0, T0) and lower row (L1, T1) of the lane.
+    uint32_t L0[W], T0[W], L1[W], T1[W];
 #pragma unroll
     for (int i = 0; i < W; ++i)
-        L[i] = T[i] = 0;
+        L0[i] = T0[i] = L1[i] = T1[i] = 0;
+    // Lattice rows held by this lane.
+    const int g0 = row_ok ? (r0 - H + row + 2 * N) % N : 0;
+    const int g1 = g0 + 1 == N ? 0 : g0 + 1;
+    auto load_row = [&](const uint8_t *src, int g, uint32_t (&Lr)[W], uint32_t (&Tr)[W]) {
+        if constexpr (IO == IO_U8) {
+            const uint4 *p = (const uint4 *)(src + (size_t)g * N);
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const uint4 u0 = p[2 * i], u1 = p[2 * i + 1];
+                const uint32_t dw[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+                bytes_to_planes(dw, Lr[i], Tr[i]);
+            }
+        } else {
+            const uint32_t *pl = (const uint32_t *)src + (size_t)g * W;
+            const uint32_t *pt = pl + (size_t)N * W;
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                Lr[i] = pl[i];
+                Tr[i] = pt[i];
+            }
+        }
+    };
+    auto store_row = [&](int g, const uint32_t (&Lr)[W], const uint32_t (&Tr)[W]) {
+        if constexpr (IO == IO_U8) {
+            uint4 *q = (uint4 *)(dst + (size_t)g * N);
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                uint32_t b[8];
+                planes_to_bytes(Lr[i], Tr[i], b);
+                q[2 * i] = make_uint4(b[0], b[1], b[2], b[3]);
+                q[2 * i + 1] = make_uint4(b[4], b[5], b[6], b[7]);
+            }
+        } else {
+            uint32_t *pl = (uint32_t *)dst + (size_t)g * W;
+            uint32_t *pt = pl + (size_t)N * W;
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                pl[i] = Lr[i];
+                pt[i] = Tr[i];
+            }
+        }
+    };
     if (wave_on) {
-        li = __builtin_amdgcn_readfirstlane(bin.lat[slot]);
         const BatchLattice &d = a.lat[li];
         const int par = (__builtin_amdgcn_readfirstlane(d.parity_base) +
                          (int)(pass - (uint32_t)__builtin_amdgcn_readfirstlane(d.pass_base))) & 1;
         const uint8_t *src = (const uint8_t *)d.buf[par];
         dst = (uint8_t *)d.buf[par ^ 1];
         if (row_ok) {
-            if constexpr (IO == IO_U8) {
-                const uint4 *p = (const uint4 *)(src + (size_t)row * N);
-#pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    const uint4 u0 = p[2 * i], u1 = p[2 * i + 1];
-                    const uint32_t dw[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-                    bytes_to_planes(dw, L[i], T[i]);
-                }
-            } else {
-                const uint32_t *pl = (const uint32_t *)src + (size_t)row * W;
-                const uint32_t *pt = pl + (size_t)N * W;
-#pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    L[i] = pl[i];
-                    T[i] = pt[i];
-                }
-            }
+            load_row(src, g0, L0, T0);
+            load_row(src, g1, L1, T1);
         }
     }
 
-    // The count slots are first added to after the first step's barrier.
-    static_assert(2 * RES_MAX_LAT * 2 <= 64, "one wave clears the count slots");
-    if (threadIdx.x < 2 * RES_MAX_LAT * 2)
-        (&sh.cnt[0][0][0])[threadIdx.x] = 0;
+    // The count slots and the missing-neighbour row are first used after
+    // the first step's barrier.
+    for (int i = threadIdx.x; i < 2 * RES_CHUNK * RES_MAX_ITEMS * 2; i += blockDim.x)
+        (&sh.cnt[0][0][0][0])[i] = 0;
+    if (threadIdx.x < RES_MAX_WORDS)
+        sh.none[threadIdx.x] = 0;
+    // Writes the gathered counts of steps [c0, c1) (one chunk) and clears
+    // their slots; run by the first wave of each item.  A whole lattice
+    // writes its trace entries; a slab writes its row of partial counts,
+    // which slab_sum_kernel adds up per lattice after the launch (plain
+    // stores: atomics from a whole wave to one cache line serialise).
+    const int part = wave_on ? __builtin_amdgcn_readfirstlane(bin.item[slot].part) : -1;
+    auto flush = [&](int c0, int c1) {
+        const int kb = (c0 / RES_CHUNK) & 1;
+        for (int j = lane; j < 2 * (c1 - c0); j += 64) {
+            const int st = c0 + (j >> 1), q = j & 1;
+            uint32_t &slotv = sh.cnt[kb][st - c0][slot][q];
+            const uint32_t v = slotv;
+            slotv = 0;
+            if (part >= 0) {
+                a.partial[((size_t)part * a.part_steps + st) * 2 + q] = v;
+            } else {
+                const uint32_t gs = step0 + (uint32_t)st;
+                if (gs < (uint32_t)a.trace_steps)
+                    a.trace[((size_t)li * a.trace_steps + gs) * 2 + q] = v;
+            }
+        }
+    };
+
+    // Horizontal phase of one row: an LR car moves when the next cell (bit
+    // j + 1, continued into the next word, word W-1 wrapping to word 0) is
+    // EMPTY; it lands one cell further.  Every mover is decided before any
+    // word changes.  Words are processed in groups of RES_GROUP with
+    // scheduling barriers between groups, so that only a group's
+    // temporaries are live next to the state.  Returns the movers' count;
+    // E receives the row's emptiness after the phase.
+    auto hphase = [&](uint32_t (&Lr)[W], const uint32_t (&Tr)[W], uint32_t (&E)[W]) {
+        uint32_t c = 0;
+        const uint32_t o0 = Lr[0] | Tr[0];
+        const uint32_t mv_last =
+            Lr[W - 1] & ~__builtin_amdgcn_alignbit(o0, Lr[W - 1] | Tr[W - 1], 1);
+        uint32_t mv_prev = mv_last, o = o0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            uint32_t mv;
+            if (i + 1 < W) {
+                const uint32_t on = Lr[i + 1] | Tr[i + 1];
+                mv = Lr[i] & ~__builtin_amdgcn_alignbit(on, o, 1);
+                o = on;
+            } else {
+                mv = mv_last;
+            }
+            const uint32_t arrive = __builtin_amdgcn_alignbit(mv, mv_prev, 31);
+            c += __builtin_popcount(mv);
+            Lr[i] = Lr[i] ^ mv ^ arrive;    // movers leave, arrivals land (disjoint)
+            E[i] = ~(Lr[i] | Tr[i]);
+            // Opaque new values (and count): updated in place here, not
+            // carried as pieces to the end of the step.
+            asm("" : "+v"(Lr[i]), "+v"(E[i]), "+v"(c));
+            mv_prev = mv;
+            if ((i + 1) % RES_GROUP == 0)
+                __builtin_amdgcn_sched_barrier(0);
+        }
+        return c;
+    };
 
     for (int s = 0; s < n_steps; ++s) {
         const int p = s & 1;
-        // Emptiness after the horizontal phase, kept per word while the
-        // VGPRs allow it (the 128 of a 16-wave block hold 3 W words and the
-        // rest up to W = 28); the widest rows recompute it where it is used.
-        constexpr bool KEEP_E = W <= 28;
-        uint32_t E[KEEP_E ? W : 1];
-        auto empty = [&](int i) { return KEEP_E ? E[i] : ~(L[i] | T[i]); };
+        uint32_t E0[W], E1[W];    // emptiness of the two rows after the horizontal phase
         uint32_t c_lr = 0, c_tb = 0;
         if (wave_on) {
-            // Horizontal phase: an LR car moves when the next cell (bit
-            // j + 1, continued into the next word, word W-1 wrapping to
-            // word 0) is EMPTY; it lands one cell further.  Every mover is
-            // decided before any word changes.
-            // Words are processed in groups of RES_GROUP with scheduling
-            // barriers between groups, so that only a group's temporaries
-            // are live next to the state (the compiler would otherwise
-            // compute every word's movers first and run out of VGPRs).
-            const uint32_t o0 = L[0] | T[0];
-            const uint32_t mv_last =
-                L[W - 1] & ~__builtin_amdgcn_alignbit(o0, L[W - 1] | T[W - 1], 1);
-            uint32_t mv_prev = mv_last, o = o0;
-#pragma unroll
-            for (int i = 0; i < W; ++i) {
-                uint32_t mv;
-                if (i + 1 < W) {
-                    const uint32_t on = L[i + 1] | T[i + 1];
-                    mv = L[i] & ~__builtin_amdgcn_alignbit(on, o, 1);
-                    o = on;
-                } else {
-                    mv = mv_last;
-                }
-                const uint32_t arrive = __builtin_amdgcn_alignbit(mv, mv_prev, 31);
-                c_lr += __builtin_popcount(mv);
-                L[i] = L[i] ^ mv ^ arrive;    // movers leave, arrivals land (disjoint)
-                // Opaque new values: updated in place here, not carried as
-                // pieces to the end of the step.
-                if constexpr (KEEP_E) {
-                    E[i] = ~(L[i] | T[i]);
-                    asm("" : "+v"(L[i]), "+v"(E[i]));
-                } else {
-                    asm("" : "+v"(L[i]));
-                }
-                mv_prev = mv;
-                if ((i + 1) % RES_GROUP == 0)
-                    __builtin_amdgcn_sched_barrier(0);
-            }
-            // Exchange: the first row's emptiness goes to the wave above,
-            // the last row's TB plane (unchanged by this phase) to the
-            // wave below.
+            c_lr = hphase(L0, T0, E0) + hphase(L1, T1, E1);
+            // Exchange: the wave's first row's emptiness goes to the wave
+            // above, its last row's TB plane (unchanged by this phase) to
+            // the wave below.
             if (lane == 0) {
 #pragma unroll
                 for (int i = 0; i < W; ++i)
-                    sh.x[p][wave][0][i] = empty(i);
+                    sh.x[p][wave][0][i] = E0[i];
             }
             if (lane == last_lane) {
 #pragma unroll
                 for (int i = 0; i < W; ++i)
-                    sh.x[p][wave][1][i] = T[i];
+                    sh.x[p][wave][1][i] = T1[i];
             }
         }
         __syncthreads();
         if (wave_on) {
+            const uint32_t *xb = wdown >= 0 ? sh.x[p][wdown][0] : sh.none;
+            const uint32_t *xa = wup >= 0 ? sh.x[p][wup][1] : sh.none;
             // Vertical phase: a TB car moves when the cell below is EMPTY
-            // after the horizontal phase; it lands one row lower.
-            auto vphase = [&](auto tail_tag) {
-                constexpr bool TAIL = decltype(tail_tag)::value;
+            // after the horizontal phase; it lands one row lower.  The
+            // upper row's cars move into the lower row of the same lane;
+            // the lower row's into the next lane's upper row, or, for the
+            // item's last lane (63, or 15, 31 or 47 in a short last wave),
+            // into the wave below.
 #pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    const uint32_t e_x = sh.x[p][wdown][0][i];   // first row of the wave below
-                    const uint32_t t_x = sh.x[p][wup][1][i];     // last row of the wave above
-                    const uint32_t e = empty(i);
-                    uint32_t e_below = from_below_or(e_x, e);
-                    if constexpr (TAIL) {
-                        // Lane 31 holds the last row.  The lane shift must
-                        // run with every lane on: the compiler would
-                        // otherwise turn the select into a branch around a
-                        // shift with lane 31 switched off, and a lane whose
-                        // source lane is off keeps its old value (lane 30
-                        // would see the wrong row below).
-                        asm volatile("" : "+v"(e_below));
-                        e_below = lane == 31 ? e_x : e_below;
-                    }
-                    const uint32_t mvt = T[i] & e_below;
-                    const uint32_t arrive = from_above_or(t_x & e, mvt);
-                    c_tb += __builtin_popcount(mvt);
-                    T[i] = T[i] ^ mvt ^ arrive;
-                    asm("" : "+v"(T[i]));
-                    if ((i + 1) % RES_GROUP == 0)
-                        __builtin_amdgcn_sched_barrier(0);
-                }
-            };
-            if (HALF && tail)
-                vphase(std::true_type{});
-            else
-                vphase(std::false_type{});
-            const uint32_t tot = wave_total(row_ok ? (c_lr | (c_tb << 16)) : 0u);
+            for (int i = 0; i < W; ++i) {
+                const uint32_t e_x = xb[i];   // first row of the wave below
+                const uint32_t t_x = xa[i];   // last row of the wave above
+                uint32_t e_below = from_below_or(e_x, E0[i]);
+                // The lane shift must run with every lane on: the compiler
+                // would otherwise turn the select into a branch around a
+                // shift with the last lane switched off, and a lane whose
+                // source lane is off keeps its old value.
+                asm volatile("" : "+v"(e_below));
+                e_below = lane == last_lane ? e_x : e_below;
+                const uint32_t mv0 = T0[i] & E1[i];
+                const uint32_t mv1 = T1[i] & e_below;
+                const uint32_t arrive = from_above_or(t_x & E0[i], mv1);
+                c_tb += __builtin_popcount(mv0) + __builtin_popcount(mv1);
+                T0[i] = T0[i] ^ mv0 ^ arrive;
+                T1[i] = T1[i] ^ mv1 ^ mv0;
+                asm("" : "+v"(T0[i]), "+v"(T1[i]), "+v"(c_tb));
+                if ((i + 1) % RES_GROUP == 0)
+                    __builtin_amdgcn_sched_barrier(0);
+            }
+            const uint32_t tot = wave_total(counted ? (c_lr | (c_tb << 16)) : 0u);
             if (lane == 0) {
-                atomicAdd(&sh.cnt[p][slot][0], tot & 0xffffu);
-                atomicAdd(&sh.cnt[p][slot][1], tot >> 16);
+                const int kb = (s / RES_CHUNK) & 1, c = s % RES_CHUNK;
+                atomicAdd(&sh.cnt[kb][c][slot][0], tot & 0xffffu);
+                atomicAdd(&sh.cnt[kb][c][slot][1], tot >> 16);
             }
-            // The counts of step s-1 are complete: every wave added them
-            // before this step's barrier.
-            if (s > 0 && wl == 0 && lane == 0) {
-                const uint32_t gs = step0 + (uint32_t)(s - 1);
-                if (gs < (uint32_t)a.trace_steps) {
-                    uint32_t *tr = a.trace + ((size_t)li * a.trace_steps + gs) * 2;
-                    tr[0] = sh.cnt[p ^ 1][slot][0];
-                    tr[1] = sh.cnt[p ^ 1][slot][1];
-                }
-                sh.cnt[p ^ 1][slot][0] = 0;
-                sh.cnt[p ^ 1][slot][1] = 0;
-            }
+            // At the first step of a chunk the previous chunk's counts are
+            // complete (every wave added them before this step's barrier),
+            // and its slots are next used two chunks on.
+            if (s >= RES_CHUNK && s % RES_CHUNK == 0 && wl == 0)
+                flush(s - RES_CHUNK, s);
         }
     }
     __syncthreads();
     if (wave_on) {
-        if (n_steps > 0 && wl == 0 && lane == 0) {
-            const int p = (n_steps - 1) & 1;
-            const uint32_t gs = step0 + (uint32_t)(n_steps - 1);
-            if (gs < (uint32_t)a.trace_steps) {
-                uint32_t *tr = a.trace + ((size_t)li * a.trace_steps + gs) * 2;
-                tr[0] = sh.cnt[p][slot][0];
-                tr[1] = sh.cnt[p][slot][1];
-            }
+        if (n_steps > 0 && wl == 0) {
+            const int c0 = (n_steps - 1) / RES_CHUNK * RES_CHUNK;   // the last chunk
+            flush(c0, n_steps);
         }
-        if (row_ok) {
-            if constexpr (IO == IO_U8) {
-                uint4 *q = (uint4 *)(dst + (size_t)row * N);
-#pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    uint32_t b[8];
-                    planes_to_bytes(L[i], T[i], b);
-                    q[2 * i] = make_uint4(b[0], b[1], b[2], b[3]);
-                    q[2 * i + 1] = make_uint4(b[4], b[5], b[6], b[7]);
-                }
-            } else {
-                uint32_t *pl = (uint32_t *)dst + (size_t)row * W;
-                uint32_t *pt = pl + (size_t)N * W;
-#pragma unroll
-                for (int i = 0; i < W; ++i) {
-                    pl[i] = L[i];
-                    pt[i] = T[i];
-                }
-            }
+        if (counted) {
+            store_row(g0, L0, T0);
+            store_row(g1, L1, T1);
         }
     }
 }
@@ -299,12 +373,12 @@ __device__ __forceinline__ void resident_dispatch(const ResidentArgs &a, const R
 
 // One block per bin; blockDim.x == 64 * RES_WAVES.
 template <int IO>
-__global__ __launch_bounds__(64 * RES_WAVES) void resident_kernel(ResidentArgs a)
+__global__ __launch_bounds__(64 * RES_WAVES, 2) void resident_kernel(ResidentArgs a)
 {
     __shared__ ResidentShared sh;
     const ResidentBin &bin = a.bins[blockIdx.x];
     const int words = __builtin_amdgcn_readfirstlane(bin.words);
-    if (__builtin_amdgcn_readfirstlane(bin.n_lat) > 0)   // padding bins only take a ticket
+    if (__builtin_amdgcn_readfirstlane(bin.n_items) > 0)   // padding bins only take a ticket
         resident_dispatch<IO, 1>(a, bin, sh, words);
 
     // The last block to finish advances the device-side step and pass (one
@@ -323,6 +397,12 @@ __global__ __launch_bounds__(64 * RES_WAVES) void resident_kernel(ResidentArgs a
         __hip_atomic_store(&a.ctr->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
+
+// One lattice cut into slabs: its slabs' partial rows are first ..
+// first + count - 1 (lattice -1: not active in this run).
+struct SlabLattice {
+    int32_t lattice, first, count, pad;
+};
 
 using ResidentFn = void (*)(ResidentArgs);
 void resident_kernels(ResidentFn *u8, ResidentFn *bp);

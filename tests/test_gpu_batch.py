@@ -180,15 +180,20 @@ EVERY_WIDTH = [32 * w for w in range(1, 33)] * 2 + [64] * 17
 
 
 @pytest.mark.parametrize("layout", [0, 1])
-def test_resident_every_width(B, layout):
-    rng = np.random.default_rng(77 + layout)
+@pytest.mark.parametrize("split", [0, 16, 64])
+def test_resident_every_width(B, layout, split):
+    """Every width, whole lattices or (split > 0) the most expensive ones cut
+    into slabs with `split` halo rows; 37 steps (with slabs: launches of
+    `split` steps and a shorter last one)."""
+    rng = np.random.default_rng(77 + layout + split)
     ns = EVERY_WIDTH
     rhos = [float(x) for x in rng.uniform(0.1, 0.7, len(ns))]
     seeds = [int(x) for x in rng.integers(0, 2**40, len(ns))]
     steps = 37
-    say(f"resident every width layout={layout} lattices={len(ns)} steps={steps}")
+    say(f"resident every width layout={layout} split={split} lattices={len(ns)} steps={steps}")
     want, wst = oracle_runs(ns, rhos, seeds, steps)
     with B.Batch(ns, rhos, seeds, layout=layout, trace_steps=64) as bt:
+        bt.set_resident(1024, split)
         assert bt.resident
         bt.run(steps)
         check_batch(bt, ns, want, wst)
@@ -212,6 +217,27 @@ def test_resident_and_streaming_agree_in_runs(B):
         check_batch(bt, ns, want, wst)
 
 
+def test_resident_slabs_on_the_sweep(B):
+    """The 512-lattice sweep with its largest lattices cut into slabs of
+    32 halo rows: 100 steps (launches of 32, 32, 32 and 4), every lattice's
+    cells and moved counts."""
+    lats = workloads.SWEEP.lattices
+    ns = [l.n for l in lats]
+    rhos = [l.rho for l in lats]
+    seeds = [l.seed for l in lats]
+    steps = 100
+    want, wst = oracle_runs(ns, rhos, seeds, steps)
+    with B.Batch(ns, rhos, seeds, trace_steps=steps) as bt:
+        bt.set_resident(1024, 32)
+        bt.run(steps)
+        check_batch(bt, ns, want, wst)
+    with B.Batch([64], [0.3], [1], trace_steps=8) as bt:
+        for bad in (-16, 8, 24, 256):
+            with pytest.raises(B.BmlError) as e:
+                bt.set_resident(1024, bad)
+            assert e.value.code == B.BML_EINVAL
+
+
 def test_resident_mode_boundary(B):
     """The mode follows the largest lattice: 1024 runs resident, 1056 does
     not; a lower limit switches a batch back to streaming.  Both sides match
@@ -233,16 +259,19 @@ def test_resident_mode_boundary(B):
             assert e.value.code == B.BML_EINVAL
 
 
-def test_resident_graph_with_retired_lattices(B):
+@pytest.mark.parametrize("split", [0, 32])
+def test_resident_graph_with_retired_lattices(B, split):
     """A captured resident run keeps its grid while lattices retire: the
     active ones are re-binned, the rest padded.  Replays, eager runs and an
-    empty active set all match the oracle."""
+    empty active set all match the oracle (with slabs: 16-step replays of
+    one launch each, 5 eager steps)."""
     ns = [64] * 20 + [96, 96, 480, 1024, 992]
     rng = np.random.default_rng(5)
     rhos = [float(x) for x in rng.uniform(0.2, 0.5, len(ns))]
     seeds = list(range(100, 100 + len(ns)))
     per = 16
     with B.Batch(ns, rhos, seeds, trace_steps=128) as bt:
+        bt.set_resident(1024, split)
         assert bt.resident
         bt.capture(per)
         bt.replay()
@@ -288,3 +317,24 @@ def test_resident_density_extremes(B):
         assert bt.resident
         bt.run(steps)
         check_batch(bt, ns, want, wst)
+
+
+def test_resident_tuner_gate_with_the_oracle(B):
+    """The resident autotuner's gate with the oracle as its reference: every
+    slab halo candidate must reproduce the oracle's moved counts and cells
+    of a batch with lattices taller than a workgroup, or tune_resident
+    raises."""
+    from paper_1804_07981_amd import autotune
+    ns = [1024, 544, 96, 768, 64]
+    rhos = [0.3, 0.36, 0.4, 0.33, 0.5]
+    seeds = [21, 22, 23, 24, 25]
+    steps = 40
+    want, wst = oracle_runs(ns, rhos, seeds, 2 * steps)
+    trace = np.zeros((len(ns), 2 * steps, 2), dtype=np.uint32)
+    for b in range(len(ns)):
+        trace[b, :, 0] = wst[b][:, 1]
+        trace[b, :, 1] = wst[b][:, 3]
+    ref = (trace, [want[0], want[len(ns) // 2], want[-1]])
+    r = autotune.tune_resident(ns, rhos, seeds, "oracle-gate", splits=(16, 48, 112),
+                               steps=steps, log=say, reference=ref)
+    assert len(r["all"]) == 3 and all(x["exact"] for x in r["all"])
