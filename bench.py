@@ -31,13 +31,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 PROFILES = os.path.join(ROOT, "profiles")
+# the sources of the streaming pass kernel, and of the register-resident
+# tile kernel: a stored counter summary holds only while its kernel's hash
+# is unchanged
 KERNEL_SOURCES = ["paper_1804_07981_amd/csrc/bml_pass.hpp",
                   "paper_1804_07981_amd/csrc/bml_tile.hpp"]
+BLOCK_SOURCES = ["paper_1804_07981_amd/csrc/bml_block.hpp"]
 
 
-def kernel_hash() -> str:
+def kernel_hash(resident: bool = False) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in (BLOCK_SOURCES if resident else KERNEL_SOURCES):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -119,6 +123,25 @@ def load_tuning(layout: int, n, group: str | None = None, model: int = 1):
     return None
 
 
+def load_resident_steps(layout: int, n, group: str | None = None, model: int = 1) -> int:
+    """Autotuned steps per launch of the register-resident tile kernel for
+    the lattice (or group) the tuning cache entry names (0: the streaming
+    kernel is faster, or no entry; Models II and III: always 0)."""
+    if model != 1:
+        return 0
+    path = os.path.join(ROOT, "paper_1804_07981_amd", "tune_cache.json")
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        return 0
+    lay = "u8" if layout == 0 else "bp"
+    for key in ([f"gfx950/{lay}/{group}"] if group else []) + [f"gfx950/{lay}/{n}"]:
+        if key in cache:
+            return int(cache[key].get("resident_steps", 0))
+    return 0
+
+
 def load_resident_split(group: str) -> int:
     """Autotuned slab halo of the register-resident batch kernel for a
     batch (0: whole lattices) from the tuning cache, else 0."""
@@ -130,10 +153,23 @@ def load_resident_split(group: str) -> int:
         return 0
 
 
-def traffic_from_profile(name: str, tuning, launches_bytes: float, profiles: str = PROFILES):
+def traffic_from_profile(name: str, tuning, launches_bytes: float, profiles: str = PROFILES,
+                         resident: int = 0):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source with the same tuning; else
-    None."""
+    it was taken on the current kernel source with the same tuning (for the
+    register-resident tile kernel: the same steps per launch); else None."""
+    if resident:
+        path = os.path.join(profiles, name.replace("pass_", "block_", 1)
+                            + f"_k{resident}.traffic.json")
+        try:
+            with open(path) as f:
+                d = json.load(f)
+        except (OSError, ValueError):
+            return None
+        if d.get("kernel_hash") != kernel_hash(resident=True) or \
+                int(d.get("probe", {}).get("resident", 0)) != resident:
+            return None
+        return d.get("hbm_bytes_per_launch")
     path = os.path.join(profiles, f"{name}_t{tuning[1]}.traffic.json")
     if not os.path.exists(path):
         return None
@@ -184,20 +220,23 @@ def pmc_summary(probe_log: str, fetch_dir: str, write_dir: str, profiles: str = 
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         disp = _pmc_per_dispatch(d, counter)
+        step_kernel = "block_kernel" if probe.get("resident") else "pass_kernel"
         copies = [v for name, v in disp.values() if "copy" in name.lower()]
-        passes = [v for name, v in disp.values() if "pass_kernel" in name]
+        passes = [v for name, v in disp.values() if step_kernel in name]
         if not copies or not passes:
-            print(f"{counter}: copy or pass_kernel dispatches missing", file=sys.stderr)
+            print(f"{counter}: copy or {step_kernel} dispatches missing", file=sys.stderr)
             return 1
         copy_kib = max(copies)
         res[counter] = {"copy_kib": copy_kib, "scale": (1 << 20) / copy_kib,
                         "pass_kib_per_dispatch": sum(passes) / len(passes),
                         "dispatches": len(passes)}
     layout = 0 if probe["layout"] == "u8" else 1
-    k = probe["t_phases"] // 2
+    resident = int(probe.get("resident", 0))
+    k = resident or probe["t_phases"] // 2
     alg = bytes_per_cell_step(layout, k) * probe["cells_per_launch"] * k
     hbm = sum(r["pass_kib_per_dispatch"] * 1024 * r["scale"] for r in res.values())
-    out = {"kernel": f"pass_kernel<{probe['layout']}, K={k}>", "probe": probe,
+    kernel = "block_kernel" if resident else "pass_kernel"
+    out = {"kernel": f"{kernel}<{probe['layout']}, K={k}>", "probe": probe,
            "kernel_hash": probe["kernel_hash"],
            "fetch_kib_per_dispatch": res["FETCH_SIZE"]["pass_kib_per_dispatch"],
            "write_kib_per_dispatch": res["WRITE_SIZE"]["pass_kib_per_dispatch"],
@@ -209,8 +248,9 @@ def pmc_summary(probe_log: str, fetch_dir: str, write_dir: str, profiles: str = 
            "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": alg,
            "ratio_to_algorithmic": hbm / alg,
            "dispatches": res["FETCH_SIZE"]["dispatches"]}
-    path = os.path.join(profiles,
-                        f"pass_{probe['layout']}_{probe['n']}_t{probe['t_phases']}.traffic.json")
+    stem = (f"block_{probe['layout']}_{probe['n']}_k{resident}" if resident else
+            f"pass_{probe['layout']}_{probe['n']}_t{probe['t_phases']}")
+    path = os.path.join(profiles, stem + ".traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
@@ -437,14 +477,16 @@ def load_for(args):
 
 
 def measure(B, dev, wl, layout: int, steps: int, warmup: int, mode: str, load, configure,
-            tuning=None) -> dict:
+            tuning=None, resident=None) -> dict:
     """Times `steps` runs of the whole workload (each lattice wl.steps steps)
     after `warmup` untimed ones.  mode "joint": every lattice on one stream,
     advanced together by joint launches (bml_step_group); "streams": one
     stream per lattice, their launches overlapping; "single": the current
-    stream.  Busy time per stream from HIP events on that stream; every
-    recorded count is checked against the initial car numbers afterwards
-    (a mismatch writes its evidence and raises)."""
+    stream.  resident: steps per launch of the register-resident tile kernel
+    (0: the streaming kernel; None: the autotuned choice).  Busy time per
+    stream from HIP events on that stream; every recorded count is checked
+    against the initial car numbers afterwards (a mismatch writes its
+    evidence and raises)."""
     import torch
     from paper_1804_07981_amd.failures import dump_corruption
     group = workloads_mod().MEDIUM_GROUP if len(wl.lattices) > 1 else None
@@ -460,6 +502,12 @@ def measure(B, dev, wl, layout: int, steps: int, warmup: int, mode: str, load, c
         if tun:
             lat.set_tuning(*tun)
         configure(lat)
+        res_k = resident
+        if res_k is None:
+            res_k = 0 if tuning else load_resident_steps(
+                layout, size_key(lt), group if mode == "joint" else None, lat.model)
+        if res_k:
+            lat.set_resident(res_k)
         lats.append(lat)
 
     def run_job():
@@ -500,13 +548,15 @@ def measure(B, dev, wl, layout: int, steps: int, warmup: int, mode: str, load, c
                       flush=True)
             raise
     tr, tp, wpb = lats[0].tuning()
-    k = tp // 2
+    res_k = lats[0].resident
+    k = res_k or tp // 2
     passes = -(-wl.steps // k) * steps
     launches = passes if mode == "joint" else passes * len(lats)
     cells = sum(lt.cells for lt in wl.lattices)
     for lat in lats:
         lat.close()
     return {"gpu_s": gpu_s, "wall_s": wall, "k": k, "tile_rows": tr, "wpb": wpb,
+            "resident": res_k,
             "launches": launches, "cells": cells, "mode": mode,
             "lattices_per_launch": len(lats) if mode == "joint" else 1,
             "lattices_total": len(lats),
@@ -530,12 +580,20 @@ def hbm_roofline(res: dict, layout: int, kname: str, extra: dict | None = None) 
     alg = bytes_per_cell_step(layout, k) * launch_cells * k
     per_launch = res["avg_launch_s"]
     achieved = alg / per_launch / 1e9
-    traffic = traffic_from_profile(kname, (res["tile_rows"], 2 * k, res["wpb"]), alg)
+    traffic = traffic_from_profile(kname, (res["tile_rows"], 2 * k, res["wpb"]), alg,
+                                   resident=res.get("resident", 0))
+    lay = "u8" if layout == 0 else "bitplane"
+    if res.get("resident"):
+        kernel = (f"block_kernel<{lay}, K={k}> (register-resident tiles of 1024 columns x up "
+                  f"to {512 - 2 * k} rows with {k} halo rows, 4 waves/block, "
+                  f"{res['lattices_per_launch']} lattice(s) per launch)")
+    else:
+        kernel = (f"pass_kernel<{lay}, K={k}> (strip rows {res['tile_rows'] or 'auto'}, "
+                  f"{res['wpb']} waves/block, {res['lattices_per_launch']} lattice(s) per "
+                  "launch)")
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-           "kernel": f"pass_kernel<{'u8' if layout == 0 else 'bitplane'}, K={k}> (strip rows "
-                     f"{res['tile_rows'] or 'auto'}, {res['wpb']} waves/block, "
-                     f"{res['lattices_per_launch']} lattice(s) per launch)",
+           "kernel": kernel,
            "algorithmic_bytes_per_launch": alg,
            "avg_launch_us": round(per_launch * 1e6, 2),
            "traffic_gbs": round(traffic / per_launch / 1e9, 1) if traffic else None,
@@ -578,9 +636,13 @@ def main() -> int:
                     help="Model II: the coin stream's seed")
     ap.add_argument("--tuning", type=int, nargs=3, metavar=("TILE_ROWS", "T_PHASES", "WPB"),
                     help="medium/large/rect: run this tuning instead of the autotuned one")
+    ap.add_argument("--resident", type=int, default=None,
+                    help="medium/large/rect: steps per launch of the register-resident tile "
+                         "kernel (0: the streaming kernel; default: the autotuned choice)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("PROBE_LOG", "FETCH_DIR", "WRITE_DIR"),
                     help="no GPU: turn two rocprofv3 --pmc runs of --probe (FETCH_SIZE, "
-                         "WRITE_SIZE) into profiles/pass_<layout>_<n>_t<T>.traffic.json")
+                         "WRITE_SIZE) into profiles/pass_<layout>_<n>_t<T>.traffic.json "
+                         "(block_<layout>_<n>_k<K>.traffic.json for the tile kernel)")
     args = ap.parse_args()
 
     if args.pmc_summary:
@@ -629,10 +691,15 @@ def main() -> int:
         lats = [B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=max(args.steps, 1),
                           device=dev, stream=stream, **lt.kwargs()) for lt in wl.lattices]
         tun = load(layout, size_key(wl.lattices[0]), group)
+        res_k = args.resident if args.resident is not None else (
+            0 if args.tuning else load_resident_steps(layout, size_key(wl.lattices[0]), group,
+                                                      args.model))
         for lat in lats:
             if tun:
                 lat.set_tuning(*tun)
             configure(lat)
+            if res_k:
+                lat.set_resident(res_k)
         B.step_group(lats, args.steps)
         torch.cuda.synchronize()
         tr, tp, wpb = lats[0].tuning()
@@ -642,7 +709,9 @@ def main() -> int:
                           "lattices_per_launch": len(lats),
                           "cells_per_launch": sum(lt.cells for lt in wl.lattices),
                           "t_phases": tp, "tile_rows": tr, "waves_per_block": wpb,
-                          "kernel_hash": kernel_hash()}), flush=True)
+                          "resident": lats[0].resident,
+                          "kernel_hash": kernel_hash(resident=bool(lats[0].resident))}),
+              flush=True)
         for lat in lats:
             lat.close()
         return 0
@@ -655,7 +724,8 @@ def main() -> int:
             f"_model{args.model}" if args.model != 1 else "")
 
     main_mode = "joint" if len(wl.lattices) > 1 else "single"
-    res = measure(B, dev, wl, layout, args.steps, args.warmup, main_mode, load, configure)
+    res = measure(B, dev, wl, layout, args.steps, args.warmup, main_mode, load, configure,
+                  resident=args.resident)
     value = res["gcups"]
     ms_per_step = res["gpu_s"] * 1e3 / args.steps
     alu = alu_roofline(layout, res["k"], value, args.model)
@@ -667,6 +737,16 @@ def main() -> int:
                         avg_launch_us=round(res["avg_launch_s"] * 1e6, 2),
                         cache_resident_gbs=hbm_roofline(res, layout,
                                                         kname_of(wl, layout))["achieved"])
+    elif res["resident"]:
+        # the register-resident tile kernel reads and writes the state once
+        # per K steps: its lane operations (the rule, the counts, the byte
+        # conversion once per launch) bind it, with its HBM rate alongside
+        hbm = hbm_roofline(res, layout, kname_of(wl, layout),
+                           {"copy_ceiling_gbs": copy_ceiling(B, dev)})
+        roofline = dict(alu, kernel=hbm["kernel"], traffic=hbm["traffic"],
+                        avg_launch_us=hbm["avg_launch_us"],
+                        algorithmic_bytes_per_launch=hbm["algorithmic_bytes_per_launch"],
+                        hbm=hbm, effective_gbs=round(value * bytes_per_cell_step(layout, 1), 1))
     else:
         roofline = hbm_roofline(res, layout, kname_of(wl, layout),
                                 {"copy_ceiling_gbs": copy_ceiling(B, dev), "alu": alu,
@@ -698,8 +778,7 @@ def main() -> int:
                                  else lt.rho / 2, lt.seed] for lt in wl.lattices],
                    "lattice_fields": ["rows", "cols", "rho_lr", "rho_tb", "seed"],
                    "steps_per_lattice": wl.steps,
-                   "tuning": {"tile_rows": res["tile_rows"], "t_phases": 2 * res["k"],
-                              "waves_per_block": res["wpb"]},
+                   "tuning": launch_shape(res),
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "step_ms_stats": {"median": round(statistics.median(res["step_ms"]), 3),
@@ -719,10 +798,16 @@ def main() -> int:
         other = 1 - layout
         r2 = measure(B, dev, wl, other, 1, 1, main_mode, load, configure)
         out["variants"] = {("bitplane" if other else "u8"): {
-            "gcups": round(r2["gcups"], 2), "t_phases": 2 * r2["k"],
-            "tile_rows": r2["tile_rows"], "mode": r2["mode"],
+            "gcups": round(r2["gcups"], 2), **launch_shape(r2), "mode": r2["mode"],
             "alu": alu_roofline(other, r2["k"], r2["gcups"], args.model),
             "hbm": hbm_roofline(r2, other, kname_of(wl, other))}}
+        if res["resident"]:
+            # the streaming kernel on the same workload and layout
+            r3 = measure(B, dev, wl, layout, 1, 1, main_mode, load, configure, resident=0)
+            out["variants"][("u8" if layout == 0 else "bitplane") + "_streaming"] = {
+                "gcups": round(r3["gcups"], 2), **launch_shape(r3), "mode": r3["mode"],
+                "alu": alu_roofline(layout, r3["k"], r3["gcups"], args.model),
+                "hbm": hbm_roofline(r3, layout, kname_of(wl, layout))}
 
     if not args.no_variants and args.workload == "large" and args.model == 1 \
             and args.topology == "torus" and not args.tuning:
@@ -744,6 +829,15 @@ def main() -> int:
     return 0
 
 
+def launch_shape(r: dict) -> dict:
+    """The launch shape a measurement ran: the tile kernel's steps per
+    launch, else the streaming kernel's strip rows, phases per pass and
+    waves per block."""
+    if r["resident"]:
+        return {"resident_steps": r["resident"]}
+    return {"tile_rows": r["tile_rows"], "t_phases": 2 * r["k"], "waves_per_block": r["wpb"]}
+
+
 def medium_block(B, dev, workloads, load, configure) -> dict:
     """The four 4096 x 4096 lattices (rho .25/.35/.38/.45, seeds 1-4, 10000
     steps each) in joint launches, both layouts, plus the same lattices on
@@ -754,8 +848,7 @@ def medium_block(B, dev, workloads, load, configure) -> dict:
     for lay in (0, 1):
         r = measure(B, dev, wl, lay, 1, 1, "joint", load, configure)
         name = "u8" if lay == 0 else "bitplane"
-        out[name] = {"gcups": round(r["gcups"], 1), "t_phases": 2 * r["k"],
-                     "tile_rows": r["tile_rows"], "waves_per_block": r["wpb"],
+        out[name] = {"gcups": round(r["gcups"], 1), **launch_shape(r),
                      "avg_launch_us": round(r["avg_launch_s"] * 1e6, 2),
                      "roofline": alu_roofline(lay, r["k"], r["gcups"])}
     r3 = measure(B, dev, wl, 0, 1, 1, "streams", load, configure)

@@ -249,6 +249,23 @@ int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases,
 int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
                    int32_t *waves_per_block);
 
+/* Register-resident tile kernel.  steps = 0 (the default): the streaming
+ * kernel above.  steps = K (even, 2..32): each launch advances the lattice
+ * K steps with the state held in registers: a workgroup loads a tile of
+ * 1024 columns by up to 512 - 2K rows together with one 32-cell halo word
+ * on each side and K halo rows above and below, advances it K steps
+ * (both phases of Sec. 2 per step, synchronous as in Sec. 3) and stores the
+ * tile's own cells, which are exact because what the held block does not
+ * know moves at most one cell and one row per step.  The state is read and
+ * written once per K steps.  Needs the model of Sec. 2 on the torus, rows a
+ * multiple of 32 and columns a multiple of 1024 (EINVAL otherwise; the
+ * library then keeps the streaming kernel), and allocates a small count
+ * buffer with the handle (EDEVICE if that fails).  Synchronises the stream.
+ * bml_get_resident returns K (0 = streaming), < 0 on error.  Results do not
+ * depend on the kernel; only speed does. */
+int bml_set_resident(bml_lattice *L, int32_t steps);
+int bml_get_resident(const bml_lattice *L);
+
 /* Steps run since bml_init (-1 for a NULL handle). */
 int64_t bml_step_count(const bml_lattice *L);
 

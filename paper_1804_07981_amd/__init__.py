@@ -17,6 +17,7 @@ from ._lib import (BML_EBADARG, BML_ECORRUPT, BML_EDEVICE, BML_EINVAL,
                    bml_initial_counts, bml_last_error, bml_pack, bml_set_tuning,
                    bml_state_bytes, bml_state_bytes_rect, bml_init_rect, bml_stats,
                    bml_set_topology, bml_get_topology, BML_TOPO_TORUS, BML_TOPO_KLEIN,
+                   bml_set_resident, bml_get_resident,
                    bml_set_model, bml_get_model, bml_step, bml_step_count, bml_step_group, bml_copy,
                    bml_step_group_static,
                    bml_unpack, exported_symbols, lib, library_path,
@@ -39,6 +40,7 @@ __all__ = [
     "exported_symbols", "bml_state_bytes", "bml_init", "bml_step", "bml_stats",
     "bml_step_group", "step_group", "bml_step_group_static", "bml_copy", "bml_state_bytes_rect", "bml_init_rect",
     "bml_set_topology", "bml_get_topology", "BML_TOPO_TORUS", "BML_TOPO_KLEIN",
+    "bml_set_resident", "bml_get_resident",
     "bml_set_model", "bml_get_model",
     "bml_get_cells", "bml_initial_counts", "bml_set_tuning", "bml_get_tuning",
     "bml_step_count", "bml_current_state", "bml_free", "bml_last_error",

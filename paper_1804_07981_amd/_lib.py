@@ -64,6 +64,8 @@ _SIGNATURES = {
     "bml_initial_counts": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
     "bml_set_tuning": ([_vp, _i32, _i32, _i32], ctypes.c_int),
     "bml_set_topology": ([_vp, _i32], ctypes.c_int),
+    "bml_set_resident": ([_vp, _i32], ctypes.c_int),
+    "bml_get_resident": ([_vp], ctypes.c_int),
     "bml_set_model": ([_vp, _i32, _u64], ctypes.c_int),
     "bml_get_topology": ([_vp], ctypes.c_int),
     "bml_get_model": ([_vp], ctypes.c_int),
@@ -204,6 +206,14 @@ def bml_init_rect(rows: int, cols: int, layout: int, seed: int, rho_lr: float, r
 
 def bml_set_topology(handle: int, topology: int) -> None:
     _check(lib().bml_set_topology(handle, topology))
+
+
+def bml_set_resident(handle: int, steps: int) -> None:
+    _check(lib().bml_set_resident(handle, steps))
+
+
+def bml_get_resident(handle: int) -> int:
+    return _check(lib().bml_get_resident(handle))
 
 
 def bml_set_model(handle: int, model: int, coin_seed: int = 0) -> None:

@@ -96,37 +96,70 @@ def _same(a, b) -> bool:
     return np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def _candidates(strip_rows, t_phases, waves, resident):
+    """Launch shapes to time: the streaming kernel's (tile_rows, t_phases,
+    waves_per_block), then the register-resident tile kernel's steps per
+    launch."""
+    return ([("stream", c) for c in itertools.product(strip_rows, t_phases, waves)]
+            + [("resident", k) for k in resident])
+
+
+def _best(results):
+    """The fastest streaming tuning, with resident_steps = the tile kernel's
+    steps per launch when one of those candidates is faster still (else 0)."""
+    stream = [r for r in results if "resident_steps" not in r]
+    res = [r for r in results if "resident_steps" in r]
+    best = dict(max(stream, key=lambda r: r["gcups"])) if stream else {}
+    best["resident_steps"] = 0
+    if res:
+        rb = max(res, key=lambda r: r["gcups"])
+        best["resident_gcups"] = rb["gcups"]
+        if not stream or rb["gcups"] > best["gcups"]:
+            best["resident_steps"] = rb["resident_steps"]
+    return best
+
+
 def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
                  t_phases=(2, 4, 8, 12, 16), waves=(2, 4), steps: int | None = None,
                  rho: float = 0.3, seed: int = 7, log=print, shape: dict | None = None,
-                 model: int = 1, reference=None) -> dict:
+                 model: int = 1, reference=None, resident=()) -> dict:
     """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice, or
     n rows x shape["cols"] with the draw in `shape` (Lattice keywords), under
-    update rule `model` (1, 2 for Model II, 3 for Model III).  `reference`:
-    the (cells, counts[steps][4]) every candidate must reproduce (default: the
-    first candidate's run)."""
+    update rule `model` (1, 2 for Model II, 3 for Model III), and whether the
+    register-resident tile kernel with one of the steps per launch in
+    `resident` beats it.  `reference`: the (cells, counts[steps][4]) every
+    candidate must reproduce (default: the first candidate's run)."""
     shape = shape or {}
     cells = n * shape.get("cols", n)
     if steps is None:
         # about 4e9 cell-steps per measurement, at least 48 steps
         steps = int(max(48, min(2000, 4e9 / cells)))
         steps -= steps % 48
+        if resident:
+            # whole launches of every tile candidate (16, 24 and 32 steps)
+            steps = -(-steps // 96) * 96
     ref = reference
     results = []
     size = f"{n}x{shape['cols']}" if "cols" in shape else f"{n}"
-    for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
+    for kind, cand in _candidates(strip_rows, t_phases, waves, resident):
         with Lattice(n, rho, seed, layout=layout, stats_cap=steps, **shape) as lat:
             if model != 1:
                 lat.set_model(model, MODEL2_COIN_SEED)
-            lat.set_tuning(tr, tp, w)
+            if kind == "stream":
+                tr, tp, w = cand
+                lat.set_tuning(tr, tp, w)
+                desc = f"rows={tr} T={tp} w={w}"
+            else:
+                lat.set_resident(cand)
+                desc = f"resident K={cand}"
             lat.step(steps)                      # warm-up (and the checked run)
             got = _checked_run(lat, steps, f"tune-{size}",
-                               {"candidate": [tr, tp, w], "rho": rho, "seed": seed})
+                               {"candidate": list(cand) if kind == "stream" else ["resident", cand], "rho": rho, "seed": seed})
             if ref is None:
                 ref = got
             if not _same(got, ref):
-                raise TuningMismatch(f"n={size} layout={layout}: candidate rows={tr} T={tp} "
-                                     f"w={w} differs from the reference")
+                raise TuningMismatch(f"n={size} layout={layout}: candidate {desc} differs "
+                                     "from the reference")
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(lat.stream)
@@ -136,27 +169,31 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
             dt = e0.elapsed_time(e1) / 1e3
         gcups = cells * steps / dt / 1e9
         results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
-                        "gcups": gcups, "exact": True})
-        log(f"  n={size} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS")
-    return {"best": max(results, key=lambda r: r["gcups"]), "all": results, "steps": steps}
+                        "gcups": gcups, "exact": True} if kind == "stream" else
+                       {"resident_steps": cand, "gcups": gcups, "exact": True})
+        log(f"  n={size} layout={layout} {desc}: {gcups:.0f} GCUPS")
+    return {"best": _best(results), "all": results, "steps": steps}
 
 
 def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 32, 48),
                t_phases=(8, 10, 12, 14, 16), waves=(2, 4), steps: int = 480, log=print,
-               model: int = 1, reference=None, make_lattice=Lattice, step=step_group) -> dict:
+               model: int = 1, reference=None, make_lattice=Lattice, step=step_group,
+               resident=()) -> dict:
     """Fastest common tuning for lattices (n, rho, seed) of one size that are
     advanced together by joint launches (bml_step_group): a launch spreads
     the strips of all of them over the device, so the best strip height
     differs from a lone lattice's.  `reference`: one (cells, counts[steps][4])
     pair per lattice, the run every candidate must reproduce (default: the
-    first candidate's).  A candidate whose counts are not conserved, or that
-    differs from the reference, stops the tuning (see the module docstring).
+    first candidate's).  `resident`: steps per launch of the register-resident
+    tile kernel to try as well.  A candidate whose counts are not conserved,
+    or that differs from the reference, stops the tuning (see the module
+    docstring).
     make_lattice / step: the Lattice constructor and the joint step (stand-ins
     in the host-side tests)."""
     ref = reference
     results = []
     cells = float(sum(n * n for n, _, _ in specs))
-    for tr, tp, w in itertools.product(strip_rows, t_phases, waves):
+    for kind, cand in _candidates(strip_rows, t_phases, waves, resident):
         stream = torch.cuda.Stream() if torch.cuda.is_available() else None
         lats = [make_lattice(n, rho, seed, layout=layout, stats_cap=steps, stream=stream)
                 for n, rho, seed in specs]
@@ -164,10 +201,16 @@ def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 3
             for lat in lats:
                 if model != 1:
                     lat.set_model(model, MODEL2_COIN_SEED)
-                lat.set_tuning(tr, tp, w)
+                if kind == "stream":
+                    tr, tp, w = cand
+                    lat.set_tuning(tr, tp, w)
+                    desc = f"rows={tr} T={tp} w={w}"
+                else:
+                    lat.set_resident(cand)
+                    desc = f"resident K={cand}"
             step(lats, steps)                        # warm-up (and the checked run)
             got = [_checked_run(lat, steps, f"tune-{name}",
-                                {"candidate": [tr, tp, w], "lattice_index": i,
+                                {"candidate": list(cand) if kind == "stream" else ["resident", cand], "lattice_index": i,
                                  "spec": list(specs[i]), "group": [list(x) for x in specs]})
                    for i, lat in enumerate(lats)]
             if ref is None:
@@ -175,8 +218,8 @@ def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 3
             for i, (a, b) in enumerate(zip(got, ref)):
                 if not _same(a, b):
                     raise TuningMismatch(
-                        f"group {name} layout={layout}: candidate rows={tr} T={tp} w={w} "
-                        f"differs from the reference on lattice {i} {specs[i]}")
+                        f"group {name} layout={layout}: candidate {desc} differs from the "
+                        f"reference on lattice {i} {specs[i]}")
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -189,9 +232,10 @@ def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 3
                 lat.close()
         gcups = cells * steps / dt / 1e9
         results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
-                        "gcups": gcups, "exact": True})
-        log(f"  group {name} layout={layout} rows={tr} T={tp} w={w}: {gcups:.0f} GCUPS")
-    return {"best": max(results, key=lambda r: r["gcups"]), "all": results, "steps": steps}
+                        "gcups": gcups, "exact": True} if kind == "stream" else
+                       {"resident_steps": cand, "gcups": gcups, "exact": True})
+        log(f"  group {name} layout={layout} {desc}: {gcups:.0f} GCUPS")
+    return {"best": _best(results), "all": results, "steps": steps}
 
 
 def tune_batch(ns, rhos, seeds, name: str, strip_rows=(16, 32, 64, 128),
@@ -291,10 +335,13 @@ def main(argv=None) -> int:
     torch.cuda.set_device(0)
     cache = load(args.cache)
     kw = dict(strip_rows=(0, 64, 256), t_phases=(4, 8, 16), waves=(4,)) if args.quick else {}
+    # the register-resident tile kernel: the model of Sec. 2, 1024-column tiles
+    res = (16, 24, 32) if m == 1 else ()
+    tiles = lambda rows, cols: res if rows % 32 == 0 and cols % 1024 == 0 else ()  # noqa: E731
     for n in args.sizes:
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
-            r = tune_lattice(n, layout, model=m, **kw)
+            r = tune_lattice(n, layout, model=m, resident=tiles(n, n), **kw)
             cache[key(layout, n, m)] = dict(r["best"], steps=r["steps"])
             print(json.dumps({"key": key(layout, n, m), **r["best"]}), flush=True)
     if args.rect:
@@ -303,7 +350,7 @@ def main(argv=None) -> int:
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
             r = tune_lattice(lt.n, layout, rho=lt.rho, seed=lt.seed, shape=lt.kwargs(),
-                             model=m, **kw)
+                             model=m, resident=tiles(lt.n, lt.cols or lt.n), **kw)
             k = key(layout, f"{lt.n}x{lt.cols}", m)
             cache[k] = dict(r["best"], steps=r["steps"])
             print(json.dumps({"key": k, **r["best"]}), flush=True)
@@ -312,7 +359,8 @@ def main(argv=None) -> int:
         specs = [(l.n, l.rho, l.seed) for l in workloads.MEDIUM.lattices]
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
-            r = tune_group(specs, layout, workloads.MEDIUM_GROUP, model=m)
+            r = tune_group(specs, layout, workloads.MEDIUM_GROUP, model=m,
+                           resident=tiles(specs[0][0], specs[0][0]))
             k = key(layout, workloads.MEDIUM_GROUP, m)
             cache[k] = dict(r["best"], steps=r["steps"])
             print(json.dumps({"key": k, **r["best"]}), flush=True)

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "bml.h"
+#include "bml_block.hpp"
 #include "bml_common.hpp"
 #include "bml_pass.hpp"
 #include "bml_tile.hpp"
@@ -393,7 +394,13 @@ struct bml_lattice {
     PassScratch *d_scratch = nullptr;         // library scratch: stats reduction
     uint8_t *d_stage = nullptr;               // bitplane read-back staging (stage_rows rows)
     int32_t stage_rows = 0;
+    // Register-resident tile kernel (bml_block.hpp): steps per launch (0 =
+    // the streaming pass kernel) and its per-tile counts.
+    int32_t block_steps = 0;
+    uint32_t *d_partial = nullptr;            // tiles * BLK_MAX_K * 4 counts
 };
+
+static int block_slabs(int rows, int halo);
 
 // Bytes of the bitplane read-back staging buffer: whole rows, at most
 // STAGE_BYTES (or one row when a row alone is larger).
@@ -687,6 +694,8 @@ int bml_set_topology(bml_lattice *L, int32_t topology)
         return fail(BML_EINVAL, "unknown topology %d", topology);
     if (topology == BML_TOPO_KLEIN && L->model != 1)
         return fail(BML_EINVAL, "Models II and III run on the torus only");
+    if (topology != BML_TOPO_TORUS && L->block_steps)
+        return fail(BML_EINVAL, "the register-resident tile kernel runs on the torus only");
     L->topology = topology;
     return BML_OK;
 }
@@ -703,6 +712,9 @@ int bml_set_model(bml_lattice *L, int32_t model, uint64_t coin_seed)
     if (model != 3 && L->both_cells)
         return fail(BML_EINVAL, "the lattice may hold cells with both an LR and a TB car, "
                                 "which only Model III defines");
+    if (model != 1 && L->block_steps)
+        return fail(BML_EINVAL, "the register-resident tile kernel runs the model of "
+                                "Sec. 2 only");
     L->model = model;
     L->coin_seed = coin_seed;
     return BML_OK;
@@ -742,6 +754,45 @@ int bml_set_tuning(bml_lattice *L, int32_t tile_rows, int32_t t_phases, int32_t 
     L->t_phases = T;
     L->wpb = W;
     return BML_OK;
+}
+
+int bml_set_resident(bml_lattice *L, int32_t steps)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    if (steps < 0 || steps > BLK_MAX_K || steps % 2)
+        return fail(BML_EINVAL, "steps=%d must be 0 or even in [2, %d]", steps, BLK_MAX_K);
+    if (steps) {
+        if (L->model != 1 || L->topology != BML_TOPO_TORUS)
+            return fail(BML_EINVAL, "the register-resident tile kernel runs the model of "
+                                    "Sec. 2 on the torus only");
+        if (L->rows % 32 || L->cols % (32 * BLK_WORDS))
+            return fail(BML_EINVAL, "%d x %d: the register-resident tile kernel needs rows "
+                                    "a multiple of 32 and columns a multiple of %d",
+                        L->rows, L->cols, 32 * BLK_WORDS);
+        const int64_t tiles = (int64_t)(L->cols / 32 / BLK_WORDS) * block_slabs(L->rows, steps);
+        const size_t bytes = (size_t)tiles * BLK_MAX_K * 4 * sizeof(uint32_t);
+        BML_HIP(hipStreamSynchronize(L->stream));   // the old buffer may be in use
+        if (L->d_partial)
+            (void)hipFree(L->d_partial);
+        L->d_partial = nullptr;
+        if (hipMalloc(&L->d_partial, bytes) != hipSuccess) {
+            L->d_partial = nullptr;
+            L->block_steps = 0;
+            return fail(BML_EDEVICE, "hipMalloc of the tile kernel's counts failed");
+        }
+    }
+    L->block_steps = steps;
+    return BML_OK;
+}
+
+int bml_get_resident(const bml_lattice *L)
+{
+    clear_error();
+    if (!live(L))
+        return fail(BML_ESTATE, "invalid handle");
+    return L->block_steps;
 }
 
 int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
@@ -874,6 +925,100 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
     return BML_OK;
 }
 
+// ---- register-resident tile kernel ---------------------------------------
+
+struct BlockTable {
+    BlockFn fn[2] = {};
+    BlockTable() { block_kernels(&fn[IO_U8], &fn[IO_BP]); }
+};
+
+static const BlockTable &block_table()
+{
+    static BlockTable t;
+    return t;
+}
+
+// Row slabs of a lattice of `rows` rows for the tile kernel with `halo`
+// halo rows: the fewest whose 32-row blocks, with the halo, fit 512 rows.
+static int block_slabs(int rows, int halo)
+{
+    const int per = (BLK_ROWS - 2 * halo) / 32;   // 32-row blocks per slab
+    return (rows / 32 + per - 1) / per;
+}
+
+// Per-step counts of every tile summed per lattice, one block per
+// (lattice, step, count); steps at or after rec_from go to the ring.
+struct BlockSumArgs {
+    const uint32_t *partial[MAX_GROUP];
+    uint32_t *stats[MAX_GROUP];
+    int64_t step0[MAX_GROUP], rec_from[MAX_GROUP], cap[MAX_GROUP];
+    int32_t tiles;
+    int32_t n_steps;
+};
+
+__global__ __launch_bounds__(256) void block_sum_kernel(BlockSumArgs a)
+{
+    const int li = blockIdx.x / (a.n_steps * 4);
+    const int j = blockIdx.x - li * a.n_steps * 4;    // step * 4 + count
+    uint32_t v = 0;
+    for (int t = threadIdx.x; t < a.tiles; t += blockDim.x)
+        v += a.partial[li][(size_t)t * BLK_MAX_K * 4 + j];
+    v = wave_sum(v);
+    __shared__ uint32_t part[4];
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t sum = part[0] + part[1] + part[2] + part[3];
+        const int64_t step = a.step0[li] + (j >> 2);
+        if (step >= a.rec_from[li])
+            a.stats[li][(size_t)(step % a.cap[li]) * 4 + (j & 3)] = sum;
+    }
+}
+
+// One launch of the tile kernel: lattices G[0..count) (same size, layout,
+// stream) advance k <= block_steps steps; lattice i is at global step
+// step0[i], and steps at or after rec_from[i] are recorded in its ring.
+static int run_block(bml_lattice *const *G, int count, int k, const int64_t *step0,
+                     const int64_t *rec_from)
+{
+    bml_lattice *L = G[0];
+    const int io = L->layout == BML_LAYOUT_U8 ? IO_U8 : IO_BP;
+    BlockArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n_lat = count;
+    a.rows = L->rows;
+    a.words = L->cols / 32;
+    a.tiles_x = a.words / BLK_WORDS;
+    a.halo = L->block_steps;
+    a.slabs = block_slabs(L->rows, a.halo);
+    a.n_steps = k;
+    const int tiles = a.tiles_x * a.slabs;
+    BlockSumArgs b;
+    std::memset(&b, 0, sizeof b);
+    b.tiles = tiles;
+    b.n_steps = k;
+    for (int i = 0; i < count; ++i) {
+        a.lat[i].src = G[i]->buf[G[i]->cur];
+        a.lat[i].dst = G[i]->buf[G[i]->cur ^ 1];
+        a.lat[i].partial = G[i]->d_partial;
+        b.partial[i] = G[i]->d_partial;
+        b.stats[i] = G[i]->stats;
+        b.step0[i] = step0[i];
+        b.rec_from[i] = rec_from[i];
+        b.cap[i] = G[i]->cap;
+    }
+    hipLaunchKernelGGL(block_table().fn[io], dim3((unsigned)(tiles * count)),
+                       dim3(64 * BLK_WAVES), 0, L->stream, a);
+    BML_HIP(hipGetLastError());
+    hipLaunchKernelGGL(block_sum_kernel, dim3((unsigned)(count * k * 4)), dim3(256), 0,
+                       L->stream, b);
+    BML_HIP(hipGetLastError());
+    for (int i = 0; i < count; ++i)
+        G[i]->cur ^= 1;
+    return BML_OK;
+}
+
 // Advances lattices G[0..count) by n_steps in joint launches.
 static int step_group(bml_lattice *const *G, int count, int64_t n_steps)
 {
@@ -884,11 +1029,12 @@ static int step_group(bml_lattice *const *G, int count, int64_t n_steps)
         rec_from[i] = end[i] - std::min<int64_t>(n_steps, G[i]->cap);
         s[i] = G[i]->steps_done;
     }
-    const int K = G[0]->t_phases / 2;
+    const bool block = G[0]->block_steps > 0;
+    const int K = block ? G[0]->block_steps : G[0]->t_phases / 2;
     int64_t done = 0;
     while (done < n_steps) {
         const int k = (int)std::min<int64_t>(K, n_steps - done);
-        int rc = run_pass(G, count, k, s, rec_from);
+        int rc = block ? run_block(G, count, k, s, rec_from) : run_pass(G, count, k, s, rec_from);
         if (rc)
             return rc;
         done += k;
@@ -936,7 +1082,7 @@ int bml_step_group(bml_lattice *const *handles, int32_t count, int64_t n_steps)
             return fail(BML_EINVAL, "lattice %d differs in size, layout, topology or model from "
                                     "lattice 0", i);
         if (Li->tile_rows != L0->tile_rows || Li->t_phases != L0->t_phases ||
-            Li->wpb != L0->wpb)
+            Li->wpb != L0->wpb || Li->block_steps != L0->block_steps)
             return fail(BML_EINVAL, "lattice %d has another tuning than lattice 0", i);
         if (Li->stream != L0->stream || Li->dev.device != L0->dev.device)
             return fail(BML_EINVAL, "lattice %d is on another stream or device", i);
@@ -1165,6 +1311,8 @@ void bml_free(bml_lattice *L)
         (void)hipFree(L->d_scratch);
     if (L->d_stage)
         (void)hipFree(L->d_stage);
+    if (L->d_partial)
+        (void)hipFree(L->d_partial);
     delete L;
 }
 

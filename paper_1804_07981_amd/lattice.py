@@ -70,6 +70,16 @@ class Lattice:
                    waves_per_block: int = 0) -> None:
         B.bml_set_tuning(self.handle, tile_rows, t_phases, waves_per_block)
 
+    def set_resident(self, steps: int) -> None:
+        """0: the streaming step kernel; K (even, 2..32): the register-resident
+        tile kernel, K steps per launch (torus, Sec. 2's model, rows a
+        multiple of 32, columns a multiple of 1024)."""
+        B.bml_set_resident(self.handle, steps)
+
+    @property
+    def resident(self) -> int:
+        return B.bml_get_resident(self.handle)
+
     def set_topology(self, topology: int) -> None:
         """BML_TOPO_TORUS (default) or BML_TOPO_KLEIN for the steps that follow."""
         B.bml_set_topology(self.handle, topology)

@@ -582,7 +582,8 @@ def test_medium_bench_shape(B, layout, medium_reference):
     import bench
     w = workloads.MEDIUM
     tun = bench.load_tuning(layout, 4096, workloads.MEDIUM_GROUP)
-    say(f"medium bench shape layout={layout} tuning={tun}")
+    res = bench.load_resident_steps(layout, 4096, workloads.MEDIUM_GROUP)
+    say(f"medium bench shape layout={layout} tuning={tun} resident={res}")
     stream = torch.cuda.Stream()
     lats = [B.Lattice(lt.n, lt.rho, lt.seed, layout=layout, stats_cap=MEDIUM_CHECK_STEPS,
                       stream=stream) for lt in w.lattices]
@@ -590,6 +591,8 @@ def test_medium_bench_shape(B, layout, medium_reference):
         for lat in lats:
             if tun:
                 lat.set_tuning(*tun)
+            if res:
+                lat.set_resident(res)
         B.step_group(lats, MEDIUM_CHECK_STEPS)
         for lat, lt, (want, wst) in zip(lats, w.lattices, medium_reference):
             got = lat.cells()
@@ -623,15 +626,19 @@ def large_reference():
 
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_large_whole_lattice(B, layout, large_reference):
-    """32768 x 32768 in the tuned launch shape the benchmark times: 64 steps
-    (8 passes at 8 steps per pass), every cell and all 64 count rows against
+    """32768 x 32768 in the tuned launch shape the benchmark times (the
+    streaming kernel's, or the tile kernel's when it was faster): 64 steps,
+    every cell and all 64 count rows against
     the whole-lattice oracle."""
     import bench
     lt = workloads.LARGE.lattices[0]
     g0, want, wst = large_reference
     tun = bench.load_tuning(layout, lt.n)
-    say(f"large whole lattice layout={layout} tuning={tun}")
+    res = bench.load_resident_steps(layout, lt.n)
+    say(f"large whole lattice layout={layout} tuning={tun} resident={res}")
     with make(B, lt.n, lt.rho, lt.seed, layout, cap=LARGE_CHECK_STEPS, tuning=tun) as lat:
+        if res:
+            lat.set_resident(res)
         lat.step(LARGE_CHECK_STEPS)
         st = stats_array(lat.stats(0, LARGE_CHECK_STEPS))
         got = lat.cells()
@@ -663,6 +670,9 @@ def test_large_sampled_windows(B, layout, large_reference):
     g0, _, wst = large_reference
     import bench
     with make(B, n, rho, seed, layout, cap=steps, tuning=bench.load_tuning(layout, n)) as lat:
+        res = bench.load_resident_steps(layout, n)
+        if res:
+            lat.set_resident(res)
         lat.step(steps)
         got = lat.cells()
         st = stats_array(lat.stats(0, steps))
@@ -728,6 +738,9 @@ def test_rect_large_sampled_windows(B, layout):
         tun = bench.load_tuning(layout, f"{rows}x{cols}")
         if tun:
             lat.set_tuning(*tun)
+        res = bench.load_resident_steps(layout, f"{rows}x{cols}")
+        if res:
+            lat.set_resident(res)
         lat.step(steps)
         got = lat.cells()
         st = stats_array(lat.stats(0, steps))
