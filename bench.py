@@ -55,7 +55,25 @@ def bytes_per_cell_step(layout: int, k: int) -> float:
     return per_cell_pass / k
 
 
-ALU_PEAK_LANE_OPS = 256 * 4 * 64 / 4 * 2.4e9   # CUs x SIMDs x lanes / clocks per op x clock
+# gfx950 vector ALU: 256 CUs x 128 lanes per clock x 2.4 GHz, the rate of
+# the published fp32 vector peak (157.3 TFLOP/s with an FMA counted as two).
+# The unit is a full-rate 32-bit lane-op slot: plain logic ops (and, or,
+# xor, three-input bit ops, moves) take one; popcount (v_bcnt_u32_b32) and
+# the funnel shift (v_alignbit_b32) issue at half that rate on this chip and
+# take two (profiles/valu_issue_rates.md).
+ALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# Slots per 32-cell word and step of the rule of Sec. 2: horizontal phase
+# occupancy or, the right neighbour's occupancy across the word boundary (a
+# funnel shift), movers and-not, arrivals (a funnel shift), update xor3;
+# vertical phase emptiness nor, movers and, update xor3: 6 logic ops + 2
+# funnel shifts = 10 slots; the four per-step counts are four popcount-adds
+# = 8 slots.
+RULE_SLOTS = 6 + 2 * 2
+COUNT_SLOTS = 4 * 2
+# Byte cells <-> bitplanes, in registers, per 32-cell word and pass: gather
+# bit 0 and bit 1 of 32 bytes into two words and rotate the bit index
+# (about 64 logic ops), and the inverse.
+CONVERT_SLOTS = 128
 
 # The paper's fastest measured runs (Sec. 7, table of mean execution times:
 # rho 0.3, 1024 steps, times read as seconds), with their machines: context
@@ -79,15 +97,16 @@ def paper_context() -> dict:
 
 
 def alu_roofline(layout: int, k: int, gcups: float, model: int = 1) -> dict:
-    """Algorithmic lane-ops of the bitwise rule: 9 logic ops per 32-cell
-    word and step plus 4 popcount-adds for the per-step counts; the byte
-    layout adds its in-register conversion, about 80 lane-ops per word per
-    pass of k steps.  Model II: 27 logic ops (the contested-cell masks and
-    both moves in one phase), 4 popcount-adds and about 29 lane-ops for the
-    word's coin hash (a 64-bit SplitMix64 output in 32-bit lane ops).  Model
-    III: the one phase without the coin, 9 logic ops + 4 popcount-adds."""
-    per_word = 27 + 4 + 29 if model == 2 else 13
-    per_cell_step = (per_word + (80.0 / k if layout == 0 else 0.0)) / 32
+    """Algorithmic full-rate lane-op slots per cell-step over the achieved
+    GCUPS, against ALU_PEAK_LANE_OPS.  Model I and Model III (one phase of
+    the same op count): RULE_SLOTS + COUNT_SLOTS per word-step.  Model II:
+    about 27 logic ops for the contested-cell masks and both moves in one
+    phase (two of them funnel shifts, +2), the counts, and about 38 slots
+    for the word's coin hash (a 64-bit SplitMix64 output in 32-bit lane ops,
+    its three multiplies at quarter rate).  The byte layout adds
+    CONVERT_SLOTS per word per pass of k steps."""
+    per_word = (27 + 2 + COUNT_SLOTS + 38) if model == 2 else RULE_SLOTS + COUNT_SLOTS
+    per_cell_step = (per_word + (CONVERT_SLOTS / k if layout == 0 else 0.0)) / 32
     achieved = gcups * 1e9 * per_cell_step
     return {"bound": "alu", "achieved": round(achieved / 1e12, 2),
             "peak": round(ALU_PEAK_LANE_OPS / 1e12, 2), "unit": "Tlane-op/s",

@@ -135,9 +135,6 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
         # about 4e9 cell-steps per measurement, at least 48 steps
         steps = int(max(48, min(2000, 4e9 / cells)))
         steps -= steps % 48
-        if resident:
-            # whole launches of every tile candidate (16, 24 and 32 steps)
-            steps = -(-steps // 96) * 96
     ref = reference
     results = []
     size = f"{n}x{shape['cols']}" if "cols" in shape else f"{n}"
@@ -160,14 +157,16 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
             if not _same(got, ref):
                 raise TuningMismatch(f"n={size} layout={layout}: candidate {desc} differs "
                                      "from the reference")
+            # timed: whole launches of the candidate
+            timed = steps if kind == "stream" else -(-steps // cand) * cand
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(lat.stream)
-            lat.step(steps)
+            lat.step(timed)
             e1.record(lat.stream)
             torch.cuda.synchronize()
             dt = e0.elapsed_time(e1) / 1e3
-        gcups = cells * steps / dt / 1e9
+        gcups = cells * timed / dt / 1e9
         results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
                         "gcups": gcups, "exact": True} if kind == "stream" else
                        {"resident_steps": cand, "gcups": gcups, "exact": True})
@@ -220,17 +219,19 @@ def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 3
                     raise TuningMismatch(
                         f"group {name} layout={layout}: candidate {desc} differs from the "
                         f"reference on lattice {i} {specs[i]}")
+            # timed: whole launches of the candidate
+            timed = steps if kind == "stream" else -(-steps // cand) * cand
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            step(lats, steps)
+            step(lats, timed)
             e1.record(stream)
             torch.cuda.synchronize()
             dt = e0.elapsed_time(e1) / 1e3
         finally:
             for lat in lats:
                 lat.close()
-        gcups = cells * steps / dt / 1e9
+        gcups = cells * timed / dt / 1e9
         results.append({"tile_rows": tr, "t_phases": tp, "waves_per_block": w,
                         "gcups": gcups, "exact": True} if kind == "stream" else
                        {"resident_steps": cand, "gcups": gcups, "exact": True})
@@ -336,7 +337,7 @@ def main(argv=None) -> int:
     cache = load(args.cache)
     kw = dict(strip_rows=(0, 64, 256), t_phases=(4, 8, 16), waves=(4,)) if args.quick else {}
     # the register-resident tile kernel: the model of Sec. 2, 1024-column tiles
-    res = (16, 24, 32) if m == 1 else ()
+    res = (16, 24, 28, 32) if m == 1 else ()
     tiles = lambda rows, cols: res if rows % 32 == 0 and cols % 1024 == 0 else ()  # noqa: E731
     for n in args.sizes:
         for lay in args.layouts:

@@ -5,7 +5,9 @@
 // rows.  A 4-wave workgroup holds one tile with one halo word on each side
 // and K halo rows above and below, two rows per lane (34 LR and 34 TB words
 // per row), loads it once, advances it K steps in registers and stores the
-// tile's own words and rows.  The rule of Marzolla, arXiv:1804.07981,
+// tile's own words and rows.  Three such workgroups fit a CU (168 VGPRs
+// per lane, 41 KB of LDS each), so each SIMD interleaves three waves.  The
+// rule of Marzolla, arXiv:1804.07981,
 // Sec. 2 decides every move from the cell's neighbour in the direction of
 // travel, so what the held block does not know (the cells beyond its halo)
 // travels at most one cell right and one row down per step, and its error
@@ -34,7 +36,7 @@ namespace bml {
 
 constexpr int BLK_WORDS = 32;                 // tile words (columns / 32)
 constexpr int BLK_W = BLK_WORDS + 2;          // words held per row: a halo word each side
-constexpr int BLK_WAVES = 4;                  // one wave per SIMD, two workgroups per CU
+constexpr int BLK_WAVES = 4;                  // one wave per SIMD, three workgroups per CU
 constexpr int BLK_ROWS = BLK_WAVES * 128;     // rows a workgroup holds (two per lane)
 constexpr int BLK_MAX_K = 32;                 // steps per launch (the halo word's 32 cells)
 
@@ -58,14 +60,76 @@ struct BlockArgs {
     int32_t n_steps;
 };
 
+// Loads and stores go through a per-wave staging area so that each memory
+// instruction covers whole 128-byte lines of a few rows (lanes along a row)
+// while the step loop keeps two rows per lane: the tile's 32 own words are
+// moved in four chunks of 8 words x 128 rows.  A staged row is 9 words
+// (8 + 1 pad) and a lane's upper and lower rows sit in separate halves, so
+// a lane reading its own rows hits bank 9 * lane + j: no conflicts.
+constexpr int BLK_CHUNK = 8;                  // words per staged chunk
+constexpr int BLK_SROW = BLK_CHUNK + 1;       // padded staged row
+
+// Exchange rows padded to 36 words: read and written 4 words (16 bytes) at a
+// time.
+constexpr int BLK_XW = 36;
+constexpr int BLK_G = 4;                      // words per scheduling group of the step
+
 struct BlockShared {
-    uint32_t x[2][BLK_WAVES][2][BLK_W];      // as ResidentShared::x
-    uint32_t none[BLK_W];                     // zero: no neighbour beyond the halo rows
+    uint32_t x[2][BLK_WAVES][2][BLK_XW];     // as ResidentShared::x
+    uint32_t none[BLK_XW];                    // zero: no neighbour beyond the halo rows
     uint32_t cnt[BLK_MAX_K][BLK_WAVES][4];    // per-wave counts of each step
+    uint32_t stage[BLK_WAVES][2][2 * 64 * BLK_SROW];   // [wave][plane][row half][lane, word]
 };
 
+// a ^ b ^ c as one three-input bit operation
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ int stage_index(int r, int j)
+{
+    return (r & 1) * 64 * BLK_SROW + (r >> 1) * BLK_SROW + j;
+}
+
+// 16 byte cells (d.x = cells 0..3, byte k of a dword = cell 4q + k) to one
+// word holding their LR bits in bits 0..15 and TB bits in bits 16..31.  The
+// gather leaves the LR bit of cell 4q + k at 8k + q and its TB bit at
+// 8k + 4 + q; index_rotl2 moves position [k t q] to [t q k].
+__device__ __forceinline__ uint32_t bytes16_to_halves(u32x4 d)
+{
+    uint32_t x = (d.x & 0x01010101u) | ((d.x & 0x02020202u) << 3);
+    x |= ((d.y & 0x01010101u) << 1) | ((d.y & 0x02020202u) << 4);
+    x |= ((d.z & 0x01010101u) << 2) | ((d.z & 0x02020202u) << 5);
+    x |= ((d.w & 0x01010101u) << 3) | ((d.w & 0x02020202u) << 6);
+    return index_rotl2(x);
+}
+
+// The inverse: the delta swaps of index_rotl2 in reverse order (each is its
+// own inverse), then the bits back to bytes.
+__device__ __forceinline__ u32x4 halves_to_bytes16(uint32_t x)
+{
+    x = delta_swap(x, 14, 0x0000ccccu);
+    x = delta_swap(x, 7, 0x00aa00aau);
+    x = delta_swap(x, 2, 0x0c0c0c0cu);
+    x = delta_swap(x, 1, 0x22222222u);
+    return (u32x4){(x & 0x01010101u) | ((x >> 3) & 0x02020202u),
+                   ((x >> 1) & 0x01010101u) | ((x >> 4) & 0x02020202u),
+                   ((x >> 2) & 0x01010101u) | ((x >> 5) & 0x02020202u),
+                   ((x >> 3) & 0x01010101u) | ((x >> 6) & 0x02020202u)};
+}
+
+// Every lane's LDS accesses before this point are complete and visible to
+// the wave's other lanes after it.
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int IO>
-__global__ __launch_bounds__(64 * BLK_WAVES, 2) void block_kernel(BlockArgs a)
+__global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
 {
     constexpr int W = BLK_W;
     __shared__ BlockShared sh;
@@ -76,9 +140,11 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 2) void block_kernel(BlockArgs a)
     const int local = blockIdx.x - li * tiles;
     const int slab = local / a.tiles_x;
     const int tx = local - slab * a.tiles_x;
-    const int blocks32 = a.rows / 32;
-    const int r0 = blocks32 * slab / a.slabs * 32;
-    const int R = blocks32 * (slab + 1) / a.slabs * 32 - r0;
+    // Slabs cut at even rows, as equal as possible (at most
+    // BLK_ROWS - 2 * halo rows each).
+    const int pairs = a.rows / 2;
+    const int r0 = pairs * slab / a.slabs * 2;
+    const int R = pairs * (slab + 1) / a.slabs * 2 - r0;
     const int H = a.halo;
     const int held = R + 2 * H;
     const int waves = (held + 127) / 128;
@@ -99,17 +165,28 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 2) void block_kernel(BlockArgs a)
     const __amdgpu_buffer_rsrc_t src = make_rsrc(a.lat[li].src, state_bytes);
     const __amdgpu_buffer_rsrc_t dst = make_rsrc(a.lat[li].dst, state_bytes);
 
-    // Lattice rows of the lane (periodic) and word w0 - 1 + i (periodic).
+    // Lattice rows of the lane (periodic).
     const int g0 = row_ok ? (r0 - H + row + 2 * N) % N : 0;
     const int g1 = g0 + 1 == N ? 0 : g0 + 1;
     const int w0 = tx * BLK_WORDS;
+    const int wrow0 = wave * 128;                           // the wave's first held row
+    const int wrows = wave_on ? min(128, held - wrow0) : 0; // rows the wave holds
+    // Lattice row of held row wrow0 + q (0 <= q < 8): the staged loops step
+    // it by 4 or 8 rows (N >= 32).
+    const int gbase = __builtin_amdgcn_readfirstlane((r0 - H + wrow0 + 2 * N) % N);
+    uint32_t *stL = sh.stage[wave][0];
+    uint32_t *stT = sh.stage[wave][1];
     uint32_t L0[W], T0[W], L1[W], T1[W];
-    auto load_row = [&](int g, uint32_t (&Lr)[W], uint32_t (&Tr)[W]) {
+
+    // The halo words (held words 0 and W - 1: lattice words w0 - 1 and
+    // w0 + 32, periodic), each lane its own two rows.
+    auto load_halo = [&](int g, uint32_t (&Lr)[W], uint32_t (&Tr)[W]) {
         const uint32_t ro = (uint32_t)g * row_bytes;
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            const int w = i == 0 ? (w0 == 0 ? words - 1 : w0 - 1)
-                                 : (w0 + i - 1 == words ? 0 : w0 + i - 1);
+        for (int h = 0; h < 2; ++h) {
+            const int i = h ? W - 1 : 0;
+            const int w = h ? (w0 + BLK_WORDS == words ? 0 : w0 + BLK_WORDS)
+                            : (w0 == 0 ? words - 1 : w0 - 1);
             if constexpr (IO == IO_U8) {
                 const u32x4 u0 = __builtin_amdgcn_raw_buffer_load_b128(
                     src, ro + (uint32_t)w * 32u, 0, 0);
@@ -124,108 +201,294 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 2) void block_kernel(BlockArgs a)
             }
         }
     };
-    auto store_row = [&](int g, const uint32_t (&Lr)[W], const uint32_t (&Tr)[W]) {
-        const uint32_t ro = (uint32_t)g * row_bytes;
-#pragma unroll
-        for (int i = 1; i < W - 1; ++i) {
-            const uint32_t w = (uint32_t)(w0 + i - 1);
-            if constexpr (IO == IO_U8) {
-                uint32_t b[8];
-                planes_to_bytes(Lr[i], Tr[i], b);
-                __builtin_amdgcn_raw_buffer_store_b128((u32x4){b[0], b[1], b[2], b[3]}, dst,
-                                                       ro + w * 32u, 0, 0);
-                __builtin_amdgcn_raw_buffer_store_b128((u32x4){b[4], b[5], b[6], b[7]}, dst,
-                                                       ro + w * 32u + 16u, 0, 0);
-            } else {
-                __builtin_amdgcn_raw_buffer_store_b32(Lr[i], dst, ro + w * 4u, 0, 0);
-                __builtin_amdgcn_raw_buffer_store_b32(Tr[i], dst, ro + plane_bytes + w * 4u, 0,
-                                                      0);
+
+    // Chunk c of the tile's own words (held words 1 + 8c .. 8 + 8c) of the
+    // wave's rows into the staging area: uint8, 16 lanes per row (16 cells,
+    // half a word, each), four rows per load; bitplanes, 8 lanes per row and
+    // plane, eight rows per load.  Rows beyond the held block stage zeros.
+    auto stage_in = [&](int c) {
+        if constexpr (IO == IO_U8) {
+            uint16_t *sL = reinterpret_cast<uint16_t *>(stL);
+            uint16_t *sT = reinterpret_cast<uint16_t *>(stT);
+            const int q = lane >> 4, w = (lane & 15) >> 1, hf = lane & 1;
+            const uint32_t co = (uint32_t)(w0 + BLK_CHUNK * c + w) * 32u + (uint32_t)hf * 16u;
+            int g = gbase + q;
+            g = g >= N ? g - N : g;
+#pragma unroll 16
+            for (int it = 0; it < 32; ++it) {
+                const int r = 4 * it + q;
+                // Unconditional loads (g is always a lattice row), so that
+                // the unrolled loads are all in flight before the first use.
+                uint32_t x = bytes16_to_halves(__builtin_amdgcn_raw_buffer_load_b128(
+                    src, (uint32_t)g * row_bytes + co, 0, 0));
+                x = r < wrows ? x : 0u;
+                const int si = 2 * stage_index(r, w) + hf;
+                sL[si] = (uint16_t)x;
+                sT[si] = (uint16_t)(x >> 16);
+                g += 4;
+                g = g >= N ? g - N : g;
+            }
+        } else {
+            const int q = lane >> 3, w = lane & 7;
+            const uint32_t co = (uint32_t)(w0 + BLK_CHUNK * c + w) * 4u;
+            int g = gbase + q;
+            g = g >= N ? g - N : g;
+#pragma unroll 4
+            for (int it = 0; it < 16; ++it) {
+                const int r = 8 * it + q;
+                const uint32_t o = (uint32_t)g * row_bytes + co;
+                const uint32_t l = __builtin_amdgcn_raw_buffer_load_b32(src, o, 0, 0);
+                const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(src, o + plane_bytes, 0, 0);
+                stL[stage_index(r, w)] = r < wrows ? l : 0u;
+                stT[stage_index(r, w)] = r < wrows ? t : 0u;
+                g += 8;
+                g = g >= N ? g - N : g;
             }
         }
     };
+    // The reverse for the counted rows: each lane stages its own rows' words
+    // of chunk c, then the wave stores them along the rows.
+    auto stage_out = [&](int c) {
+        if constexpr (IO == IO_U8) {
+            const uint16_t *sL = reinterpret_cast<const uint16_t *>(stL);
+            const uint16_t *sT = reinterpret_cast<const uint16_t *>(stT);
+            const int q = lane >> 4, w = (lane & 15) >> 1, hf = lane & 1;
+            const uint32_t co = (uint32_t)(w0 + BLK_CHUNK * c + w) * 32u + (uint32_t)hf * 16u;
+            int g = gbase + q;
+            g = g >= N ? g - N : g;
+#pragma unroll 8
+            for (int it = 0; it < 32; ++it) {
+                const int r = 4 * it + q;
+                const int hr = wrow0 + r;
+                if (hr >= H && hr < H + R) {
+                    const int si = 2 * stage_index(r, w) + hf;
+                    const uint32_t x = (uint32_t)sL[si] | ((uint32_t)sT[si] << 16);
+                    __builtin_amdgcn_raw_buffer_store_b128(halves_to_bytes16(x), dst,
+                                                           (uint32_t)g * row_bytes + co, 0, 0);
+                }
+                g += 4;
+                g = g >= N ? g - N : g;
+            }
+        } else {
+            const int q = lane >> 3, w = lane & 7;
+            const uint32_t co = (uint32_t)(w0 + BLK_CHUNK * c + w) * 4u;
+            int g = gbase + q;
+            g = g >= N ? g - N : g;
+#pragma unroll 4
+            for (int it = 0; it < 16; ++it) {
+                const int r = 8 * it + q;
+                const int hr = wrow0 + r;
+                if (hr >= H && hr < H + R) {
+                    const uint32_t o = (uint32_t)g * row_bytes + co;
+                    __builtin_amdgcn_raw_buffer_store_b32(stL[stage_index(r, w)], dst, o, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(stT[stage_index(r, w)], dst,
+                                                          o + plane_bytes, 0, 0);
+                }
+                g += 8;
+                g = g >= N ? g - N : g;
+            }
+        }
+    };
+
 #pragma unroll
     for (int i = 0; i < W; ++i)
         L0[i] = T0[i] = L1[i] = T1[i] = 0;
-    if (row_ok) {
-        load_row(g0, L0, T0);
-        load_row(g1, L1, T1);
+    if (wave_on) {
+#pragma unroll
+        for (int c = 0; c < BLK_WORDS / BLK_CHUNK; ++c) {
+            stage_in(c);
+            wave_sync_lds();
+#pragma unroll
+            for (int j = 0; j < BLK_CHUNK; ++j) {
+                const int i = 1 + BLK_CHUNK * c + j;
+                L0[i] = stL[stage_index(2 * lane, j)];
+                T0[i] = stT[stage_index(2 * lane, j)];
+                L1[i] = stL[stage_index(2 * lane + 1, j)];
+                T1[i] = stT[stage_index(2 * lane + 1, j)];
+            }
+            wave_sync_lds();
+        }
     }
-    if (threadIdx.x < W)
+    if (row_ok) {
+        load_halo(g0, L0, T0);
+        load_halo(g1, L1, T1);
+    }
+    if (threadIdx.x < BLK_XW)
         sh.none[threadIdx.x] = 0;
 
-    // Horizontal phase of one row with open ends: the cell beyond the last
+    // Horizontal phase of both rows with open ends: the cell beyond the last
     // held one counts as occupied, nothing arrives into the first.  Every
-    // mover is decided before any word changes.  Returns the LR movers of
-    // the tile's own words; E receives the row's emptiness after the phase.
-    auto hphase = [&](uint32_t (&Lr)[W], const uint32_t (&Tr)[W], uint32_t (&E)[W],
-                      uint32_t &n_lr) {
-        uint32_t c = 0;
-        uint32_t mv_prev = 0, o = Lr[0] | Tr[0];
+    // mover is decided before any word changes.  The words go in groups of
+    // BLK_G, each stage of the rule applied to the group's words of both
+    // rows before the next stage, so that a lone wave finds independent
+    // instructions to issue back to back.  Returns the LR movers of the
+    // tile's own words.  The emptiness the vertical phase needs is
+    // recomputed there from the planes (no array of it stays live).
+    auto hphase = [&](uint32_t &n_lr) {
+        // one accumulator per popcount stream: each popcount adds into its
+        // own (v_bcnt_u32_b32 with an addend), no separate adds
+        uint32_t c0 = 0, c1 = 0, n0 = 0, n1 = 0;
+        uint32_t p0 = 0, p1 = 0, o0 = L0[0] | T0[0], o1 = L1[0] | T1[0];
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            const uint32_t on = i + 1 < W ? (Lr[i + 1] | Tr[i + 1]) : 0xffffffffu;
-            const uint32_t mv = Lr[i] & ~__builtin_amdgcn_alignbit(on, o, 1);
-            o = on;
-            const uint32_t arrive = __builtin_amdgcn_alignbit(mv, mv_prev, 31);
-            Lr[i] = Lr[i] ^ mv ^ arrive;    // movers leave, arrivals land (disjoint)
-            E[i] = ~(Lr[i] | Tr[i]);
-            if (i >= 1 && i < W - 1) {
-                c += __builtin_popcount(mv);
-                n_lr += __builtin_popcount(Lr[i]);
+        for (int g = 0; g < W; g += BLK_G) {
+            uint32_t on0[BLK_G], on1[BLK_G], m0[BLK_G], m1[BLK_G];
+#pragma unroll
+            for (int j = 0; j < BLK_G; ++j) {       // occupancy of the next word
+                const int i = g + j;
+                if (i < W) {
+                    on0[j] = i + 1 < W ? (L0[i + 1] | T0[i + 1]) : 0xffffffffu;
+                    on1[j] = i + 1 < W ? (L1[i + 1] | T1[i + 1]) : 0xffffffffu;
+                }
             }
+#pragma unroll
+            for (int j = 0; j < BLK_G; ++j) {       // movers: the next cell is empty
+                const int i = g + j;
+                if (i < W) {
+                    m0[j] = L0[i] & ~__builtin_amdgcn_alignbit(on0[j], j ? on0[j - 1] : o0, 1);
+                    m1[j] = L1[i] & ~__builtin_amdgcn_alignbit(on1[j], j ? on1[j - 1] : o1, 1);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < BLK_G; ++j) {       // movers leave, arrivals land (disjoint)
+                const int i = g + j;
+                if (i < W) {
+                    L0[i] = xor3(L0[i], m0[j],
+                                 __builtin_amdgcn_alignbit(m0[j], j ? m0[j - 1] : p0, 31));
+                    L1[i] = xor3(L1[i], m1[j],
+                                 __builtin_amdgcn_alignbit(m1[j], j ? m1[j - 1] : p1, 31));
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < BLK_G; ++j) {
+                const int i = g + j;
+                if (i >= 1 && i < W - 1) {
+                    c0 = __builtin_popcount(m0[j]) + c0;
+                    c1 = __builtin_popcount(m1[j]) + c1;
+                    n0 = __builtin_popcount(L0[i]) + n0;
+                    n1 = __builtin_popcount(L1[i]) + n1;
+                    asm("" : "+v"(c0), "+v"(c1), "+v"(n0), "+v"(n1));
+                }
+            }
+            const int last = (W - g < BLK_G ? W - g : BLK_G) - 1;
+            o0 = on0[last];
+            o1 = on1[last];
+            p0 = m0[last];
+            p1 = m1[last];
             // Opaque new values (and counts): updated in place here, not
             // carried as pieces to the end of the step.
-            asm("" : "+v"(Lr[i]), "+v"(E[i]), "+v"(c), "+v"(n_lr));
-            mv_prev = mv;
-            if ((i + 1) % RES_GROUP == 0)
-                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < BLK_G; ++j) {
+                const int i = g + j;
+                if (i < W)
+                    asm("" : "+v"(L0[i]), "+v"(L1[i]));
+            }
+            asm("" : "+v"(c0), "+v"(c1), "+v"(n0), "+v"(n1));
+            __builtin_amdgcn_sched_barrier(0);
         }
-        return c;
+        n_lr = n0 + n1;
+        return c0 + c1;
     };
 
     for (int s = 0; s < n_steps; ++s) {
         const int p = s & 1;
-        uint32_t E0[W], E1[W];
-        uint32_t n_lr = 0, c_lr = 0, n_tb = 0, c_tb = 0;
+        uint32_t n_lr = 0, c_lr = 0, n_tb = 0, c_tb = 0, n_tb1 = 0, c_tb1 = 0;
         if (wave_on) {
-            c_lr = hphase(L0, T0, E0, n_lr);
-            c_lr += hphase(L1, T1, E1, n_lr);
+            c_lr = hphase(n_lr);
             if (lane == 0) {
 #pragma unroll
-                for (int i = 0; i < W; ++i)
-                    sh.x[p][wave][0][i] = E0[i];
+                for (int i = 0; i < BLK_XW; i += 4)
+                    *reinterpret_cast<u32x4 *>(&sh.x[p][wave][0][i]) =
+                        (u32x4){~(L0[i] | T0[i]), ~(L0[i + 1] | T0[i + 1]),
+                                i + 2 < W ? ~(L0[i + 2] | T0[i + 2]) : 0u,
+                                i + 3 < W ? ~(L0[i + 3] | T0[i + 3]) : 0u};
             }
             if (lane == last_lane) {
 #pragma unroll
-                for (int i = 0; i < W; ++i)
-                    sh.x[p][wave][1][i] = T1[i];
+                for (int i = 0; i < BLK_XW; i += 4)
+                    *reinterpret_cast<u32x4 *>(&sh.x[p][wave][1][i]) =
+                        (u32x4){T1[i], T1[i + 1], i + 2 < W ? T1[i + 2] : 0u,
+                                i + 3 < W ? T1[i + 3] : 0u};
             }
         }
         __syncthreads();
         if (wave_on) {
             const uint32_t *xb = wdown >= 0 ? sh.x[p][wdown][0] : sh.none;
             const uint32_t *xa = wup >= 0 ? sh.x[p][wup][1] : sh.none;
+            // The neighbour rows four words at a time, one group ahead of
+            // their use, so that LDS latency hides behind the previous group.
+            u32x4 nb = *reinterpret_cast<const u32x4 *>(xb);
+            u32x4 na = *reinterpret_cast<const u32x4 *>(xa);
 #pragma unroll
-            for (int i = 0; i < W; ++i) {
-                const uint32_t e_x = xb[i];
-                const uint32_t t_x = xa[i];
-                uint32_t e_below = from_below_or(e_x, E0[i]);
-                // The lane shift runs with every lane on (see bml_resident.hpp).
-                asm volatile("" : "+v"(e_below));
-                e_below = lane == last_lane ? e_x : e_below;
-                const uint32_t mv0 = T0[i] & E1[i];
-                const uint32_t mv1 = T1[i] & e_below;
-                const uint32_t arrive = from_above_or(t_x & E0[i], mv1);
-                T0[i] = T0[i] ^ mv0 ^ arrive;
-                T1[i] = T1[i] ^ mv1 ^ mv0;
-                if (i >= 1 && i < W - 1) {
-                    c_tb += __builtin_popcount(mv0) + __builtin_popcount(mv1);
-                    n_tb += __builtin_popcount(T0[i]) + __builtin_popcount(T1[i]);
+            for (int g = 0; g < BLK_XW; g += 4) {
+                const u32x4 cb = nb, ca = na;
+                if (g + 4 < BLK_XW) {
+                    nb = *reinterpret_cast<const u32x4 *>(xb + g + 4);
+                    na = *reinterpret_cast<const u32x4 *>(xa + g + 4);
                 }
-                asm("" : "+v"(T0[i]), "+v"(T1[i]), "+v"(c_tb), "+v"(n_tb));
-                if ((i + 1) % RES_GROUP == 0)
-                    __builtin_amdgcn_sched_barrier(0);
+                uint32_t e0[4], e1[4], eb[4], mv0[4], mv1[4], ar[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W) {
+                        e0[j] = ~(L0[i] | T0[i]);
+                        e1[j] = ~(L1[i] | T1[i]);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W) {
+                        eb[j] = from_below_or(cb[j], e0[j]);
+                        // The lane shift runs with every lane on (see
+                        // bml_resident.hpp).
+                        asm volatile("" : "+v"(eb[j]));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W) {
+                        eb[j] = lane == last_lane ? cb[j] : eb[j];
+                        mv0[j] = T0[i] & e1[j];
+                        mv1[j] = T1[i] & eb[j];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W)
+                        ar[j] = from_above_or(ca[j] & e0[j], mv1[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W) {
+                        T0[i] = xor3(T0[i], mv0[j], ar[j]);
+                        T1[i] = xor3(T1[i], mv1[j], mv0[j]);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i >= 1 && i < W - 1) {
+                        c_tb = __builtin_popcount(mv0[j]) + c_tb;
+                        c_tb1 = __builtin_popcount(mv1[j]) + c_tb1;
+                        n_tb = __builtin_popcount(T0[i]) + n_tb;
+                        n_tb1 = __builtin_popcount(T1[i]) + n_tb1;
+                        asm("" : "+v"(c_tb), "+v"(c_tb1), "+v"(n_tb), "+v"(n_tb1));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W)
+                        asm("" : "+v"(T0[i]), "+v"(T1[i]));
+                }
+                asm("" : "+v"(c_tb), "+v"(c_tb1), "+v"(n_tb), "+v"(n_tb1));
+                __builtin_amdgcn_sched_barrier(0);
             }
+            c_tb += c_tb1;
+            n_tb += n_tb1;
             const uint32_t t0 = wave_total(counted ? n_lr : 0u);
             const uint32_t t1 = wave_total(counted ? c_lr : 0u);
             const uint32_t t2 = wave_total(counted ? n_tb : 0u);
@@ -252,9 +515,21 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 2) void block_kernel(BlockArgs a)
             v += sh.cnt[st][w][q];
         part[j] = v;
     }
-    if (counted) {
-        store_row(g0, L0, T0);
-        store_row(g1, L1, T1);
+    if (wave_on) {
+#pragma unroll
+        for (int c = 0; c < BLK_WORDS / BLK_CHUNK; ++c) {
+#pragma unroll
+            for (int j = 0; j < BLK_CHUNK; ++j) {
+                const int i = 1 + BLK_CHUNK * c + j;
+                stL[stage_index(2 * lane, j)] = L0[i];
+                stT[stage_index(2 * lane, j)] = T0[i];
+                stL[stage_index(2 * lane + 1, j)] = L1[i];
+                stT[stage_index(2 * lane + 1, j)] = T1[i];
+            }
+            wave_sync_lds();
+            stage_out(c);
+            wave_sync_lds();
+        }
     }
 }
 

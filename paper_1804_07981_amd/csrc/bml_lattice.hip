@@ -939,11 +939,12 @@ static const BlockTable &block_table()
 }
 
 // Row slabs of a lattice of `rows` rows for the tile kernel with `halo`
-// halo rows: the fewest whose 32-row blocks, with the halo, fit 512 rows.
+// halo rows: the fewest that, cut at even rows and held with the halo,
+// fit 512 rows.
 static int block_slabs(int rows, int halo)
 {
-    const int per = (BLK_ROWS - 2 * halo) / 32;   // 32-row blocks per slab
-    return (rows / 32 + per - 1) / per;
+    const int per = BLK_ROWS - 2 * halo;          // own rows a slab can hold
+    return (rows + per - 1) / per;
 }
 
 // Per-step counts of every tile summed per lattice, one block per

@@ -23,17 +23,19 @@ def test_algorithmic_bytes_per_cell_step():
 
 
 def test_alu_roofline_counts():
-    r = bench.alu_roofline(1, 8, 1000.0)             # bitplane: 13 lane-ops per word-step
-    assert r["lane_ops_per_cell_step"] == pytest.approx(13 / 32, rel=1e-3)
-    assert r["achieved"] == pytest.approx(1000e9 * 13 / 32 / 1e12, abs=0.01)
-    u8 = bench.alu_roofline(0, 8, 1000.0)            # + 80 conversion lane-ops per word and pass
-    assert u8["lane_ops_per_cell_step"] == pytest.approx((13 + 10) / 32, rel=1e-3)
+    r = bench.alu_roofline(1, 8, 1000.0)             # bitplane: 18 slots per word-step
+    assert r["lane_ops_per_cell_step"] == pytest.approx(18 / 32, rel=1e-3)
+    assert r["achieved"] == pytest.approx(1000e9 * 18 / 32 / 1e12, abs=0.01)
+    u8 = bench.alu_roofline(0, 8, 1000.0)            # + 128 conversion slots per word and pass
+    assert u8["lane_ops_per_cell_step"] == pytest.approx((18 + 16) / 32, rel=1e-3)
     assert bench.alu_roofline(1, 8, 1.0, model=2)["lane_ops_per_cell_step"] == \
-        pytest.approx(60 / 32, rel=1e-3)
+        pytest.approx(75 / 32, rel=1e-3)
     assert bench.alu_roofline(1, 8, 1.0, model=3)["lane_ops_per_cell_step"] == \
-        pytest.approx(13 / 32, rel=1e-3)
-    # 256 CUs x 4 SIMDs x 64 lanes, one instruction per 4 clocks, 2.4 GHz
-    assert bench.ALU_PEAK_LANE_OPS == pytest.approx(3.93216e13)
+        pytest.approx(18 / 32, rel=1e-3)
+    # 256 CUs x 128 lanes per clock x 2.4 GHz: the fp32 vector rate
+    # (157.3 TFLOP/s counting an FMA as two)
+    assert bench.ALU_PEAK_LANE_OPS == pytest.approx(7.86432e13)
+    assert 2 * bench.ALU_PEAK_LANE_OPS == pytest.approx(157.3e12, rel=1e-3)
 
 
 def _write_pmc(dirpath, counter, rows):

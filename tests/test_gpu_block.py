@@ -46,10 +46,12 @@ def check(lat, want, wst, steps):
 
 # rows x cols, halo steps, steps: one and several tiles and slabs, a lattice
 # shorter than its halo (its held block wraps around it several times), runs
-# ending inside a launch
+# ending inside a launch, slabs cut unevenly (1376 rows at K = 28: four
+# slabs of 344; 2336 rows at K = 30: six slabs of 388 or 390 rows)
 CASES = [(1024, 1024, 32, 70), (1024, 1024, 16, 37), (1024, 1024, 2, 9),
          (2048, 3072, 32, 65), (96, 1024, 32, 40), (32, 2048, 32, 33),
-         (1472, 1024, 24, 50), (512, 4096, 8, 20)]
+         (1472, 1024, 24, 50), (512, 4096, 8, 20), (1376, 2048, 28, 61),
+         (2336, 1024, 30, 31)]
 
 
 @pytest.mark.parametrize("layout", [0, 1])
