@@ -136,8 +136,14 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tiles = a.tiles_x * a.slabs;
-    const int li = blockIdx.x / tiles;
-    const int local = blockIdx.x - li * tiles;
+    // Workgroups go to the eight XCDs in turn (workgroup b to XCD b % 8);
+    // each XCD takes a contiguous run of tiles, so that the neighbours whose
+    // boundary lines a tile reads as halo (the tiles left and right, the
+    // slabs above and below) mostly run on the same XCD and share its L2.
+    const int nb = (int)gridDim.x, xcd = (int)blockIdx.x & 7;
+    const int t = xcd * (nb >> 3) + min(xcd, nb & 7) + ((int)blockIdx.x >> 3);
+    const int li = t / tiles;
+    const int local = t - li * tiles;
     const int slab = local / a.tiles_x;
     const int tx = local - slab * a.tiles_x;
     // Slabs cut at even rows, as equal as possible (at most
