@@ -75,17 +75,11 @@ constexpr int BLK_XW = 36;
 constexpr int BLK_G = 4;                      // words per scheduling group of the step
 
 struct BlockShared {
-    uint32_t x[2][BLK_WAVES][2][BLK_XW];     // as ResidentShared::x
+    uint32_t x[2][BLK_WAVES][2][BLK_XW];     // as ResidentShared::x (16-byte aligned: first member)
     uint32_t none[BLK_XW];                    // zero: no neighbour beyond the halo rows
     uint32_t cnt[BLK_MAX_K][BLK_WAVES][4];    // per-wave counts of each step
     uint32_t stage[BLK_WAVES][2][2 * 64 * BLK_SROW];   // [wave][plane][row half][lane, word]
 };
-
-// a ^ b ^ c as one three-input bit operation
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
 
 __device__ __forceinline__ int stage_index(int r, int j)
 {

@@ -98,7 +98,7 @@ __device__ __forceinline__ uint32_t from_above_or(uint32_t old, uint32_t v)
 // stands for the missing neighbour beyond a slab's outermost rows (no car
 // above, no empty cell below).
 struct ResidentShared {
-    uint32_t x[2][RES_WAVES][2][RES_MAX_WORDS];
+    alignas(16) uint32_t x[2][RES_WAVES][2][RES_MAX_WORDS];   // read 16 bytes at a time
     uint32_t none[RES_MAX_WORDS];
     // Moved counts [chunk parity][step in chunk][item][LR, TB], gathered
     // over RES_CHUNK steps and then added to the trace in one burst: a
@@ -106,6 +106,12 @@ struct ResidentShared {
     // completes, every step.
     uint32_t cnt[2][RES_CHUNK][RES_MAX_ITEMS][2];
 };
+
+// a ^ b ^ c as one three-input bit operation
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 
 template <int IO, int W>
 __device__ __forceinline__ void resident_body(const ResidentArgs &a, const ResidentBin &bin,
@@ -245,56 +251,78 @@ __device__ __forceinline__ void resident_body(const ResidentArgs &a, const Resid
         }
     };
 
-    // Horizontal phase of one row: an LR car moves when the next cell (bit
-    // j + 1, continued into the next word, word W-1 wrapping to word 0) is
-    // EMPTY; it lands one cell further.  Every mover is decided before any
-    // word changes.  Words are processed in groups of RES_GROUP with
-    // scheduling barriers between groups, so that only a group's
-    // temporaries are live next to the state.  Returns the movers' count;
-    // E receives the row's emptiness after the phase.
-    auto hphase = [&](uint32_t (&Lr)[W], const uint32_t (&Tr)[W], uint32_t (&E)[W]) {
-        uint32_t c = 0;
-        const uint32_t o0 = Lr[0] | Tr[0];
-        const uint32_t mv_last =
-            Lr[W - 1] & ~__builtin_amdgcn_alignbit(o0, Lr[W - 1] | Tr[W - 1], 1);
-        uint32_t mv_prev = mv_last, o = o0;
+    // Horizontal phase of both rows: an LR car moves when the next cell
+    // (bit j + 1, continued into the next word, word W-1 wrapping to word
+    // 0) is EMPTY; it lands one cell further.  Every mover is decided before
+    // any word changes.  Words go in groups of RES_GROUP, each stage of the
+    // rule applied to the group's words of both rows before the next stage,
+    // so that consecutive instructions rarely depend on each other, with
+    // scheduling barriers between groups so that only a group's temporaries
+    // are live next to the state.  Returns the movers' count.  The emptiness
+    // the vertical phase needs is recomputed there from the planes (no
+    // array of it stays live).
+    auto hphase = [&]() {
+        uint32_t c0 = 0, c1 = 0;
+        const uint32_t q0 = L0[0] | T0[0], q1 = L1[0] | T1[0];   // word 0 before the phase
+        const uint32_t last0 = L0[W - 1] & ~__builtin_amdgcn_alignbit(q0, L0[W - 1] | T0[W - 1], 1);
+        const uint32_t last1 = L1[W - 1] & ~__builtin_amdgcn_alignbit(q1, L1[W - 1] | T1[W - 1], 1);
+        uint32_t p0 = last0, p1 = last1, o0 = q0, o1 = q1;
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            uint32_t mv;
-            if (i + 1 < W) {
-                const uint32_t on = Lr[i + 1] | Tr[i + 1];
-                mv = Lr[i] & ~__builtin_amdgcn_alignbit(on, o, 1);
-                o = on;
-            } else {
-                mv = mv_last;
+        for (int g = 0; g < W; g += RES_GROUP) {
+            uint32_t m0[RES_GROUP], m1[RES_GROUP];
+#pragma unroll
+            for (int j = 0; j < RES_GROUP; ++j) {     // movers: the next cell is empty
+                const int i = g + j;
+                if (i + 1 < W) {
+                    const uint32_t on0 = L0[i + 1] | T0[i + 1], on1 = L1[i + 1] | T1[i + 1];
+                    m0[j] = L0[i] & ~__builtin_amdgcn_alignbit(on0, o0, 1);
+                    m1[j] = L1[i] & ~__builtin_amdgcn_alignbit(on1, o1, 1);
+                    o0 = on0;
+                    o1 = on1;
+                } else if (i + 1 == W) {
+                    m0[j] = last0;
+                    m1[j] = last1;
+                }
             }
-            const uint32_t arrive = __builtin_amdgcn_alignbit(mv, mv_prev, 31);
-            c += __builtin_popcount(mv);
-            Lr[i] = Lr[i] ^ mv ^ arrive;    // movers leave, arrivals land (disjoint)
-            E[i] = ~(Lr[i] | Tr[i]);
-            // Opaque new values (and count): updated in place here, not
-            // carried as pieces to the end of the step.
-            asm("" : "+v"(Lr[i]), "+v"(E[i]), "+v"(c));
-            mv_prev = mv;
-            if ((i + 1) % RES_GROUP == 0)
-                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < RES_GROUP; ++j) {     // movers leave, arrivals land (disjoint)
+                const int i = g + j;
+                if (i < W) {
+                    L0[i] = xor3(L0[i], m0[j], __builtin_amdgcn_alignbit(m0[j], j ? m0[j - 1] : p0, 31));
+                    L1[i] = xor3(L1[i], m1[j], __builtin_amdgcn_alignbit(m1[j], j ? m1[j - 1] : p1, 31));
+                    c0 = __builtin_popcount(m0[j]) + c0;
+                    c1 = __builtin_popcount(m1[j]) + c1;
+                    asm("" : "+v"(c0), "+v"(c1));
+                }
+            }
+            const int last = (W - g < RES_GROUP ? W - g : RES_GROUP) - 1;
+            p0 = m0[last];
+            p1 = m1[last];
+            // Opaque new values: updated in place here, not carried as
+            // pieces to the end of the step.
+#pragma unroll
+            for (int j = 0; j < RES_GROUP; ++j) {
+                const int i = g + j;
+                if (i < W)
+                    asm("" : "+v"(L0[i]), "+v"(L1[i]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        return c;
+        return c0 + c1;
     };
 
     for (int s = 0; s < n_steps; ++s) {
         const int p = s & 1;
-        uint32_t E0[W], E1[W];    // emptiness of the two rows after the horizontal phase
-        uint32_t c_lr = 0, c_tb = 0;
+        uint32_t c_lr = 0, c_tb = 0, c_tb1 = 0;
         if (wave_on) {
-            c_lr = hphase(L0, T0, E0) + hphase(L1, T1, E1);
+            c_lr = hphase();
             // Exchange: the wave's first row's emptiness goes to the wave
             // above, its last row's TB plane (unchanged by this phase) to
             // the wave below.
             if (lane == 0) {
 #pragma unroll
                 for (int i = 0; i < W; ++i)
-                    sh.x[p][wave][0][i] = E0[i];
+                    sh.x[p][wave][0][i] = ~(L0[i] | T0[i]);
             }
             if (lane == last_lane) {
 #pragma unroll
@@ -311,28 +339,63 @@ __device__ __forceinline__ void resident_body(const ResidentArgs &a, const Resid
             // upper row's cars move into the lower row of the same lane;
             // the lower row's into the next lane's upper row, or, for the
             // item's last lane (63, or 15, 31 or 47 in a short last wave),
-            // into the wave below.
+            // into the wave below.  The neighbour waves' rows are read four
+            // words at a time, one group ahead of their use, so that LDS
+            // latency hides behind the previous group.
+            u32x4 nb = *reinterpret_cast<const u32x4 *>(xb);
+            u32x4 na = *reinterpret_cast<const u32x4 *>(xa);
 #pragma unroll
-            for (int i = 0; i < W; ++i) {
-                const uint32_t e_x = xb[i];   // first row of the wave below
-                const uint32_t t_x = xa[i];   // last row of the wave above
-                uint32_t e_below = from_below_or(e_x, E0[i]);
-                // The lane shift must run with every lane on: the compiler
-                // would otherwise turn the select into a branch around a
-                // shift with the last lane switched off, and a lane whose
-                // source lane is off keeps its old value.
-                asm volatile("" : "+v"(e_below));
-                e_below = lane == last_lane ? e_x : e_below;
-                const uint32_t mv0 = T0[i] & E1[i];
-                const uint32_t mv1 = T1[i] & e_below;
-                const uint32_t arrive = from_above_or(t_x & E0[i], mv1);
-                c_tb += __builtin_popcount(mv0) + __builtin_popcount(mv1);
-                T0[i] = T0[i] ^ mv0 ^ arrive;
-                T1[i] = T1[i] ^ mv1 ^ mv0;
-                asm("" : "+v"(T0[i]), "+v"(T1[i]), "+v"(c_tb));
-                if ((i + 1) % RES_GROUP == 0)
-                    __builtin_amdgcn_sched_barrier(0);
+            for (int g = 0; g < W; g += 4) {
+                const u32x4 cb = nb, ca = na;   // first row of the wave below, last row above
+                if (g + 4 < W) {
+                    nb = *reinterpret_cast<const u32x4 *>(xb + g + 4);
+                    na = *reinterpret_cast<const u32x4 *>(xa + g + 4);
+                }
+                uint32_t e0[4], eb[4], mv0[4], mv1[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W) {
+                        e0[j] = ~(L0[i] | T0[i]);
+                        eb[j] = from_below_or(cb[j], e0[j]);
+                        // The lane shift must run with every lane on: the
+                        // compiler would otherwise turn the select into a
+                        // branch around a shift with the last lane switched
+                        // off, and a lane whose source lane is off keeps its
+                        // old value.
+                        asm volatile("" : "+v"(eb[j]));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W) {
+                        eb[j] = lane == last_lane ? cb[j] : eb[j];
+                        mv0[j] = T0[i] & ~(L1[i] | T1[i]);
+                        mv1[j] = T1[i] & eb[j];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W) {
+                        const uint32_t arrive = from_above_or(ca[j] & e0[j], mv1[j]);
+                        T0[i] = xor3(T0[i], mv0[j], arrive);
+                        T1[i] = xor3(T1[i], mv1[j], mv0[j]);
+                        c_tb = __builtin_popcount(mv0[j]) + c_tb;
+                        c_tb1 = __builtin_popcount(mv1[j]) + c_tb1;
+                        asm("" : "+v"(c_tb), "+v"(c_tb1));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = g + j;
+                    if (i < W)
+                        asm("" : "+v"(T0[i]), "+v"(T1[i]));
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
+            c_tb += c_tb1;
             const uint32_t tot = wave_total(counted ? (c_lr | (c_tb << 16)) : 0u);
             if (lane == 0) {
                 const int kb = (s / RES_CHUNK) & 1, c = s % RES_CHUNK;
@@ -373,7 +436,7 @@ __device__ __forceinline__ void resident_dispatch(const ResidentArgs &a, const R
 
 // One block per bin; blockDim.x == 64 * RES_WAVES.
 template <int IO>
-__global__ __launch_bounds__(64 * RES_WAVES, 2) void resident_kernel(ResidentArgs a)
+__global__ __launch_bounds__(64 * RES_WAVES, 3) void resident_kernel(ResidentArgs a)
 {
     __shared__ ResidentShared sh;
     const ResidentBin &bin = a.bins[blockIdx.x];
