@@ -26,7 +26,7 @@ PASS_VARIANTS = [
     for kind, (topo, model) in PASS_KINDS.items() for io in ("u8", "bp")
     for rng, (row, klo, kn) in PASS_RANGES.items()]
 SOURCES = ["bml_lattice.hip", "bml_batch.hip", "bml_batch_u8.hip", "bml_batch_bp.hip",
-           "bml_resident.hip", "bml_block.hip", "bml_mlp.hip"]
+           "bml_resident_u8.hip", "bml_resident_bp.hip", "bml_block.hip", "bml_mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",

@@ -34,7 +34,11 @@ static const BatchTable &batch_kernels()
 
 struct ResidentTable {
     ResidentFn fn[2] = {};
-    ResidentTable() { resident_kernels(&fn[IO_U8], &fn[IO_BP]); }
+    ResidentTable()
+    {
+        fn[IO_U8] = resident_kernel_u8();
+        fn[IO_BP] = resident_kernel_bp();
+    }
 };
 
 static const ResidentTable &resident_table()

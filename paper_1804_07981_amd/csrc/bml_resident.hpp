@@ -468,6 +468,7 @@ struct SlabLattice {
 };
 
 using ResidentFn = void (*)(ResidentArgs);
-void resident_kernels(ResidentFn *u8, ResidentFn *bp);
+ResidentFn resident_kernel_u8();
+ResidentFn resident_kernel_bp();
 
 } // namespace bml
