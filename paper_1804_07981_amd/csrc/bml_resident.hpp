@@ -17,8 +17,9 @@
 // the horizontal phase decides every move from the words before any of
 // them changes, and the vertical phase from the post-horizontal occupancy.
 // Two rows per lane halve the wave shifts per row and the per-wave work
-// that does not depend on W, and leave each lane up to 256 VGPRs (8
-// wavefronts per workgroup, one workgroup per CU).
+// that does not depend on W.  A workgroup is 4 wavefronts (one per SIMD);
+// at most 168 VGPRs per lane let three workgroups share a CU, so each SIMD
+// interleaves three waves.
 //
 // Work items.  An item is either a whole lattice (halo 0: its last row's
 // lower neighbour is its first row, the periodic edge of Sec. 2) or a slab
@@ -30,7 +31,7 @@
 // Slabs let one lattice spread over several workgroups (CUs) for the K <= H
 // steps of a launch, at the price of recomputing the halo rows.
 //
-// A workgroup (8 wavefronts) runs a bin of items of one row width W:
+// A workgroup (4 wavefronts) runs a bin of items of one row width W:
 // ceil(rows held / 128) wavefronts each.  Per step and item the moved counts
 // of the two phases are summed (wave total, then LDS) and added to the
 // lattice's trace entry.  The state is read once at the start of a launch
@@ -46,7 +47,7 @@
 namespace bml {
 
 constexpr int RES_MAX_WORDS = 32;   // N <= 1024
-constexpr int RES_WAVES = 4;        // waves per block (one per SIMD; two blocks per CU)
+constexpr int RES_WAVES = 4;        // waves per block (one per SIMD; three blocks per CU)
 constexpr int RES_WAVE_ROWS = 128;  // rows per wave: two per lane
 constexpr int RES_MAX_ITEMS = RES_WAVES;   // items per block (each starts a wave)
 constexpr int RES_GROUP = 4;        // words per scheduling group of the step loop
