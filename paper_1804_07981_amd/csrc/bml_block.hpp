@@ -77,7 +77,11 @@ constexpr int BLK_G = 4;                      // words per scheduling group of t
 struct BlockShared {
     uint32_t x[2][BLK_WAVES][2][BLK_XW];     // as ResidentShared::x (16-byte aligned: first member)
     uint32_t none[BLK_XW];                    // zero: no neighbour beyond the halo rows
-    uint32_t cnt[BLK_MAX_K][BLK_WAVES][4];    // per-wave counts of each step
+    // Per wave and step: LR cars that entered the tile's own cells minus
+    // those that left them, LR movers, the same difference for TB cars, TB
+    // movers.
+    uint32_t cnt[BLK_MAX_K][BLK_WAVES][4];
+    uint32_t cars[2][BLK_WAVES][2];           // [after load, after the steps][wave][LR, TB]
     uint32_t stage[BLK_WAVES][2][2 * 64 * BLK_SROW];   // [wave][plane][row half][lane, word]
 };
 
@@ -313,6 +317,32 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
         load_halo(g0, L0, T0);
         load_halo(g1, L1, T1);
     }
+    // Cars on the tile's own cells, per wave: counted directly after the
+    // load and after the last step; the per-step counts in between follow
+    // from what crosses the tile's edges, and must end at the second count.
+    auto count_cars = [&](int when) {
+        uint32_t nl = 0, nt = 0;
+#pragma unroll
+        for (int i = 1; i < W - 1; ++i) {
+            nl = __builtin_popcount(L0[i]) + nl;
+            nl = __builtin_popcount(L1[i]) + nl;
+            nt = __builtin_popcount(T0[i]) + nt;
+            nt = __builtin_popcount(T1[i]) + nt;
+        }
+        const uint32_t cl = wave_total(counted ? nl : 0u);
+        const uint32_t ct = wave_total(counted ? nt : 0u);
+        if (lane == 0) {
+            sh.cars[when][wave][0] = cl;
+            sh.cars[when][wave][1] = ct;
+        }
+    };
+    count_cars(0);
+    // The lanes whose lower row is the last held row above the tile's own
+    // rows (its TB movers enter them) and the tile's last own row (its TB
+    // movers leave them).
+    const int in_row = H - 2, out_row = H + R - 2;
+    const int w_in = in_row >> 7, l_in = (in_row & 127) >> 1;
+    const int w_out = out_row >> 7, l_out = (out_row & 127) >> 1;
     if (threadIdx.x < BLK_XW)
         sh.none[threadIdx.x] = 0;
 
@@ -324,10 +354,10 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     // instructions to issue back to back.  Returns the LR movers of the
     // tile's own words.  The emptiness the vertical phase needs is
     // recomputed there from the planes (no array of it stays live).
-    auto hphase = [&](uint32_t &n_lr) {
+    auto hphase = [&](uint32_t &flux) {
         // one accumulator per popcount stream: each popcount adds into its
         // own (v_bcnt_u32_b32 with an addend), no separate adds
-        uint32_t c0 = 0, c1 = 0, n0 = 0, n1 = 0;
+        uint32_t c0 = 0, c1 = 0;
         uint32_t p0 = 0, p1 = 0, o0 = L0[0] | T0[0], o1 = L1[0] | T1[0];
 #pragma unroll
         for (int g = 0; g < W; g += BLK_G) {
@@ -364,10 +394,14 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                 if (i >= 1 && i < W - 1) {
                     c0 = __builtin_popcount(m0[j]) + c0;
                     c1 = __builtin_popcount(m1[j]) + c1;
-                    n0 = __builtin_popcount(L0[i]) + n0;
-                    n1 = __builtin_popcount(L1[i]) + n1;
-                    asm("" : "+v"(c0), "+v"(c1), "+v"(n0), "+v"(n1));
+                    asm("" : "+v"(c0), "+v"(c1));
                 }
+                // cars entering the own words from the left halo word, and
+                // leaving the last own word for the right one
+                if (i == 0)
+                    flux = (m0[j] >> 31) + (m1[j] >> 31);
+                if (i == W - 2)
+                    flux -= (m0[j] >> 31) + (m1[j] >> 31);
             }
             const int last = (W - g < BLK_G ? W - g : BLK_G) - 1;
             o0 = on0[last];
@@ -382,18 +416,17 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                 if (i < W)
                     asm("" : "+v"(L0[i]), "+v"(L1[i]));
             }
-            asm("" : "+v"(c0), "+v"(c1), "+v"(n0), "+v"(n1));
+            asm("" : "+v"(c0), "+v"(c1), "+v"(flux));
             __builtin_amdgcn_sched_barrier(0);
         }
-        n_lr = n0 + n1;
         return c0 + c1;
     };
 
     for (int s = 0; s < n_steps; ++s) {
         const int p = s & 1;
-        uint32_t n_lr = 0, c_lr = 0, n_tb = 0, c_tb = 0, n_tb1 = 0, c_tb1 = 0;
+        uint32_t f_lr = 0, c_lr = 0, c_tb = 0, c_tb1 = 0;
         if (wave_on) {
-            c_lr = hphase(n_lr);
+            c_lr = hphase(f_lr);
             if (lane == 0) {
 #pragma unroll
                 for (int i = 0; i < BLK_XW; i += 4)
@@ -473,9 +506,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                     if (i >= 1 && i < W - 1) {
                         c_tb = __builtin_popcount(mv0[j]) + c_tb;
                         c_tb1 = __builtin_popcount(mv1[j]) + c_tb1;
-                        n_tb = __builtin_popcount(T0[i]) + n_tb;
-                        n_tb1 = __builtin_popcount(T1[i]) + n_tb1;
-                        asm("" : "+v"(c_tb), "+v"(c_tb1), "+v"(n_tb), "+v"(n_tb1));
+                        asm("" : "+v"(c_tb), "+v"(c_tb1));
                     }
                 }
 #pragma unroll
@@ -484,14 +515,19 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                     if (i < W)
                         asm("" : "+v"(T0[i]), "+v"(T1[i]));
                 }
-                asm("" : "+v"(c_tb), "+v"(c_tb1), "+v"(n_tb), "+v"(n_tb1));
+                asm("" : "+v"(c_tb), "+v"(c_tb1));
                 __builtin_amdgcn_sched_barrier(0);
             }
+            // TB cars entering the own rows from the row above them, minus
+            // those leaving the last own row (lower-row movers of two lanes)
+            uint32_t t2 = 0;
+            if (wave == w_in)
+                t2 += (uint32_t)__builtin_amdgcn_readlane((int)c_tb1, l_in);
+            if (wave == w_out)
+                t2 -= (uint32_t)__builtin_amdgcn_readlane((int)c_tb1, l_out);
             c_tb += c_tb1;
-            n_tb += n_tb1;
-            const uint32_t t0 = wave_total(counted ? n_lr : 0u);
+            const uint32_t t0 = wave_total(counted ? f_lr : 0u);
             const uint32_t t1 = wave_total(counted ? c_lr : 0u);
-            const uint32_t t2 = wave_total(counted ? n_tb : 0u);
             const uint32_t t3 = wave_total(counted ? c_tb : 0u);
             if (lane == 0) {
                 sh.cnt[s][wave][0] = t0;
@@ -504,16 +540,38 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                 sh.cnt[s][wave][3] = 0;
         }
     }
+    count_cars(1);
     __syncthreads();
-    // The tile's counts of every step of the launch.
+    // The tile's counts of every step of the launch: movers as summed; cars
+    // as the count after the load plus what crossed the edges up to each
+    // step.  If that does not end at the count after the last step, the
+    // tile's car counts are written as all ones, so that the lattice's sums
+    // fail the conservation check.
     uint32_t *part = a.lat[li].partial + (size_t)local * BLK_MAX_K * 4;
-    for (int j = threadIdx.x; j < n_steps * 4; j += blockDim.x) {
-        const int st = j >> 2, q = j & 3;
-        uint32_t v = 0;
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        uint32_t v = 0, end = 0;
+        if (!(q & 1)) {
 #pragma unroll
-        for (int w = 0; w < BLK_WAVES; ++w)
-            v += sh.cnt[st][w][q];
-        part[j] = v;
+            for (int w = 0; w < BLK_WAVES; ++w) {
+                v += sh.cars[0][w][q >> 1];
+                end += sh.cars[1][w][q >> 1];
+            }
+        }
+        uint32_t total = v;
+        for (int st = 0; st < n_steps; ++st)
+#pragma unroll
+            for (int w = 0; w < BLK_WAVES; ++w)
+                total += sh.cnt[st][w][q];
+        const bool bad = !(q & 1) && total != end;
+        for (int st = 0; st < n_steps; ++st) {
+            uint32_t d = 0;
+#pragma unroll
+            for (int w = 0; w < BLK_WAVES; ++w)
+                d += sh.cnt[st][w][q];
+            v = (q & 1) ? d : v + d;
+            part[st * 4 + q] = bad ? 0xffffffffu : v;
+        }
     }
     if (wave_on) {
 #pragma unroll
