@@ -182,27 +182,25 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     uint32_t *stT = sh.stage[wave][1];
     uint32_t L0[W], T0[W], L1[W], T1[W];
 
-    // The halo words (held words 0 and W - 1: lattice words w0 - 1 and
-    // w0 + 32, periodic), each lane its own two rows.
-    auto load_halo = [&](int g, uint32_t (&Lr)[W], uint32_t (&Tr)[W]) {
+    // Halo word h of a row (h = 0: held word 0, lattice word w0 - 1; h = 1:
+    // held word W - 1, lattice word w0 + 32; periodic), each lane its own
+    // rows.
+    auto load_halo = [&](int h, int g, uint32_t (&Lr)[W], uint32_t (&Tr)[W]) {
         const uint32_t ro = (uint32_t)g * row_bytes;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = h ? W - 1 : 0;
-            const int w = h ? (w0 + BLK_WORDS == words ? 0 : w0 + BLK_WORDS)
-                            : (w0 == 0 ? words - 1 : w0 - 1);
-            if constexpr (IO == IO_U8) {
-                const u32x4 u0 = __builtin_amdgcn_raw_buffer_load_b128(
-                    src, ro + (uint32_t)w * 32u, 0, 0);
-                const u32x4 u1 = __builtin_amdgcn_raw_buffer_load_b128(
-                    src, ro + (uint32_t)w * 32u + 16u, 0, 0);
-                const uint32_t dw[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-                bytes_to_planes(dw, Lr[i], Tr[i]);
-            } else {
-                Lr[i] = __builtin_amdgcn_raw_buffer_load_b32(src, ro + (uint32_t)w * 4u, 0, 0);
-                Tr[i] = __builtin_amdgcn_raw_buffer_load_b32(
-                    src, ro + plane_bytes + (uint32_t)w * 4u, 0, 0);
-            }
+        const int i = h ? W - 1 : 0;
+        const int w = h ? (w0 + BLK_WORDS == words ? 0 : w0 + BLK_WORDS)
+                        : (w0 == 0 ? words - 1 : w0 - 1);
+        if constexpr (IO == IO_U8) {
+            const u32x4 u0 = __builtin_amdgcn_raw_buffer_load_b128(src, ro + (uint32_t)w * 32u,
+                                                                   0, 0);
+            const u32x4 u1 = __builtin_amdgcn_raw_buffer_load_b128(
+                src, ro + (uint32_t)w * 32u + 16u, 0, 0);
+            const uint32_t dw[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+            bytes_to_planes(dw, Lr[i], Tr[i]);
+        } else {
+            Lr[i] = __builtin_amdgcn_raw_buffer_load_b32(src, ro + (uint32_t)w * 4u, 0, 0);
+            Tr[i] = __builtin_amdgcn_raw_buffer_load_b32(src, ro + plane_bytes + (uint32_t)w * 4u,
+                                                         0, 0);
         }
     };
 
@@ -297,6 +295,13 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
 #pragma unroll
     for (int i = 0; i < W; ++i)
         L0[i] = T0[i] = L1[i] = T1[i] = 0;
+    // The right halo word is the first word the tile to the right loads,
+    // the left one the last word the tile to the left loads: loaded at the
+    // same times, their lines are mostly still in the XCD's L2.
+    if (row_ok) {
+        load_halo(1, g0, L0, T0);
+        load_halo(1, g1, L1, T1);
+    }
     if (wave_on) {
 #pragma unroll
         for (int c = 0; c < BLK_WORDS / BLK_CHUNK; ++c) {
@@ -314,8 +319,8 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
         }
     }
     if (row_ok) {
-        load_halo(g0, L0, T0);
-        load_halo(g1, L1, T1);
+        load_halo(0, g0, L0, T0);
+        load_halo(0, g1, L1, T1);
     }
     // Cars on the tile's own cells, per wave: counted directly after the
     // load and after the last step; the per-step counts in between follow
