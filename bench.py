@@ -145,8 +145,9 @@ def load_tuning(layout: int, n, group: str | None = None, model: int = 1):
 def load_resident_steps(layout: int, n, group: str | None = None, model: int = 1) -> int:
     """Autotuned steps per launch of the register-resident tile kernel for
     the lattice (or group) the tuning cache entry names (0: the streaming
-    kernel is faster, or no entry; Models II and III: always 0)."""
-    if model != 1:
+    kernel is faster, or no entry).  Model III reads only its own (/model3)
+    entries; Model II, which the tile kernel does not run: always 0."""
+    if model == 2:
         return 0
     path = os.path.join(ROOT, "paper_1804_07981_amd", "tune_cache.json")
     try:
@@ -155,7 +156,8 @@ def load_resident_steps(layout: int, n, group: str | None = None, model: int = 1
     except (OSError, ValueError):
         return 0
     lay = "u8" if layout == 0 else "bp"
-    for key in ([f"gfx950/{lay}/{group}"] if group else []) + [f"gfx950/{lay}/{n}"]:
+    suffix = "/model3" if model == 3 else ""
+    for key in ([f"gfx950/{lay}/{group}{suffix}"] if group else []) + [f"gfx950/{lay}/{n}{suffix}"]:
         if key in cache:
             return int(cache[key].get("resident_steps", 0))
     return 0

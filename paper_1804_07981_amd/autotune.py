@@ -336,8 +336,9 @@ def main(argv=None) -> int:
     torch.cuda.set_device(0)
     cache = load(args.cache)
     kw = dict(strip_rows=(0, 64, 256), t_phases=(4, 8, 16), waves=(4,)) if args.quick else {}
-    # the register-resident tile kernel: the model of Sec. 2, 1024-column tiles
-    res = (16, 24, 28, 32) if m == 1 else ()
+    # the register-resident tile kernel: the model of Sec. 2 and Model III,
+    # 1024-column tiles
+    res = (16, 24, 28, 32) if m in (1, 3) else ()
     tiles = lambda rows, cols: res if rows % 32 == 0 and cols % 1024 == 0 else ()  # noqa: E731
     for n in args.sizes:
         for lay in args.layouts:

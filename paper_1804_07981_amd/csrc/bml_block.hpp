@@ -126,7 +126,12 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int IO>
+// MODEL 1: the two-phase rule of Sec. 2 (horizontal phase, then the
+// vertical phase on the state it leaves).  MODEL 3: Model III, one phase in
+// which every car looks at the state before the step (a car moves when its
+// target cell held no car; an empty cell wanted by an LR and a TB car takes
+// both).
+template <int IO, int MODEL>
 __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
 {
     constexpr int W = BLK_W;
@@ -431,7 +436,11 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
         const int p = s & 1;
         uint32_t f_lr = 0, c_lr = 0, c_tb = 0, c_tb1 = 0;
         if (wave_on) {
-            c_lr = hphase(f_lr);
+            // Model III reads every neighbour before the step: the rows
+            // exchanged below are then the state before the step, and its
+            // LR moves are made in the vertical loop.
+            if constexpr (MODEL == 1)
+                c_lr = hphase(f_lr);
             if (lane == 0) {
 #pragma unroll
                 for (int i = 0; i < BLK_XW; i += 4)
@@ -454,18 +463,42 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
             const uint32_t *xa = wup >= 0 ? sh.x[p][wup][1] : sh.none;
             // The neighbour rows four words at a time, one group ahead of
             // their use, so that LDS latency hides behind the previous group.
-            u32x4 nb = *reinterpret_cast<const u32x4 *>(xb);
-            u32x4 na = *reinterpret_cast<const u32x4 *>(xa);
+            // Words per group: Model III keeps more values live per word
+            // (its LR movers too), so its groups are half as wide.
+            constexpr int VG = MODEL == 3 ? 2 : 4;
+            typedef uint32_t xvec __attribute__((ext_vector_type(VG)));
+            xvec nb = *reinterpret_cast<const xvec *>(xb);
+            xvec na = *reinterpret_cast<const xvec *>(xa);
+            // Model III: occupancy of the current word and LR movers of the
+            // previous one, carried from group to group
+            uint32_t o0 = L0[0] | T0[0], o1 = L1[0] | T1[0], q0 = 0, q1 = 0, c_l1 = 0;
 #pragma unroll
-            for (int g = 0; g < BLK_XW; g += 4) {
-                const u32x4 cb = nb, ca = na;
-                if (g + 4 < BLK_XW) {
-                    nb = *reinterpret_cast<const u32x4 *>(xb + g + 4);
-                    na = *reinterpret_cast<const u32x4 *>(xa + g + 4);
+            for (int g = 0; g < BLK_XW; g += VG) {
+                const xvec cb = nb, ca = na;
+                if (g + VG < BLK_XW) {
+                    nb = *reinterpret_cast<const xvec *>(xb + g + VG);
+                    na = *reinterpret_cast<const xvec *>(xa + g + VG);
                 }
-                uint32_t e0[4], e1[4], eb[4], mv0[4], mv1[4], ar[4];
+                uint32_t e0[VG], e1[VG], eb[VG], mv0[VG], mv1[VG], ar[VG], m0[VG], m1[VG];
+                if constexpr (MODEL == 3) {
+                    // LR movers from the state before the step: the next
+                    // cell held no car (open right end: the cell beyond the
+                    // last held word counts as occupied)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < VG; ++j) {
+                        const int i = g + j;
+                        if (i < W) {
+                            const uint32_t on0 = i + 1 < W ? (L0[i + 1] | T0[i + 1]) : 0xffffffffu;
+                            const uint32_t on1 = i + 1 < W ? (L1[i + 1] | T1[i + 1]) : 0xffffffffu;
+                            m0[j] = L0[i] & ~__builtin_amdgcn_alignbit(on0, o0, 1);
+                            m1[j] = L1[i] & ~__builtin_amdgcn_alignbit(on1, o1, 1);
+                            o0 = on0;
+                            o1 = on1;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i < W) {
                         e0[j] = ~(L0[i] | T0[i]);
@@ -473,7 +506,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i < W) {
                         eb[j] = from_below_or(cb[j], e0[j]);
@@ -483,7 +516,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i < W) {
                         eb[j] = lane == last_lane ? cb[j] : eb[j];
@@ -492,21 +525,46 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i < W)
                         ar[j] = from_above_or(ca[j] & e0[j], mv1[j]);
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i < W) {
                         T0[i] = xor3(T0[i], mv0[j], ar[j]);
                         T1[i] = xor3(T1[i], mv1[j], mv0[j]);
                     }
                 }
+                if constexpr (MODEL == 3) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < VG; ++j) {
+                        const int i = g + j;
+                        if (i < W) {
+                            L0[i] = xor3(L0[i], m0[j],
+                                         __builtin_amdgcn_alignbit(m0[j], j ? m0[j - 1] : q0, 31));
+                            L1[i] = xor3(L1[i], m1[j],
+                                         __builtin_amdgcn_alignbit(m1[j], j ? m1[j - 1] : q1, 31));
+                            if (i >= 1 && i < W - 1) {
+                                c_lr = __builtin_popcount(m0[j]) + c_lr;
+                                c_l1 = __builtin_popcount(m1[j]) + c_l1;
+                                asm("" : "+v"(c_lr), "+v"(c_l1));
+                            }
+                            if (i == 0)
+                                f_lr = (m0[j] >> 31) + (m1[j] >> 31);
+                            if (i == W - 2)
+                                f_lr -= (m0[j] >> 31) + (m1[j] >> 31);
+                            asm("" : "+v"(L0[i]), "+v"(L1[i]));
+                        }
+                    }
+                    const int last = (W - g < VG ? W - g : VG) - 1;
+                    q0 = m0[last];
+                    q1 = m1[last];
+                }
+#pragma unroll
+                for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i >= 1 && i < W - 1) {
                         c_tb = __builtin_popcount(mv0[j]) + c_tb;
@@ -515,7 +573,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i < W)
                         asm("" : "+v"(T0[i]), "+v"(T1[i]));
@@ -523,6 +581,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                 asm("" : "+v"(c_tb), "+v"(c_tb1));
                 __builtin_amdgcn_sched_barrier(0);
             }
+            c_lr += c_l1;
             // TB cars entering the own rows from the row above them, minus
             // those leaving the last own row (lower-row movers of two lanes)
             uint32_t t2 = 0;
@@ -597,6 +656,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
 }
 
 using BlockFn = void (*)(BlockArgs);
-void block_kernels(BlockFn *u8, BlockFn *bp);
+// [layout][0: the two-phase rule, 1: Model III]
+void block_kernels(BlockFn (*fn)[2]);
 
 } // namespace bml

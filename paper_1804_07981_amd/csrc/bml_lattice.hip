@@ -712,9 +712,9 @@ int bml_set_model(bml_lattice *L, int32_t model, uint64_t coin_seed)
     if (model != 3 && L->both_cells)
         return fail(BML_EINVAL, "the lattice may hold cells with both an LR and a TB car, "
                                 "which only Model III defines");
-    if (model != 1 && L->block_steps)
+    if (model == 2 && L->block_steps)
         return fail(BML_EINVAL, "the register-resident tile kernel runs the model of "
-                                "Sec. 2 only");
+                                "Sec. 2 and Model III only");
     L->model = model;
     L->coin_seed = coin_seed;
     return BML_OK;
@@ -764,9 +764,9 @@ int bml_set_resident(bml_lattice *L, int32_t steps)
     if (steps < 0 || steps > BLK_MAX_K || steps % 2)
         return fail(BML_EINVAL, "steps=%d must be 0 or even in [2, %d]", steps, BLK_MAX_K);
     if (steps) {
-        if (L->model != 1 || L->topology != BML_TOPO_TORUS)
+        if (L->model == 2 || L->topology != BML_TOPO_TORUS)
             return fail(BML_EINVAL, "the register-resident tile kernel runs the model of "
-                                    "Sec. 2 on the torus only");
+                                    "Sec. 2 and Model III on the torus only");
         if (L->rows % 32 || L->cols % (32 * BLK_WORDS))
             return fail(BML_EINVAL, "%d x %d: the register-resident tile kernel needs rows "
                                     "a multiple of 32 and columns a multiple of %d",
@@ -928,8 +928,8 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
 // ---- register-resident tile kernel ---------------------------------------
 
 struct BlockTable {
-    BlockFn fn[2] = {};
-    BlockTable() { block_kernels(&fn[IO_U8], &fn[IO_BP]); }
+    BlockFn fn[2][2] = {};   // [layout][0: the two-phase rule, 1: Model III]
+    BlockTable() { block_kernels(fn); }
 };
 
 static const BlockTable &block_table()
@@ -1009,7 +1009,7 @@ static int run_block(bml_lattice *const *G, int count, int k, const int64_t *ste
         b.rec_from[i] = rec_from[i];
         b.cap[i] = G[i]->cap;
     }
-    hipLaunchKernelGGL(block_table().fn[io], dim3((unsigned)(tiles * count)),
+    hipLaunchKernelGGL(block_table().fn[io][L->model == 3 ? 1 : 0], dim3((unsigned)(tiles * count)),
                        dim3(64 * BLK_WAVES), 0, L->stream, a);
     BML_HIP(hipGetLastError());
     hipLaunchKernelGGL(block_sum_kernel, dim3((unsigned)(count * k * 4)), dim3(256), 0,

@@ -2,7 +2,8 @@
 against the CPU oracle: cells and all four counts of every step, for tile
 and slab counts of one and several, halos from 2 to 32 steps, runs that
 are not a whole number of launches, lattices shorter than their halo,
-joint launches of several lattices, and the arguments it refuses."""
+joint launches of several lattices, Model III, and the arguments it
+refuses."""
 import sys
 
 import numpy as np
@@ -71,6 +72,30 @@ def test_block_matches_oracle(B, layout, rows, cols, k, steps):
         check(lat, want, wst, steps)
 
 
+M3_CASES = [(1024, 1024, 32, 70), (2048, 2048, 28, 57), (96, 1024, 16, 33),
+            (1376, 2048, 28, 61)]
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("rows,cols,k,steps", M3_CASES,
+                         ids=[f"{r}x{c}_k{k}_s{s}" for r, c, k, s in M3_CASES])
+def test_block_model3_matches_oracle(B, layout, rows, cols, k, steps):
+    """Model III (one phase; a contested cell takes both cars) in the tile
+    kernel: cells (values 0..3) and every count of every step."""
+    rho_lr, rho_tb = 0.21, 0.24
+    seed = rows + 3 * cols + k
+    say(f"block model3 {rows}x{cols} k={k} steps={steps} layout={layout}")
+    g0 = oracle.init_cells_asym(rows, cols, seed, rho_lr, rho_tb)
+    want, wst = oracle.run_model3(g0, steps, n_threads=HOST_THREADS)
+    assert (want == 3).any()                # some cells hold both cars
+    with B.Lattice(rows, seed=seed, layout=layout, cols=cols, rho_lr=rho_lr, rho_tb=rho_tb,
+                   stats_cap=steps) as lat:
+        lat.set_model(3)
+        lat.set_resident(k)
+        lat.step(steps)
+        check(lat, want, wst, steps)
+
+
 def test_block_continues_streaming_runs(B):
     """Runs alternate between the tile kernel (two halos) and the streaming
     kernel on one lattice: the counts ring and the cells follow the oracle."""
@@ -116,8 +141,17 @@ def test_block_refusals(B):
             assert e.value.code == B.BML_EINVAL
         lat.set_resident(32)
         with pytest.raises(B.BmlError) as e:
-            lat.set_model(2, 5)
+            lat.set_model(2, 5)                  # Model II: the streaming kernel only
         assert e.value.code == B.BML_EINVAL
+        lat.set_model(3)
+        lat.set_model(1)
+        lat.set_resident(0)
+        lat.set_model(2, 5)
+        with pytest.raises(B.BmlError) as e:
+            lat.set_resident(16)
+        assert e.value.code == B.BML_EINVAL
+        lat.set_model(1)
+        lat.set_resident(32)
         with pytest.raises(B.BmlError) as e:
             lat.set_topology(B.BML_TOPO_KLEIN)
         assert e.value.code == B.BML_EINVAL

@@ -216,6 +216,9 @@ def test_model3_large_sampled_windows(B, layout):
         tun = bench.load_tuning(layout, n, None, 3)
         if tun:
             lat.set_tuning(*tun)
+        res = bench.load_resident_steps(layout, n, None, 3)
+        if res:
+            lat.set_resident(res)
         lat.step(steps)
         got = lat.cells()
         st = stats_array(lat.stats(0, steps))
