@@ -185,6 +185,17 @@ static int64_t item_work(const ResidentItem &it, int W)
 
 static int rows_waves(int rows) { return (rows + RES_WAVE_ROWS - 1) / RES_WAVE_ROWS; }
 
+// Compute units of the current device (256 when the query fails).
+static int device_cus()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+        return 256;
+    return n;
+}
+
 static int held_waves(const ResidentItem &it) { return rows_waves(it.rows + 2 * it.halo); }
 
 constexpr int RES_BLOCK_ROWS = RES_WAVES * RES_WAVE_ROWS;   // rows one workgroup holds
@@ -277,6 +288,13 @@ static std::vector<ResidentBin> resident_bins(const bml_batch *B, const std::vec
     };
     std::stable_sort(bins.begin(), bins.end(),
                      [&](const ResidentBin &x, const ResidentBin &y) { return cost(x) > cost(y); });
+    // Workgroup b shares a CU with b + cus and b + 2 cus (the dispatcher
+    // fills one slot of every CU before the next): alternate the direction
+    // of each run of `cus` bins, so that a CU that takes one of the heaviest
+    // bins takes one of the lightest of the next run.
+    const int cus = device_cus();
+    for (size_t t = cus; t < bins.size(); t += 2 * (size_t)cus)
+        std::reverse(bins.begin() + t, bins.begin() + std::min(bins.size(), t + cus));
     return bins;
 }
 
