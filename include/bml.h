@@ -252,7 +252,9 @@ int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
 /* Register-resident tile kernel.  steps = 0 (the default): the streaming
  * kernel above.  steps = K (even, 2..32): each launch advances the lattice
  * K steps with the state held in registers: a workgroup loads a tile of
- * 1024 columns by up to 512 - 2K rows together with one 32-cell halo word
+ * 1024 columns (512 or 256 when the lattice, or the group of lattices
+ * stepped together, is too small to give every compute unit two such
+ * tiles) by up to 512 - 2K rows together with one 32-cell halo word
  * on each side and K halo rows above and below, advances it K steps
  * (both phases of Sec. 2 per step, synchronous as in Sec. 3, or Model III's
  * one phase) and stores the tile's own cells, which are exact because what
@@ -260,7 +262,7 @@ int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
  * The state is read and written once per K steps.  Needs the model of
  * Sec. 2 or Model III (bml_set_model; Model II is refused here and, once
  * the tile kernel is on, by bml_set_model) on the torus, rows a multiple of
- * 32 and columns a multiple of 1024 (EINVAL otherwise; the
+ * 32 and columns a multiple of 256 (EINVAL otherwise; the
  * library then keeps the streaming kernel), and allocates a small count
  * buffer with the handle (EDEVICE if that fails).  Synchronises the stream.
  * bml_get_resident returns K (0 = streaming), < 0 on error.  Results do not

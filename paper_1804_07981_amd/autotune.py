@@ -339,7 +339,7 @@ def main(argv=None) -> int:
     # the register-resident tile kernel: the model of Sec. 2 and Model III,
     # 1024-column tiles
     res = (16, 24, 28, 32) if m in (1, 3) else ()
-    tiles = lambda rows, cols: res if rows % 32 == 0 and cols % 1024 == 0 else ()  # noqa: E731
+    tiles = lambda rows, cols: res if rows % 32 == 0 and cols % 256 == 0 else ()  # noqa: E731
     for n in args.sizes:
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE

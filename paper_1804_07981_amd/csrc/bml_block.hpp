@@ -1,14 +1,15 @@
 // bml_block.hpp -- register-resident tile kernel for single lattices
 // (gfx950): up to 32 steps per HBM pass.
 //
-// The lattice is cut into tiles of 32 words (1024 cells) by up to 512 - 2K
-// rows.  A 4-wave workgroup holds one tile with one halo word on each side
-// and K halo rows above and below, two rows per lane (34 LR and 34 TB words
-// per row), loads it once, advances it K steps in registers and stores the
-// tile's own words and rows.  Three such workgroups fit a CU (168 VGPRs
-// per lane, 41 KB of LDS each), so each SIMD interleaves three waves.  The
-// rule of Marzolla, arXiv:1804.07981,
-// Sec. 2 decides every move from the cell's neighbour in the direction of
+// The lattice is cut into tiles of 32 words (1024 cells; 16 or 8 words for
+// lattices too small to give every CU work) by up to 512 - 2K rows.  A
+// 4-wave workgroup holds one tile with one halo word on each side and K
+// halo rows above and below, two rows per lane (34 LR and 34 TB words per
+// row for the widest tiles), loads it once, advances it K steps in
+// registers and stores the tile's own words and rows.  Three such
+// workgroups fit a CU (at most 168 VGPRs per lane, 41 KB of LDS each), so
+// each SIMD interleaves three waves.  The rule of Marzolla,
+// arXiv:1804.07981, Sec. 2 decides every move from the cell's neighbour in the direction of
 // travel, so what the held block does not know (the cells beyond its halo)
 // travels at most one cell right and one row down per step, and its error
 // reaches at most K cells into the 32-cell halo words and K rows into the
@@ -34,8 +35,7 @@
 
 namespace bml {
 
-constexpr int BLK_WORDS = 32;                 // tile words (columns / 32)
-constexpr int BLK_W = BLK_WORDS + 2;          // words held per row: a halo word each side
+constexpr int BLK_WORDS = 32;                 // own words per row of the widest tiles
 constexpr int BLK_WAVES = 4;                  // one wave per SIMD, three workgroups per CU
 constexpr int BLK_ROWS = BLK_WAVES * 128;     // rows a workgroup holds (two per lane)
 constexpr int BLK_MAX_K = 32;                 // steps per launch (the halo word's 32 cells)
@@ -131,10 +131,14 @@ __device__ __forceinline__ void wave_sync_lds()
 // which every car looks at the state before the step (a car moves when its
 // target cell held no car; an empty cell wanted by an LR and a TB car takes
 // both).
-template <int IO, int MODEL>
+// TW: own words per tile row (32, 16 or 8); narrower tiles make more
+// workgroups for lattices too small to fill the GPU with 1024-column tiles.
+template <int IO, int MODEL, int TW>
 __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
 {
-    constexpr int W = BLK_W;
+    static_assert(TW % BLK_CHUNK == 0 && TW <= BLK_WORDS, "tile width");
+    constexpr int W = TW + 2;                    // words held per row
+    constexpr int XW = (W + 3) / 4 * 4;          // exchange words, whole 16-byte groups
     __shared__ BlockShared sh;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     // Lattice rows of the lane (periodic).
     const int g0 = row_ok ? (r0 - H + row + 2 * N) % N : 0;
     const int g1 = g0 + 1 == N ? 0 : g0 + 1;
-    const int w0 = tx * BLK_WORDS;
+    const int w0 = tx * TW;
     const int wrow0 = wave * 128;                           // the wave's first held row
     const int wrows = wave_on ? min(128, held - wrow0) : 0; // rows the wave holds
     // Lattice row of held row wrow0 + q (0 <= q < 8): the staged loops step
@@ -193,7 +197,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     auto load_halo = [&](int h, int g, uint32_t (&Lr)[W], uint32_t (&Tr)[W]) {
         const uint32_t ro = (uint32_t)g * row_bytes;
         const int i = h ? W - 1 : 0;
-        const int w = h ? (w0 + BLK_WORDS == words ? 0 : w0 + BLK_WORDS)
+        const int w = h ? (w0 + TW == words ? 0 : w0 + TW)
                         : (w0 == 0 ? words - 1 : w0 - 1);
         if constexpr (IO == IO_U8) {
             const u32x4 u0 = __builtin_amdgcn_raw_buffer_load_b128(src, ro + (uint32_t)w * 32u,
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     }
     if (wave_on) {
 #pragma unroll
-        for (int c = 0; c < BLK_WORDS / BLK_CHUNK; ++c) {
+        for (int c = 0; c < TW / BLK_CHUNK; ++c) {
             stage_in(c);
             wave_sync_lds();
 #pragma unroll
@@ -443,17 +447,17 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                 c_lr = hphase(f_lr);
             if (lane == 0) {
 #pragma unroll
-                for (int i = 0; i < BLK_XW; i += 4)
+                for (int i = 0; i < XW; i += 4)
                     *reinterpret_cast<u32x4 *>(&sh.x[p][wave][0][i]) =
-                        (u32x4){~(L0[i] | T0[i]), ~(L0[i + 1] | T0[i + 1]),
+                        (u32x4){~(L0[i] | T0[i]), i + 1 < W ? ~(L0[i + 1] | T0[i + 1]) : 0u,
                                 i + 2 < W ? ~(L0[i + 2] | T0[i + 2]) : 0u,
                                 i + 3 < W ? ~(L0[i + 3] | T0[i + 3]) : 0u};
             }
             if (lane == last_lane) {
 #pragma unroll
-                for (int i = 0; i < BLK_XW; i += 4)
+                for (int i = 0; i < XW; i += 4)
                     *reinterpret_cast<u32x4 *>(&sh.x[p][wave][1][i]) =
-                        (u32x4){T1[i], T1[i + 1], i + 2 < W ? T1[i + 2] : 0u,
+                        (u32x4){T1[i], i + 1 < W ? T1[i + 1] : 0u, i + 2 < W ? T1[i + 2] : 0u,
                                 i + 3 < W ? T1[i + 3] : 0u};
             }
         }
@@ -473,9 +477,9 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
             // previous one, carried from group to group
             uint32_t o0 = L0[0] | T0[0], o1 = L1[0] | T1[0], q0 = 0, q1 = 0, c_l1 = 0;
 #pragma unroll
-            for (int g = 0; g < BLK_XW; g += VG) {
+            for (int g = 0; g < XW; g += VG) {
                 const xvec cb = nb, ca = na;
-                if (g + VG < BLK_XW) {
+                if (g + VG < XW) {
                     nb = *reinterpret_cast<const xvec *>(xb + g + VG);
                     na = *reinterpret_cast<const xvec *>(xa + g + VG);
                 }
@@ -639,7 +643,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     }
     if (wave_on) {
 #pragma unroll
-        for (int c = 0; c < BLK_WORDS / BLK_CHUNK; ++c) {
+        for (int c = 0; c < TW / BLK_CHUNK; ++c) {
 #pragma unroll
             for (int j = 0; j < BLK_CHUNK; ++j) {
                 const int i = 1 + BLK_CHUNK * c + j;
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
 }
 
 using BlockFn = void (*)(BlockArgs);
-// [layout][0: the two-phase rule, 1: Model III]
-void block_kernels(BlockFn (*fn)[2]);
+// [layout][0: the two-phase rule, 1: Model III][tile width 32, 16, 8 words]
+void block_kernels(BlockFn (*fn)[2][3]);
 
 } // namespace bml

@@ -767,11 +767,12 @@ int bml_set_resident(bml_lattice *L, int32_t steps)
         if (L->model == 2 || L->topology != BML_TOPO_TORUS)
             return fail(BML_EINVAL, "the register-resident tile kernel runs the model of "
                                     "Sec. 2 and Model III on the torus only");
-        if (L->rows % 32 || L->cols % (32 * BLK_WORDS))
+        if (L->rows % 32 || L->cols % (32 * BLK_CHUNK))
             return fail(BML_EINVAL, "%d x %d: the register-resident tile kernel needs rows "
                                     "a multiple of 32 and columns a multiple of %d",
-                        L->rows, L->cols, 32 * BLK_WORDS);
-        const int64_t tiles = (int64_t)(L->cols / 32 / BLK_WORDS) * block_slabs(L->rows, steps);
+                        L->rows, L->cols, 32 * BLK_CHUNK);
+        // counts of the narrowest tiles (the most tiles a launch may use)
+        const int64_t tiles = (int64_t)(L->cols / 32 / BLK_CHUNK) * block_slabs(L->rows, steps);
         const size_t bytes = (size_t)tiles * BLK_MAX_K * 4 * sizeof(uint32_t);
         BML_HIP(hipStreamSynchronize(L->stream));   // the old buffer may be in use
         if (L->d_partial)
@@ -927,10 +928,25 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
 
 // ---- register-resident tile kernel ---------------------------------------
 
+// Tile widths (own words per row) of the tile kernel, widest first.
+constexpr int BLK_WIDTHS[3] = {32, 16, 8};
+
 struct BlockTable {
-    BlockFn fn[2][2] = {};   // [layout][0: the two-phase rule, 1: Model III]
+    // [layout][0: the two-phase rule, 1: Model III][width index]
+    BlockFn fn[2][2][3] = {};
     BlockTable() { block_kernels(fn); }
 };
+
+// Compute units of the current device (256 when the query fails).
+static int block_device_cus()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+        return 256;
+    return n;
+}
 
 static const BlockTable &block_table()
 {
@@ -990,10 +1006,24 @@ static int run_block(bml_lattice *const *G, int count, int k, const int64_t *ste
     a.n_lat = count;
     a.rows = L->rows;
     a.words = L->cols / 32;
-    a.tiles_x = a.words / BLK_WORDS;
     a.halo = L->block_steps;
     a.slabs = block_slabs(L->rows, a.halo);
     a.n_steps = k;
+    // The widest tiles that still give every CU two workgroups (narrower
+    // tiles hold more halo columns per own column), else the narrowest
+    // that divide the row.
+    static const int cus = block_device_cus();
+    int wi = -1;
+    for (int i = 0; i < 3; ++i) {
+        if (a.words % BLK_WIDTHS[i])
+            continue;
+        wi = i;
+        if ((int64_t)count * (a.words / BLK_WIDTHS[i]) * a.slabs >= 2 * cus)
+            break;
+    }
+    if (wi < 0)
+        return fail(BML_EINVAL, "%d columns: not a whole number of tiles", L->cols);
+    a.tiles_x = a.words / BLK_WIDTHS[wi];
     const int tiles = a.tiles_x * a.slabs;
     BlockSumArgs b;
     std::memset(&b, 0, sizeof b);
@@ -1009,7 +1039,7 @@ static int run_block(bml_lattice *const *G, int count, int k, const int64_t *ste
         b.rec_from[i] = rec_from[i];
         b.cap[i] = G[i]->cap;
     }
-    hipLaunchKernelGGL(block_table().fn[io][L->model == 3 ? 1 : 0], dim3((unsigned)(tiles * count)),
+    hipLaunchKernelGGL(block_table().fn[io][L->model == 3 ? 1 : 0][wi], dim3((unsigned)(tiles * count)),
                        dim3(64 * BLK_WAVES), 0, L->stream, a);
     BML_HIP(hipGetLastError());
     hipLaunchKernelGGL(block_sum_kernel, dim3((unsigned)(count * k * 4)), dim3(256), 0,

@@ -48,11 +48,16 @@ def check(lat, want, wst, steps):
 # rows x cols, halo steps, steps: one and several tiles and slabs, a lattice
 # shorter than its halo (its held block wraps around it several times), runs
 # ending inside a launch, slabs cut unevenly (1376 rows at K = 28: four
-# slabs of 344; 2336 rows at K = 30: six slabs of 388 or 390 rows)
+# slabs of 344; 2336 rows at K = 30: six slabs of 388 or 390 rows), and the
+# three tile widths
 CASES = [(1024, 1024, 32, 70), (1024, 1024, 16, 37), (1024, 1024, 2, 9),
          (2048, 3072, 32, 65), (96, 1024, 32, 40), (32, 2048, 32, 33),
          (1472, 1024, 24, 50), (512, 4096, 8, 20), (1376, 2048, 28, 61),
-         (2336, 1024, 30, 31)]
+         (2336, 1024, 30, 31),
+         # narrower tiles: 16 words (4064 x 32768 at K = 2: 256 tiles of 32
+         # words would leave CUs idle), 8 words (a lone 4096^2 lattice; 768
+         # and 256 columns, which only 8-word tiles divide)
+         (4064, 32768, 2, 9), (4096, 4096, 32, 45), (1024, 768, 8, 20), (512, 256, 32, 40)]
 
 
 @pytest.mark.parametrize("layout", [0, 1])
@@ -160,7 +165,7 @@ def test_block_refusals(B):
         with pytest.raises(B.BmlError) as e:
             lat.set_resident(16)                 # Klein bottle: the streaming kernel only
         assert e.value.code == B.BML_EINVAL
-    with B.Lattice(96, 0.3, 1, stats_cap=8) as lat:  # 96 columns: not whole 1024-column tiles
+    with B.Lattice(96, 0.3, 1, stats_cap=8) as lat:  # 96 columns: not whole 256-column tiles
         with pytest.raises(B.BmlError) as e:
             lat.set_resident(16)
         assert e.value.code == B.BML_EINVAL
