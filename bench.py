@@ -605,9 +605,9 @@ def hbm_roofline(res: dict, layout: int, kname: str, extra: dict | None = None) 
                                    resident=res.get("resident", 0))
     lay = "u8" if layout == 0 else "bitplane"
     if res.get("resident"):
-        kernel = (f"block_kernel<{lay}, K={k}> (register-resident tiles of 1024 columns x up "
-                  f"to {512 - 2 * k} rows with {k} halo rows, 4 waves/block, "
-                  f"{res['lattices_per_launch']} lattice(s) per launch)")
+        kernel = (f"block_kernel<{lay}, K={k}> (register-resident tiles of 1024, 512 or 256 "
+                  f"columns by launch size x up to {512 - 2 * k} rows with {k} halo rows, "
+                  f"4 waves/block, {res['lattices_per_launch']} lattice(s) per launch)")
     else:
         kernel = (f"pass_kernel<{lay}, K={k}> (strip rows {res['tile_rows'] or 'auto'}, "
                   f"{res['wpb']} waves/block, {res['lattices_per_launch']} lattice(s) per "
