@@ -142,12 +142,14 @@ def load_tuning(layout: int, n, group: str | None = None, model: int = 1):
     return None
 
 
-def load_resident_steps(layout: int, n, group: str | None = None, model: int = 1) -> int:
+def load_resident_steps(layout: int, n, group: str | None = None, model: int = 1,
+                        topology: int = 0) -> int:
     """Autotuned steps per launch of the register-resident tile kernel for
     the lattice (or group) the tuning cache entry names (0: the streaming
     kernel is faster, or no entry).  Model III reads only its own (/model3)
-    entries; Model II, which the tile kernel does not run: always 0."""
-    if model == 2:
+    entries, the Klein bottle (topology 1) its own (/klein); Model II, which
+    the tile kernel does not run: always 0."""
+    if model == 2 or (model == 3 and topology != 0):
         return 0
     path = os.path.join(ROOT, "paper_1804_07981_amd", "tune_cache.json")
     try:
@@ -156,7 +158,7 @@ def load_resident_steps(layout: int, n, group: str | None = None, model: int = 1
     except (OSError, ValueError):
         return 0
     lay = "u8" if layout == 0 else "bp"
-    suffix = "/model3" if model == 3 else ""
+    suffix = "/model3" if model == 3 else "/klein" if topology != 0 else ""
     for key in ([f"gfx950/{lay}/{group}{suffix}"] if group else []) + [f"gfx950/{lay}/{n}{suffix}"]:
         if key in cache:
             return int(cache[key].get("resident_steps", 0))
@@ -526,7 +528,8 @@ def measure(B, dev, wl, layout: int, steps: int, warmup: int, mode: str, load, c
         res_k = resident
         if res_k is None:
             res_k = 0 if tuning else load_resident_steps(
-                layout, size_key(lt), group if mode == "joint" else None, lat.model)
+                layout, size_key(lt), group if mode == "joint" else None, lat.model,
+                lat.topology)
         if res_k:
             lat.set_resident(res_k)
         lats.append(lat)
@@ -714,7 +717,7 @@ def main() -> int:
         tun = load(layout, size_key(wl.lattices[0]), group)
         res_k = args.resident if args.resident is not None else (
             0 if args.tuning else load_resident_steps(layout, size_key(wl.lattices[0]), group,
-                                                      args.model))
+                                                      args.model, topology))
         for lat in lats:
             if tun:
                 lat.set_tuning(*tun)

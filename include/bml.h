@@ -260,9 +260,11 @@ int bml_get_tuning(const bml_lattice *L, int32_t *tile_rows, int32_t *t_phases,
  * one phase) and stores the tile's own cells, which are exact because what
  * the held block does not know moves at most one cell and one row per step.
  * The state is read and written once per K steps.  Needs the model of
- * Sec. 2 or Model III (bml_set_model; Model II is refused here and, once
- * the tile kernel is on, by bml_set_model) on the torus, rows a multiple of
- * 32 and columns a multiple of 256 (EINVAL otherwise; the
+ * Sec. 2 (on the torus or on the Klein bottle above, where a tile of the
+ * first or last slab holds the rows across the glued edge mirrored) or
+ * Model III on the torus (bml_set_model; Model II is refused
+ * here and, once the tile kernel is on, by bml_set_model), rows a multiple
+ * of 32 and columns a multiple of 256 (EINVAL otherwise; the
  * library then keeps the streaming kernel), and allocates a small count
  * buffer with the handle (EDEVICE if that fails).  Synchronises the stream.
  * bml_get_resident returns K (0 = streaming), < 0 on error.  Results do not

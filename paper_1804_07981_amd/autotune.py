@@ -48,11 +48,12 @@ def arch() -> str:
     return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
 
 
-def key(layout: int, n, model: int = 1) -> str:
+def key(layout: int, n, model: int = 1, topology: int = 0) -> str:
     """Cache key: arch/layout/size, with a /model2 or /model3 suffix for
-    Models II and III."""
+    Models II and III and /klein for the Klein bottle."""
     return (f"{arch()}/{'u8' if layout == L.BML_LAYOUT_U8 else 'bp'}/{n}"
-            + (f"/model{model}" if model != 1 else ""))
+            + (f"/model{model}" if model != 1 else "")
+            + ("/klein" if topology != 0 else ""))
 
 
 def load(path: str = CACHE) -> dict:
@@ -122,10 +123,11 @@ def _best(results):
 def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
                  t_phases=(2, 4, 8, 12, 16), waves=(2, 4), steps: int | None = None,
                  rho: float = 0.3, seed: int = 7, log=print, shape: dict | None = None,
-                 model: int = 1, reference=None, resident=()) -> dict:
+                 model: int = 1, reference=None, resident=(), topology: int = 0) -> dict:
     """Fastest (tile_rows, t_phases, waves_per_block) for an n x n lattice, or
     n rows x shape["cols"] with the draw in `shape` (Lattice keywords), under
-    update rule `model` (1, 2 for Model II, 3 for Model III), and whether the
+    update rule `model` (1, 2 for Model II, 3 for Model III) on `topology`
+    (BML_TOPO_TORUS or BML_TOPO_KLEIN), and whether the
     register-resident tile kernel with one of the steps per launch in
     `resident` beats it.  `reference`: the (cells, counts[steps][4]) every
     candidate must reproduce (default: the first candidate's run)."""
@@ -140,6 +142,8 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
     size = f"{n}x{shape['cols']}" if "cols" in shape else f"{n}"
     for kind, cand in _candidates(strip_rows, t_phases, waves, resident):
         with Lattice(n, rho, seed, layout=layout, stats_cap=steps, **shape) as lat:
+            if topology != 0:
+                lat.set_topology(topology)
             if model != 1:
                 lat.set_model(model, MODEL2_COIN_SEED)
             if kind == "stream":
@@ -177,7 +181,7 @@ def tune_lattice(n: int, layout: int, strip_rows=(0, 8, 16, 32, 64, 128, 256),
 def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 32, 48),
                t_phases=(8, 10, 12, 14, 16), waves=(2, 4), steps: int = 480, log=print,
                model: int = 1, reference=None, make_lattice=Lattice, step=step_group,
-               resident=()) -> dict:
+               resident=(), topology: int = 0) -> dict:
     """Fastest common tuning for lattices (n, rho, seed) of one size that are
     advanced together by joint launches (bml_step_group): a launch spreads
     the strips of all of them over the device, so the best strip height
@@ -198,6 +202,8 @@ def tune_group(specs, layout: int, name: str, strip_rows=(0, 4, 8, 12, 16, 24, 3
                 for n, rho, seed in specs]
         try:
             for lat in lats:
+                if topology != 0:
+                    lat.set_topology(topology)
                 if model != 1:
                     lat.set_model(model, MODEL2_COIN_SEED)
                 if kind == "stream":
@@ -331,8 +337,13 @@ def main(argv=None) -> int:
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
     ap.add_argument("--model", type=int, choices=[1, 2, 3], default=1,
                     help="update rule of the tuned runs: 1, 2 (Model II) or 3 (Model III)")
+    ap.add_argument("--klein", action="store_true",
+                    help="tune on the Klein bottle (the model of Sec. 2 only)")
     args = ap.parse_args(argv)
     m = args.model
+    topo = L.BML_TOPO_KLEIN if args.klein else L.BML_TOPO_TORUS
+    if args.klein and m != 1:
+        ap.error("--klein: the model of Sec. 2 only")
     torch.cuda.set_device(0)
     cache = load(args.cache)
     kw = dict(strip_rows=(0, 64, 256), t_phases=(4, 8, 16), waves=(4,)) if args.quick else {}
@@ -343,17 +354,18 @@ def main(argv=None) -> int:
     for n in args.sizes:
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
-            r = tune_lattice(n, layout, model=m, resident=tiles(n, n), **kw)
-            cache[key(layout, n, m)] = dict(r["best"], steps=r["steps"])
-            print(json.dumps({"key": key(layout, n, m), **r["best"]}), flush=True)
+            r = tune_lattice(n, layout, model=m, resident=tiles(n, n), topology=topo, **kw)
+            cache[key(layout, n, m, topo)] = dict(r["best"], steps=r["steps"])
+            print(json.dumps({"key": key(layout, n, m, topo), **r["best"]}), flush=True)
     if args.rect:
         import workloads
         lt = workloads.RECT.lattices[0]
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
             r = tune_lattice(lt.n, layout, rho=lt.rho, seed=lt.seed, shape=lt.kwargs(),
-                             model=m, resident=tiles(lt.n, lt.cols or lt.n), **kw)
-            k = key(layout, f"{lt.n}x{lt.cols}", m)
+                             model=m, resident=tiles(lt.n, lt.cols or lt.n), topology=topo,
+                             **kw)
+            k = key(layout, f"{lt.n}x{lt.cols}", m, topo)
             cache[k] = dict(r["best"], steps=r["steps"])
             print(json.dumps({"key": k, **r["best"]}), flush=True)
     if args.medium:
@@ -362,8 +374,8 @@ def main(argv=None) -> int:
         for lay in args.layouts:
             layout = L.BML_LAYOUT_U8 if lay == "u8" else L.BML_LAYOUT_BITPLANE
             r = tune_group(specs, layout, workloads.MEDIUM_GROUP, model=m,
-                           resident=tiles(specs[0][0], specs[0][0]))
-            k = key(layout, workloads.MEDIUM_GROUP, m)
+                           resident=tiles(specs[0][0], specs[0][0]), topology=topo)
+            k = key(layout, workloads.MEDIUM_GROUP, m, topo)
             cache[k] = dict(r["best"], steps=r["steps"])
             print(json.dumps({"key": k, **r["best"]}), flush=True)
     if args.batch:

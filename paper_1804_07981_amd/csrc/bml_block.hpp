@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "bml_pass.hpp"
 #include "bml_resident.hpp"
 #include "bml_tile.hpp"
@@ -133,9 +135,16 @@ __device__ __forceinline__ void wave_sync_lds()
 // both).
 // TW: own words per tile row (32, 16 or 8); narrower tiles make more
 // workgroups for lattices too small to fill the GPU with 1024-column tiles.
-template <int IO, int MODEL, int TW>
+// KLEIN: the Klein bottle (top and bottom edges glued with a reversal;
+// the model of Sec. 2 only): a held row beyond the lattice's first or last
+// row is the row across the glued edge, held mirrored (tile column j holds
+// the lattice cell vertically next to it, cols - 1 - j), so its LR cars move
+// towards lower tile columns.  Only tiles of the first and last slab hold
+// such rows, and only they run the mirrored horizontal phase.
+template <int IO, int MODEL, int TW, bool KLEIN>
 __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
 {
+    static_assert(!KLEIN || MODEL == 1, "Klein bottle: the model of Sec. 2 only");
     static_assert(TW % BLK_CHUNK == 0 && TW <= BLK_WORDS, "tile width");
     constexpr int W = TW + 2;                    // words held per row
     constexpr int XW = (W + 3) / 4 * 4;          // exchange words, whole 16-byte groups
@@ -148,7 +157,14 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     // boundary lines a tile reads as halo (the tiles left and right, the
     // slabs above and below) mostly run on the same XCD and share its L2.
     const int nb = (int)gridDim.x, xcd = (int)blockIdx.x & 7;
-    const int t = xcd * (nb >> 3) + min(xcd, nb & 7) + ((int)blockIdx.x >> 3);
+    int j = (int)blockIdx.x >> 3;
+    // Klein bottle: the tiles of the first and last slab do more work per
+    // step; the last XCD takes its run backwards, so that they start in the
+    // first round instead of finishing the launch.
+    if constexpr (KLEIN)
+        if (xcd == 7)
+            j = (nb >> 3) - 1 - j;   // XCD 7 runs exactly nb / 8 workgroups
+    const int t = xcd * (nb >> 3) + min(xcd, nb & 7) + j;
     const int li = t / tiles;
     const int local = t - li * tiles;
     const int slab = local / a.tiles_x;
@@ -187,6 +203,14 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     // Lattice row of held row wrow0 + q (0 <= q < 8): the staged loops step
     // it by 4 or 8 rows (N >= 32).
     const int gbase = __builtin_amdgcn_readfirstlane((r0 - H + wrow0 + 2 * N) % N);
+    // Klein bottle: the block holds rows across the glued edge (edge), and
+    // which of the lane's two rows are such rows (held mirrored).
+    const int ubase = r0 - H + wrow0;            // unwrapped lattice row of held row wrow0
+    const bool edge = KLEIN && (r0 - H < 0 || r0 + R + H > N);
+    // the wave holds mirrored rows (uniform across the wave)
+    const bool wave_mir = edge && wave_on && (ubase < 0 || ubase + wrows > N);
+    const bool mir0 = edge && (r0 - H + row < 0 || r0 - H + row >= N);
+    const bool mir1 = edge && (r0 - H + row + 1 < 0 || r0 - H + row + 1 >= N);
     uint32_t *stL = sh.stage[wave][0];
     uint32_t *stT = sh.stage[wave][1];
     uint32_t L0[W], T0[W], L1[W], T1[W];
@@ -194,23 +218,31 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     // Halo word h of a row (h = 0: held word 0, lattice word w0 - 1; h = 1:
     // held word W - 1, lattice word w0 + 32; periodic), each lane its own
     // rows.
-    auto load_halo = [&](int h, int g, uint32_t (&Lr)[W], uint32_t (&Tr)[W]) {
+    auto load_halo = [&](int h, int g, bool mir, uint32_t (&Lr)[W], uint32_t (&Tr)[W]) {
         const uint32_t ro = (uint32_t)g * row_bytes;
         const int i = h ? W - 1 : 0;
-        const int w = h ? (w0 + TW == words ? 0 : w0 + TW)
-                        : (w0 == 0 ? words - 1 : w0 - 1);
+        int w = h ? (w0 + TW == words ? 0 : w0 + TW) : (w0 == 0 ? words - 1 : w0 - 1);
+        if (KLEIN && mir)
+            w = words - 1 - w;                   // the mirror word, bits reversed below
+        uint32_t l, t;
         if constexpr (IO == IO_U8) {
             const u32x4 u0 = __builtin_amdgcn_raw_buffer_load_b128(src, ro + (uint32_t)w * 32u,
                                                                    0, 0);
             const u32x4 u1 = __builtin_amdgcn_raw_buffer_load_b128(
                 src, ro + (uint32_t)w * 32u + 16u, 0, 0);
             const uint32_t dw[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-            bytes_to_planes(dw, Lr[i], Tr[i]);
+            bytes_to_planes(dw, l, t);
         } else {
-            Lr[i] = __builtin_amdgcn_raw_buffer_load_b32(src, ro + (uint32_t)w * 4u, 0, 0);
-            Tr[i] = __builtin_amdgcn_raw_buffer_load_b32(src, ro + plane_bytes + (uint32_t)w * 4u,
-                                                         0, 0);
+            l = __builtin_amdgcn_raw_buffer_load_b32(src, ro + (uint32_t)w * 4u, 0, 0);
+            t = __builtin_amdgcn_raw_buffer_load_b32(src, ro + plane_bytes + (uint32_t)w * 4u, 0,
+                                                     0);
         }
+        if (KLEIN && mir) {
+            l = __builtin_bitreverse32(l);
+            t = __builtin_bitreverse32(t);
+        }
+        Lr[i] = l;
+        Tr[i] = t;
     };
 
     // Chunk c of the tile's own words (held words 1 + 8c .. 8 + 8c) of the
@@ -223,15 +255,23 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
             uint16_t *sT = reinterpret_cast<uint16_t *>(stT);
             const int q = lane >> 4, w = (lane & 15) >> 1, hf = lane & 1;
             const uint32_t co = (uint32_t)(w0 + BLK_CHUNK * c + w) * 32u + (uint32_t)hf * 16u;
+            // a mirrored row: the other half of the mirror word, cells reversed
+            const uint32_t co_m =
+                (uint32_t)(words - 1 - (w0 + BLK_CHUNK * c + w)) * 32u + (uint32_t)(1 - hf) * 16u;
             int g = gbase + q;
             g = g >= N ? g - N : g;
 #pragma unroll 16
             for (int it = 0; it < 32; ++it) {
                 const int r = 4 * it + q;
+                const bool mir = edge && (ubase + r < 0 || ubase + r >= N);
                 // Unconditional loads (g is always a lattice row), so that
                 // the unrolled loads are all in flight before the first use.
                 uint32_t x = bytes16_to_halves(__builtin_amdgcn_raw_buffer_load_b128(
-                    src, (uint32_t)g * row_bytes + co, 0, 0));
+                    src, (uint32_t)g * row_bytes + (KLEIN && mir ? co_m : co), 0, 0));
+                if (KLEIN && mir) {                  // both halves' cells reversed
+                    x = __builtin_bitreverse32(x);
+                    x = __builtin_amdgcn_alignbit(x, x, 16);
+                }
                 x = r < wrows ? x : 0u;
                 const int si = 2 * stage_index(r, w) + hf;
                 sL[si] = (uint16_t)x;
@@ -242,14 +282,20 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
         } else {
             const int q = lane >> 3, w = lane & 7;
             const uint32_t co = (uint32_t)(w0 + BLK_CHUNK * c + w) * 4u;
+            const uint32_t co_m = (uint32_t)(words - 1 - (w0 + BLK_CHUNK * c + w)) * 4u;
             int g = gbase + q;
             g = g >= N ? g - N : g;
 #pragma unroll 4
             for (int it = 0; it < 16; ++it) {
                 const int r = 8 * it + q;
-                const uint32_t o = (uint32_t)g * row_bytes + co;
-                const uint32_t l = __builtin_amdgcn_raw_buffer_load_b32(src, o, 0, 0);
-                const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(src, o + plane_bytes, 0, 0);
+                const bool mir = edge && (ubase + r < 0 || ubase + r >= N);
+                const uint32_t o = (uint32_t)g * row_bytes + (KLEIN && mir ? co_m : co);
+                uint32_t l = __builtin_amdgcn_raw_buffer_load_b32(src, o, 0, 0);
+                uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(src, o + plane_bytes, 0, 0);
+                if (KLEIN && mir) {
+                    l = __builtin_bitreverse32(l);
+                    t = __builtin_bitreverse32(t);
+                }
                 stL[stage_index(r, w)] = r < wrows ? l : 0u;
                 stT[stage_index(r, w)] = r < wrows ? t : 0u;
                 g += 8;
@@ -308,8 +354,8 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     // the left one the last word the tile to the left loads: loaded at the
     // same times, their lines are mostly still in the XCD's L2.
     if (row_ok) {
-        load_halo(1, g0, L0, T0);
-        load_halo(1, g1, L1, T1);
+        load_halo(1, g0, mir0, L0, T0);
+        load_halo(1, g1, mir1, L1, T1);
     }
     if (wave_on) {
 #pragma unroll
@@ -328,8 +374,8 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
         }
     }
     if (row_ok) {
-        load_halo(0, g0, L0, T0);
-        load_halo(0, g1, L1, T1);
+        load_halo(0, g0, mir0, L0, T0);
+        load_halo(0, g1, mir1, L1, T1);
     }
     // Cars on the tile's own cells, per wave: counted directly after the
     // load and after the last step; the per-step counts in between follow
@@ -368,6 +414,31 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
     // instructions to issue back to back.  Returns the LR movers of the
     // tile's own words.  The emptiness the vertical phase needs is
     // recomputed there from the planes (no array of it stays live).
+    // Klein bottle: a mirrored row reversed in place (word order and bit
+    // order), so that its LR cars move towards higher columns; the
+    // horizontal phase then runs unchanged on it (its open ends swap with
+    // the row), and a second reversal restores the tile frame.  Lanes whose
+    // rows are not mirrored keep them.
+    auto reverse_mirrored = [&]() {
+#pragma unroll
+        for (int i = 0; i < W / 2; ++i) {
+            const int k = W - 1 - i;
+            uint32_t a, b;
+            a = L0[i]; b = L0[k];
+            L0[i] = mir0 ? __builtin_bitreverse32(b) : a;
+            L0[k] = mir0 ? __builtin_bitreverse32(a) : b;
+            a = T0[i]; b = T0[k];
+            T0[i] = mir0 ? __builtin_bitreverse32(b) : a;
+            T0[k] = mir0 ? __builtin_bitreverse32(a) : b;
+            a = L1[i]; b = L1[k];
+            L1[i] = mir1 ? __builtin_bitreverse32(b) : a;
+            L1[k] = mir1 ? __builtin_bitreverse32(a) : b;
+            a = T1[i]; b = T1[k];
+            T1[i] = mir1 ? __builtin_bitreverse32(b) : a;
+            T1[k] = mir1 ? __builtin_bitreverse32(a) : b;
+        }
+    };
+
     auto hphase = [&](uint32_t &flux) {
         // one accumulator per popcount stream: each popcount adds into its
         // own (v_bcnt_u32_b32 with an addend), no separate adds
@@ -443,8 +514,17 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
             // Model III reads every neighbour before the step: the rows
             // exchanged below are then the state before the step, and its
             // LR moves are made in the vertical loop.
-            if constexpr (MODEL == 1)
+            if constexpr (MODEL == 1) {
+                if constexpr (KLEIN) {
+                    if (wave_mir)
+                        reverse_mirrored();
+                }
                 c_lr = hphase(f_lr);
+                if constexpr (KLEIN) {
+                    if (wave_mir)
+                        reverse_mirrored();
+                }
+            }
             if (lane == 0) {
 #pragma unroll
                 for (int i = 0; i < XW; i += 4)
@@ -660,7 +740,8 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
 }
 
 using BlockFn = void (*)(BlockArgs);
-// [layout][0: the two-phase rule, 1: Model III][tile width 32, 16, 8 words]
-void block_kernels(BlockFn (*fn)[2][3]);
+// [layout][0: the two-phase rule, 1: Model III, 2: the two-phase rule on
+// the Klein bottle][tile width 32, 16, 8 words]
+void block_kernels(BlockFn (*fn)[3][3]);
 
 } // namespace bml

@@ -694,8 +694,6 @@ int bml_set_topology(bml_lattice *L, int32_t topology)
         return fail(BML_EINVAL, "unknown topology %d", topology);
     if (topology == BML_TOPO_KLEIN && L->model != 1)
         return fail(BML_EINVAL, "Models II and III run on the torus only");
-    if (topology != BML_TOPO_TORUS && L->block_steps)
-        return fail(BML_EINVAL, "the register-resident tile kernel runs on the torus only");
     L->topology = topology;
     return BML_OK;
 }
@@ -764,9 +762,9 @@ int bml_set_resident(bml_lattice *L, int32_t steps)
     if (steps < 0 || steps > BLK_MAX_K || steps % 2)
         return fail(BML_EINVAL, "steps=%d must be 0 or even in [2, %d]", steps, BLK_MAX_K);
     if (steps) {
-        if (L->model == 2 || L->topology != BML_TOPO_TORUS)
+        if (L->model == 2)
             return fail(BML_EINVAL, "the register-resident tile kernel runs the model of "
-                                    "Sec. 2 and Model III on the torus only");
+                                    "Sec. 2 (torus or Klein bottle) and Model III (torus)");
         if (L->rows % 32 || L->cols % (32 * BLK_CHUNK))
             return fail(BML_EINVAL, "%d x %d: the register-resident tile kernel needs rows "
                                     "a multiple of 32 and columns a multiple of %d",
@@ -932,8 +930,9 @@ static int run_pass(bml_lattice *const *G, int count, int k, const int64_t *step
 constexpr int BLK_WIDTHS[3] = {32, 16, 8};
 
 struct BlockTable {
-    // [layout][0: the two-phase rule, 1: Model III][width index]
-    BlockFn fn[2][2][3] = {};
+    // [layout][0: the two-phase rule, 1: Model III, 2: the two-phase rule on
+    // the Klein bottle][width index]
+    BlockFn fn[2][3][3] = {};
     BlockTable() { block_kernels(fn); }
 };
 
@@ -1039,7 +1038,8 @@ static int run_block(bml_lattice *const *G, int count, int k, const int64_t *ste
         b.rec_from[i] = rec_from[i];
         b.cap[i] = G[i]->cap;
     }
-    hipLaunchKernelGGL(block_table().fn[io][L->model == 3 ? 1 : 0][wi], dim3((unsigned)(tiles * count)),
+    const int rule = L->model == 3 ? 1 : L->topology == BML_TOPO_KLEIN ? 2 : 0;
+    hipLaunchKernelGGL(block_table().fn[io][rule][wi], dim3((unsigned)(tiles * count)),
                        dim3(64 * BLK_WAVES), 0, L->stream, a);
     BML_HIP(hipGetLastError());
     hipLaunchKernelGGL(block_sum_kernel, dim3((unsigned)(count * k * 4)), dim3(256), 0,

@@ -72,8 +72,9 @@ class Lattice:
 
     def set_resident(self, steps: int) -> None:
         """0: the streaming step kernel; K (even, 2..32): the register-resident
-        tile kernel, K steps per launch (torus, Sec. 2's model, rows a
-        multiple of 32, columns a multiple of 1024)."""
+        tile kernel, K steps per launch (Sec. 2's model on the torus or the
+        Klein bottle, or Model III on the torus; rows a multiple of 32,
+        columns a multiple of 256)."""
         B.bml_set_resident(self.handle, steps)
 
     @property

@@ -2,8 +2,8 @@
 against the CPU oracle: cells and all four counts of every step, for tile
 and slab counts of one and several, halos from 2 to 32 steps, runs that
 are not a whole number of launches, lattices shorter than their halo,
-joint launches of several lattices, Model III, and the arguments it
-refuses."""
+joint launches of several lattices, Model III, the Klein bottle, and the
+arguments it refuses."""
 import sys
 
 import numpy as np
@@ -101,6 +101,32 @@ def test_block_model3_matches_oracle(B, layout, rows, cols, k, steps):
         check(lat, want, wst, steps)
 
 
+KLEIN_CASES = [(1024, 1024, 32, 70), (2048, 3072, 28, 57), (96, 1024, 16, 33),
+               (32, 2048, 32, 33), (1376, 2048, 28, 61), (4096, 4096, 32, 45),
+               (1024, 768, 8, 20)]
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("rows,cols,k,steps", KLEIN_CASES,
+                         ids=[f"{r}x{c}_k{k}_s{s}" for r, c, k, s in KLEIN_CASES])
+def test_block_klein_matches_oracle(B, layout, rows, cols, k, steps):
+    """The Klein bottle in the tile kernel (rows across the glued edge held
+    mirrored in the first and last slabs; lattices shorter than the halo
+    hold rows from across the edge on both sides): cells and every count of
+    every step against the oracle's Klein bottle."""
+    rho_lr, rho_tb = 0.2, 0.22
+    seed = 5 * rows + cols + k
+    say(f"block klein {rows}x{cols} k={k} steps={steps} layout={layout}")
+    g0 = oracle.init_cells_asym(rows, cols, seed, rho_lr, rho_tb)
+    want, wst = oracle.run(g0, steps, n_threads=HOST_THREADS, topology=oracle.KLEIN)
+    with B.Lattice(rows, seed=seed, layout=layout, cols=cols, rho_lr=rho_lr, rho_tb=rho_tb,
+                   stats_cap=steps) as lat:
+        lat.set_topology(B.BML_TOPO_KLEIN)
+        lat.set_resident(k)
+        lat.step(steps)
+        check(lat, want, wst, steps)
+
+
 def test_block_continues_streaming_runs(B):
     """Runs alternate between the tile kernel (two halos) and the streaming
     kernel on one lattice: the counts ring and the cells follow the oracle."""
@@ -157,14 +183,11 @@ def test_block_refusals(B):
         assert e.value.code == B.BML_EINVAL
         lat.set_model(1)
         lat.set_resident(32)
+        lat.set_topology(B.BML_TOPO_KLEIN)       # the tile kernel runs the Klein bottle too
         with pytest.raises(B.BmlError) as e:
-            lat.set_topology(B.BML_TOPO_KLEIN)
+            lat.set_model(3)                     # Model III: the torus only
         assert e.value.code == B.BML_EINVAL
-        lat.set_resident(0)
-        lat.set_topology(B.BML_TOPO_KLEIN)
-        with pytest.raises(B.BmlError) as e:
-            lat.set_resident(16)                 # Klein bottle: the streaming kernel only
-        assert e.value.code == B.BML_EINVAL
+        lat.set_topology(B.BML_TOPO_TORUS)
     with B.Lattice(96, 0.3, 1, stats_cap=8) as lat:  # 96 columns: not whole 256-column tiles
         with pytest.raises(B.BmlError) as e:
             lat.set_resident(16)

@@ -689,21 +689,23 @@ def test_large_sampled_windows(B, layout, large_reference):
 
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_klein_large(B, layout, large_reference):
-    """32768 x 32768 Klein bottle in the benchmark's launch shape, 40 steps:
-    windows whose dependence cone stays clear of the glued edge match the
-    torus oracle on padded windows; over the whole lattice every row keeps
-    its LR cars and every column pair (j, N-1-j) its TB cars (a TB car
-    crossing the glued edge changes column j for N-1-j); the car counts of
-    every step are the initial ones."""
+    """32768 x 32768 Klein bottle in the benchmark's launch shape (the tile
+    kernel's when it was faster), 40 steps: every cell and every step's
+    counts against the whole-lattice Klein oracle; every row keeps its LR
+    cars and every column pair (j, N-1-j) its TB cars (a TB car crossing
+    the glued edge changes column j for N-1-j)."""
     import bench
-    n, rho, seed, steps, W = 32768, 0.30, 7, 40, 64
-    say(f"klein large n={n} layout={layout}")
+    n, rho, seed, steps = 32768, 0.30, 7, 40
     g0 = large_reference[0]
+    tun = bench.load_tuning(layout, n)
+    res = bench.load_resident_steps(layout, n, None, 1, B.BML_TOPO_KLEIN)
+    say(f"klein large n={n} layout={layout} tuning={tun} resident={res}")
     with make(B, n, rho, seed, layout, cap=steps) as lat:
         lat.set_topology(B.BML_TOPO_KLEIN)
-        tun = bench.load_tuning(layout, n)
         if tun:
             lat.set_tuning(*tun)
+        if res:
+            lat.set_resident(res)
         lat.step(steps)
         got = lat.cells()
         st = stats_array(lat.stats(0, steps))
@@ -712,14 +714,14 @@ def test_klein_large(B, layout, large_reference):
     tb_got, tb0 = (got == 2).sum(axis=0), (g0 == 2).sum(axis=0)
     assert np.array_equal(tb_got + tb_got[::-1], tb0 + tb0[::-1])
     assert not np.array_equal(tb_got, tb0)      # some TB cars crossed the glued edge
-    rng = np.random.default_rng(74)
-    picks = [(steps, 0), (n - W - steps, n - W), (n // 2, n // 2 - 32)]
-    picks += [(int(rng.integers(steps, n - W - steps)), int(rng.integers(0, n))) for _ in range(5)]
-    for i0, j0 in picks:
-        pad = window(g0, i0 - steps, j0 - steps, W + 2 * steps)
-        ref, _ = oracle.run(pad, steps)
-        assert np.array_equal(window(got, i0, j0, W), ref[steps:steps + W, steps:steps + W]), \
-            (i0, j0)
+    say(f"oracle: 32768^2 Klein {steps} steps, {HOST_THREADS} threads")
+    want, wst = oracle.run(g0, steps, n_threads=HOST_THREADS, topology=oracle.KLEIN)
+    if not np.array_equal(st, wst):
+        s0 = int(np.argwhere((st != wst).any(axis=1))[0, 0])
+        pytest.fail(f"counts differ from step {s0}: {st[s0]} vs {wst[s0]}")
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        pytest.fail(f"{len(bad)} cells differ, first at {bad[0]}")
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
