@@ -7,8 +7,9 @@ product: the two share no code.
 
 The lattice arithmetic lives in ``bml_oracle.c`` (plain C, optional OpenMP
 row split as in the paper's Sec. 4); this module builds it with gcc, loads it
-with ctypes and wraps it for numpy arrays.  ``mlp.py`` and ``features.py``
-hold the fp64 oracle of the learned early-exit classifier.
+with ctypes and wraps it for numpy arrays.  ``mlp.py`` holds the fp64 oracle
+of the learned early-exit classifier (trace features, labels, network,
+gradient, Adam and BF16 inference).
 
 Paper: M. Marzolla, "Parallel Implementations of Cellular Automata for
 Traffic Models", arXiv:1804.07981 (Sec. 2 model and case tables, Sec. 3
