@@ -69,6 +69,7 @@ struct BlockArgs {
 // (8 + 1 pad) and a lane's upper and lower rows sit in separate halves, so
 // a lane reading its own rows hits bank 9 * lane + j: no conflicts.
 constexpr int BLK_CHUNK = 8;                  // words per staged chunk
+constexpr int BLK_BATCH = 8;                  // staged rows whose loads are in flight per lane
 constexpr int BLK_SROW = BLK_CHUNK + 1;       // padded staged row
 
 // Exchange rows padded to 36 words: read and written 4 words (16 bytes) at a
@@ -260,24 +261,37 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                 (uint32_t)(words - 1 - (w0 + BLK_CHUNK * c + w)) * 32u + (uint32_t)(1 - hf) * 16u;
             int g = gbase + q;
             g = g >= N ? g - N : g;
-#pragma unroll 16
-            for (int it = 0; it < 32; ++it) {
-                const int r = 4 * it + q;
-                const bool mir = edge && (ubase + r < 0 || ubase + r >= N);
-                // Unconditional loads (g is always a lattice row), so that
-                // the unrolled loads are all in flight before the first use.
-                uint32_t x = bytes16_to_halves(__builtin_amdgcn_raw_buffer_load_b128(
-                    src, (uint32_t)g * row_bytes + (KLEIN && mir ? co_m : co), 0, 0));
-                if (KLEIN && mir) {                  // both halves' cells reversed
-                    x = __builtin_bitreverse32(x);
-                    x = __builtin_amdgcn_alignbit(x, x, 16);
+            // Batches of BLK_BATCH loads, all issued before the first is
+            // used: a batch's registers fit beside the state of the chunks
+            // already held (without explicit batches the compiler waited for
+            // each load of the last chunks before issuing the next).
+#pragma unroll 1
+            for (int it0 = 0; it0 < 32; it0 += BLK_BATCH) {
+                u32x4 v[BLK_BATCH];
+#pragma unroll
+                for (int k = 0; k < BLK_BATCH; ++k) {
+                    const int r = 4 * (it0 + k) + q;
+                    const bool mir = edge && (ubase + r < 0 || ubase + r >= N);
+                    // Unconditional loads: g is always a lattice row.
+                    v[k] = __builtin_amdgcn_raw_buffer_load_b128(
+                        src, (uint32_t)g * row_bytes + (KLEIN && mir ? co_m : co), 0, 0);
+                    g += 4;
+                    g = g >= N ? g - N : g;
                 }
-                x = r < wrows ? x : 0u;
-                const int si = 2 * stage_index(r, w) + hf;
-                sL[si] = (uint16_t)x;
-                sT[si] = (uint16_t)(x >> 16);
-                g += 4;
-                g = g >= N ? g - N : g;
+#pragma unroll
+                for (int k = 0; k < BLK_BATCH; ++k) {
+                    const int r = 4 * (it0 + k) + q;
+                    const bool mir = edge && (ubase + r < 0 || ubase + r >= N);
+                    uint32_t x = bytes16_to_halves(v[k]);
+                    if (KLEIN && mir) {              // both halves' cells reversed
+                        x = __builtin_bitreverse32(x);
+                        x = __builtin_amdgcn_alignbit(x, x, 16);
+                    }
+                    x = r < wrows ? x : 0u;
+                    const int si = 2 * stage_index(r, w) + hf;
+                    sL[si] = (uint16_t)x;
+                    sT[si] = (uint16_t)(x >> 16);
+                }
             }
         } else {
             const int q = lane >> 3, w = lane & 7;
@@ -285,21 +299,30 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
             const uint32_t co_m = (uint32_t)(words - 1 - (w0 + BLK_CHUNK * c + w)) * 4u;
             int g = gbase + q;
             g = g >= N ? g - N : g;
-#pragma unroll 4
-            for (int it = 0; it < 16; ++it) {
-                const int r = 8 * it + q;
-                const bool mir = edge && (ubase + r < 0 || ubase + r >= N);
-                const uint32_t o = (uint32_t)g * row_bytes + (KLEIN && mir ? co_m : co);
-                uint32_t l = __builtin_amdgcn_raw_buffer_load_b32(src, o, 0, 0);
-                uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(src, o + plane_bytes, 0, 0);
-                if (KLEIN && mir) {
-                    l = __builtin_bitreverse32(l);
-                    t = __builtin_bitreverse32(t);
+#pragma unroll 1
+            for (int it0 = 0; it0 < 16; it0 += BLK_BATCH) {
+                uint32_t l[BLK_BATCH], t[BLK_BATCH];
+#pragma unroll
+                for (int k = 0; k < BLK_BATCH; ++k) {
+                    const int r = 8 * (it0 + k) + q;
+                    const bool mir = edge && (ubase + r < 0 || ubase + r >= N);
+                    const uint32_t o = (uint32_t)g * row_bytes + (KLEIN && mir ? co_m : co);
+                    l[k] = __builtin_amdgcn_raw_buffer_load_b32(src, o, 0, 0);
+                    t[k] = __builtin_amdgcn_raw_buffer_load_b32(src, o + plane_bytes, 0, 0);
+                    g += 8;
+                    g = g >= N ? g - N : g;
                 }
-                stL[stage_index(r, w)] = r < wrows ? l : 0u;
-                stT[stage_index(r, w)] = r < wrows ? t : 0u;
-                g += 8;
-                g = g >= N ? g - N : g;
+#pragma unroll
+                for (int k = 0; k < BLK_BATCH; ++k) {
+                    const int r = 8 * (it0 + k) + q;
+                    const bool mir = edge && (ubase + r < 0 || ubase + r >= N);
+                    if (KLEIN && mir) {
+                        l[k] = __builtin_bitreverse32(l[k]);
+                        t[k] = __builtin_bitreverse32(t[k]);
+                    }
+                    stL[stage_index(r, w)] = r < wrows ? l[k] : 0u;
+                    stT[stage_index(r, w)] = r < wrows ? t[k] : 0u;
+                }
             }
         }
     };
@@ -313,36 +336,50 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
             const uint32_t co = (uint32_t)(w0 + BLK_CHUNK * c + w) * 32u + (uint32_t)hf * 16u;
             int g = gbase + q;
             g = g >= N ? g - N : g;
-#pragma unroll 8
-            for (int it = 0; it < 32; ++it) {
-                const int r = 4 * it + q;
-                const int hr = wrow0 + r;
-                if (hr >= H && hr < H + R) {
-                    const int si = 2 * stage_index(r, w) + hf;
-                    const uint32_t x = (uint32_t)sL[si] | ((uint32_t)sT[si] << 16);
-                    __builtin_amdgcn_raw_buffer_store_b128(halves_to_bytes16(x), dst,
-                                                           (uint32_t)g * row_bytes + co, 0, 0);
+            // Batches: the staged halves of BLK_BATCH rows are read before
+            // the first is converted, so that one LDS latency covers them.
+#pragma unroll 1
+            for (int it0 = 0; it0 < 32; it0 += BLK_BATCH) {
+                uint32_t x[BLK_BATCH];
+#pragma unroll
+                for (int k = 0; k < BLK_BATCH; ++k) {
+                    const int si = 2 * stage_index(4 * (it0 + k) + q, w) + hf;
+                    x[k] = (uint32_t)sL[si] | ((uint32_t)sT[si] << 16);
                 }
-                g += 4;
-                g = g >= N ? g - N : g;
+#pragma unroll
+                for (int k = 0; k < BLK_BATCH; ++k) {
+                    const int hr = wrow0 + 4 * (it0 + k) + q;
+                    if (hr >= H && hr < H + R)
+                        __builtin_amdgcn_raw_buffer_store_b128(halves_to_bytes16(x[k]), dst,
+                                                               (uint32_t)g * row_bytes + co, 0, 0);
+                    g += 4;
+                    g = g >= N ? g - N : g;
+                }
             }
         } else {
             const int q = lane >> 3, w = lane & 7;
             const uint32_t co = (uint32_t)(w0 + BLK_CHUNK * c + w) * 4u;
             int g = gbase + q;
             g = g >= N ? g - N : g;
-#pragma unroll 4
-            for (int it = 0; it < 16; ++it) {
-                const int r = 8 * it + q;
-                const int hr = wrow0 + r;
-                if (hr >= H && hr < H + R) {
-                    const uint32_t o = (uint32_t)g * row_bytes + co;
-                    __builtin_amdgcn_raw_buffer_store_b32(stL[stage_index(r, w)], dst, o, 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b32(stT[stage_index(r, w)], dst,
-                                                          o + plane_bytes, 0, 0);
+#pragma unroll 1
+            for (int it0 = 0; it0 < 16; it0 += BLK_BATCH) {
+                uint32_t l[BLK_BATCH], t[BLK_BATCH];
+#pragma unroll
+                for (int k = 0; k < BLK_BATCH; ++k) {
+                    l[k] = stL[stage_index(8 * (it0 + k) + q, w)];
+                    t[k] = stT[stage_index(8 * (it0 + k) + q, w)];
                 }
-                g += 8;
-                g = g >= N ? g - N : g;
+#pragma unroll
+                for (int k = 0; k < BLK_BATCH; ++k) {
+                    const int hr = wrow0 + 8 * (it0 + k) + q;
+                    if (hr >= H && hr < H + R) {
+                        const uint32_t o = (uint32_t)g * row_bytes + co;
+                        __builtin_amdgcn_raw_buffer_store_b32(l[k], dst, o, 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(t[k], dst, o + plane_bytes, 0, 0);
+                    }
+                    g += 8;
+                    g = g >= N ? g - N : g;
+                }
             }
         }
     };
