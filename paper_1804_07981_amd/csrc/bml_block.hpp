@@ -630,6 +630,12 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                 for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i < W) {
+                        // The lane below; lane 63 keeps the first row of
+                        // the wave below (or none).  In a short last wave
+                        // the last held row sees an unused lane instead of
+                        // none: that row is a halo row of the open lower
+                        // end, whose error reaches the own rows only after
+                        // more than H >= K steps, so it needs no select.
                         eb[j] = from_below_or(cb[j], e0[j]);
                         // The lane shift runs with every lane on (see
                         // bml_resident.hpp).
@@ -640,7 +646,6 @@ __global__ __launch_bounds__(64 * BLK_WAVES, 3) void block_kernel(BlockArgs a)
                 for (int j = 0; j < VG; ++j) {
                     const int i = g + j;
                     if (i < W) {
-                        eb[j] = lane == last_lane ? cb[j] : eb[j];
                         mv0[j] = T0[i] & e1[j];
                         mv1[j] = T1[i] & eb[j];
                     }
