@@ -114,7 +114,9 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-template <int IO, int W>
+// SLAB: the bin is one slab of a taller lattice (open ends with halo rows)
+// rather than whole lattices (periodic).
+template <int IO, int W, bool SLAB>
 __device__ __forceinline__ void resident_body(const ResidentArgs &a, const ResidentBin &bin,
                                               ResidentShared &sh)
 {
@@ -371,7 +373,14 @@ __device__ __forceinline__ void resident_body(const ResidentArgs &a, const Resid
                 for (int j = 0; j < 4; ++j) {
                     const int i = g + j;
                     if (i < W) {
-                        eb[j] = lane == last_lane ? cb[j] : eb[j];
+                        // The item's last row takes the row below it from
+                        // LDS (a whole lattice's first row) where it does
+                        // not sit in lane 63.  A slab's last held row is a
+                        // halo row of its open lower end, whose error
+                        // reaches the stored rows only after more than
+                        // H >= n_steps steps: it may see the unused lane.
+                        if constexpr (!SLAB)
+                            eb[j] = lane == last_lane ? cb[j] : eb[j];
                         mv0[j] = T0[i] & ~(L1[i] | T1[i]);
                         mv1[j] = T1[i] & eb[j];
                     }
@@ -425,13 +434,17 @@ __device__ __forceinline__ void resident_body(const ResidentArgs &a, const Resid
 
 template <int IO, int W>
 __device__ __forceinline__ void resident_dispatch(const ResidentArgs &a, const ResidentBin &bin,
-                                                  ResidentShared &sh, int words)
+                                                  ResidentShared &sh, int words, bool slab)
 {
     if constexpr (W <= RES_MAX_WORDS) {
-        if (words == W)
-            resident_body<IO, W>(a, bin, sh);
-        else
-            resident_dispatch<IO, W + 1>(a, bin, sh, words);
+        if (words == W) {
+            if (slab)
+                resident_body<IO, W, true>(a, bin, sh);
+            else
+                resident_body<IO, W, false>(a, bin, sh);
+        } else {
+            resident_dispatch<IO, W + 1>(a, bin, sh, words, slab);
+        }
     }
 }
 
@@ -443,7 +456,8 @@ __global__ __launch_bounds__(64 * RES_WAVES, 3) void resident_kernel(ResidentArg
     const ResidentBin &bin = a.bins[blockIdx.x];
     const int words = __builtin_amdgcn_readfirstlane(bin.words);
     if (__builtin_amdgcn_readfirstlane(bin.n_items) > 0)   // padding bins only take a ticket
-        resident_dispatch<IO, 1>(a, bin, sh, words);
+        resident_dispatch<IO, 1>(a, bin, sh, words,
+                                 __builtin_amdgcn_readfirstlane(bin.item[0].halo) > 0);
 
     // The last block to finish advances the device-side step and pass (one
     // pass: every lattice's state moved once between its two buffers).
