@@ -93,9 +93,7 @@ struct bml_batch {
     BatchLattice *d_lat = nullptr;
     BatchItem *d_items = nullptr;
     ResidentBin *d_bins = nullptr;
-    SlabLattice *d_cut = nullptr;           // lattices cut into slabs (res_cut entries)
-    uint32_t *d_partial = nullptr;          // slabs' partial counts (res_parts rows)
-    int32_t res_cut = 0, res_parts = 0, res_halo = 0;
+    int32_t res_cut = 0, res_halo = 0;      // lattices cut into slabs; their halo rows
     BatchCounters *d_ctr = nullptr;
     unsigned long long *d_counts = nullptr;
     uint8_t *d_stage = nullptr;   // bitplane read-back staging, stage_bytes
@@ -130,10 +128,6 @@ static void batch_release(bml_batch *B)
         (void)hipFree(B->d_items);
     if (B->d_bins)
         (void)hipFree(B->d_bins);
-    if (B->d_cut)
-        (void)hipFree(B->d_cut);
-    if (B->d_partial)
-        (void)hipFree(B->d_partial);
     if (B->d_ctr)
         (void)hipFree(B->d_ctr);
     if (B->d_counts)
@@ -237,16 +231,6 @@ static std::vector<ResidentBin> resident_bins(const bml_batch *B, const std::vec
 {
     std::vector<ResidentBin> bins;
     const int K = B->res_halo;
-    // Partial-count rows of the slabs: lattice by lattice, whatever is
-    // active, so that a row's meaning does not change while lattices retire.
-    std::vector<int> part_base(B->count, -1);
-    for (int b = 0, next = 0; b < B->count; ++b) {
-        const int P = lattice_slabs(B, b);
-        if (P > 1) {
-            part_base[b] = next;
-            next += P;
-        }
-    }
     for (int W = 1; W <= RES_MAX_WORDS; ++W) {
         const int n = 32 * W;
         ResidentBin cur{};
@@ -262,7 +246,7 @@ static std::vector<ResidentBin> resident_bins(const bml_batch *B, const std::vec
                     ResidentBin sb{};
                     sb.words = W;
                     sb.n_items = 1;
-                    sb.item[0] = ResidentItem{b, lo, hi - lo, K, part_base[b] + i};
+                    sb.item[0] = ResidentItem{b, lo, hi - lo, K, i};
                     bins.push_back(sb);
                 }
                 continue;
@@ -346,41 +330,18 @@ static int upload_work(bml_batch *B)
             B->res_halo = plan_halo(B);
             const std::vector<uint8_t> all(B->count, 1);
             const int32_t grid = std::max<int32_t>(1, (int32_t)resident_bins(B, all).size());
-            int32_t cut = 0, parts = 0;
-            for (int b = 0; b < B->count; ++b) {
-                const int P = lattice_slabs(B, b);
-                if (P > 1) {
-                    ++cut;
-                    parts += P;
-                }
-            }
-            for (void **p : {(void **)&B->d_bins, (void **)&B->d_cut, (void **)&B->d_partial}) {
-                if (*p)
-                    (void)hipFree(*p);
-                *p = nullptr;
-            }
-            if (hipMalloc(&B->d_bins, (size_t)grid * sizeof(ResidentBin)) != hipSuccess ||
-                (cut && hipMalloc(&B->d_cut, (size_t)cut * sizeof(SlabLattice)) != hipSuccess) ||
-                (parts && hipMalloc(&B->d_partial, (size_t)parts * B->res_halo * 2 *
-                                                       sizeof(uint32_t)) != hipSuccess)) {
+            int32_t cut = 0;
+            for (int b = 0; b < B->count; ++b)
+                cut += lattice_slabs(B, b) > 1;
+            if (B->d_bins)
+                (void)hipFree(B->d_bins);
+            B->d_bins = nullptr;
+            if (hipMalloc(&B->d_bins, (size_t)grid * sizeof(ResidentBin)) != hipSuccess) {
                 B->res_grid = 0;
                 return fail(BML_EDEVICE, "hipMalloc of the resident plan failed");
             }
             B->res_grid = grid;
             B->res_cut = cut;
-            B->res_parts = parts;
-        }
-        if (B->res_cut) {
-            std::vector<SlabLattice> cut;
-            for (int b = 0, next = 0; b < B->count; ++b) {
-                const int P = lattice_slabs(B, b);
-                if (P > 1) {
-                    cut.push_back(SlabLattice{B->active[b] ? b : -1, next, P, 0});
-                    next += P;
-                }
-            }
-            BML_HIP(hipMemcpyAsync(B->d_cut, cut.data(), cut.size() * sizeof(SlabLattice),
-                                   hipMemcpyHostToDevice, B->stream));
         }
         std::vector<ResidentBin> bins = resident_bins(B, B->active);
         if ((int64_t)bins.size() > B->res_grid)
@@ -421,31 +382,6 @@ __global__ void zero_trace_kernel(uint32_t *trace, int32_t count, int64_t trace_
         const int64_t b = i / per, r = i - b * per;
         trace[(b * trace_steps + s0) * 2 + r] = 0;
     }
-}
-
-// Adds up the slabs' partial counts of the last resident launch (n_steps
-// steps, the device step counter already advanced past them) into the trace
-// of each cut lattice.  One thread per (cut lattice, step, count).
-__global__ __launch_bounds__(256) void slab_sum_kernel(const SlabLattice *cut, int32_t n_cut,
-                                                       const uint32_t *partial, int32_t part_steps,
-                                                       uint32_t *trace, int32_t trace_steps,
-                                                       const BatchCounters *ctr, int32_t n_steps)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n_cut * n_steps * 2)
-        return;
-    const int e = (int)(i / (2 * n_steps));
-    const int st = (int)(i / 2 % n_steps), q = (int)(i & 1);
-    const SlabLattice c = cut[e];
-    const uint32_t gs = __hip_atomic_load(&ctr->step, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT) - (uint32_t)n_steps +
-                        (uint32_t)st;
-    if (c.lattice < 0 || gs >= (uint32_t)trace_steps)
-        return;
-    uint32_t sum = 0;
-    for (int p = 0; p < c.count; ++p)
-        sum += partial[((size_t)(c.first + p) * part_steps + st) * 2 + q];
-    trace[((size_t)c.lattice * trace_steps + gs) * 2 + q] = sum;
 }
 
 static int batch_blocks_per_cu(int io, int k, int threads, int *out)
@@ -494,21 +430,11 @@ static int enqueue_run(bml_batch *B, int64_t n_steps, int64_t *passes)
             a.bins = B->d_bins;
             a.ctr = B->d_ctr;
             a.trace = B->trace;
-            a.partial = B->d_partial;
             a.trace_steps = (int32_t)B->trace_steps;
-            a.part_steps = B->res_halo;
             a.n_steps = (int32_t)k;
             hipLaunchKernelGGL(fn, dim3((unsigned)B->res_grid), dim3(64 * RES_WAVES), 0,
                                B->stream, a);
             BML_HIP(hipGetLastError());
-            if (B->res_cut) {
-                const int64_t threads = (int64_t)B->res_cut * k * 2;
-                hipLaunchKernelGGL(slab_sum_kernel, dim3((unsigned)((threads + 255) / 256)),
-                                   dim3(256), 0, B->stream, B->d_cut, B->res_cut, B->d_partial,
-                                   B->res_halo, B->trace, (int32_t)B->trace_steps, B->d_ctr,
-                                   (int32_t)k);
-                BML_HIP(hipGetLastError());
-            }
             s += k;
             ++p;
         }

@@ -59,7 +59,7 @@ struct ResidentItem {
     int32_t r0;                     // first row stored (0 for a whole lattice)
     int32_t rows;                   // rows stored: N for a whole lattice
     int32_t halo;                   // halo rows above and below (0: whole, periodic)
-    int32_t part;                   // slab's partial-count row (-1: whole lattice)
+    int32_t slab;                   // the slab's index in its lattice (-1: whole lattice)
 };
 
 // Items of one row width run by one block.
@@ -74,9 +74,7 @@ struct ResidentArgs {
     const ResidentBin *bins;
     BatchCounters *ctr;
     uint32_t *trace;                // [lattice][trace_steps][2]: LR moved, TB moved
-    uint32_t *partial;              // [slab][part_steps][2]: a slab's moved counts
     int32_t trace_steps;
-    int32_t part_steps;             // steps per partial row (>= n_steps when slabs exist)
     int32_t n_steps;                // steps of this launch (<= every slab's halo)
 };
 
@@ -231,12 +229,12 @@ __device__ __forceinline__ void resident_body(const ResidentArgs &a, const Resid
         (&sh.cnt[0][0][0][0])[i] = 0;
     if (threadIdx.x < RES_MAX_WORDS)
         sh.none[threadIdx.x] = 0;
-    // Writes the gathered counts of steps [c0, c1) (one chunk) and clears
-    // their slots; run by the first wave of each item.  A whole lattice
-    // writes its trace entries; a slab writes its row of partial counts,
-    // which slab_sum_kernel adds up per lattice after the launch (plain
-    // stores: atomics from a whole wave to one cache line serialise).
-    const int part = wave_on ? __builtin_amdgcn_readfirstlane(bin.item[slot].part) : -1;
+    // Writes the gathered counts of steps [c0, c1) (one chunk) to the trace
+    // and clears their slots; run by the first wave of each item.  A whole
+    // lattice stores its trace entries; the slabs of a lattice add theirs
+    // into the lattice's entries, which the run zeroed before its first
+    // launch (at most a few slabs add to one entry, once per chunk).
+    const bool is_slab = wave_on && __builtin_amdgcn_readfirstlane(bin.item[slot].slab) >= 0;
     auto flush = [&](int c0, int c1) {
         const int kb = (c0 / RES_CHUNK) & 1;
         for (int j = lane; j < 2 * (c1 - c0); j += 64) {
@@ -244,12 +242,13 @@ __device__ __forceinline__ void resident_body(const ResidentArgs &a, const Resid
             uint32_t &slotv = sh.cnt[kb][st - c0][slot][q];
             const uint32_t v = slotv;
             slotv = 0;
-            if (part >= 0) {
-                a.partial[((size_t)part * a.part_steps + st) * 2 + q] = v;
-            } else {
-                const uint32_t gs = step0 + (uint32_t)st;
-                if (gs < (uint32_t)a.trace_steps)
-                    a.trace[((size_t)li * a.trace_steps + gs) * 2 + q] = v;
+            const uint32_t gs = step0 + (uint32_t)st;
+            if (gs < (uint32_t)a.trace_steps) {
+                uint32_t *t = &a.trace[((size_t)li * a.trace_steps + gs) * 2 + q];
+                if (is_slab)
+                    __hip_atomic_fetch_add(t, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    *t = v;
             }
         }
     };
@@ -475,12 +474,6 @@ __global__ __launch_bounds__(64 * RES_WAVES, 3) void resident_kernel(ResidentArg
         __hip_atomic_store(&a.ctr->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
-
-// One lattice cut into slabs: its slabs' partial rows are first ..
-// first + count - 1 (lattice -1: not active in this run).
-struct SlabLattice {
-    int32_t lattice, first, count, pad;
-};
 
 using ResidentFn = void (*)(ResidentArgs);
 ResidentFn resident_kernel_u8();
