@@ -374,11 +374,12 @@ __device__ __forceinline__ void resident_body(const ResidentArgs &a, const Resid
                     if (i < W) {
                         // The item's last row takes the row below it from
                         // LDS (a whole lattice's first row) where it does
-                        // not sit in lane 63.  A slab's last held row is a
-                        // halo row of its open lower end, whose error
+                        // not sit in lane 63, i.e. when N is not a multiple
+                        // of the 128 rows of a wave.  A slab's last held row
+                        // is a halo row of its open lower end, whose error
                         // reaches the stored rows only after more than
                         // H >= n_steps steps: it may see the unused lane.
-                        if constexpr (!SLAB)
+                        if constexpr (!SLAB && (32 * W) % RES_WAVE_ROWS != 0)
                             eb[j] = lane == last_lane ? cb[j] : eb[j];
                         mv0[j] = T0[i] & ~(L1[i] | T1[i]);
                         mv1[j] = T1[i] & eb[j];
